@@ -1,0 +1,124 @@
+/*
+ * Reference oracle for TPC sector track finding (test infrastructure only).
+ *
+ * A plain, sequential CPU implementation of the sector tracking method that the paper
+ * (arXiv:2009.07515, Sec. 6 "Track reconstruction with continuous data") runs standalone
+ * on the GPU: per-row search grids, neighbour links between adjacent pad rows, a cellular
+ * automaton that turns reciprocal links into chains, and a 5-parameter Kalman filter that
+ * fits and follows helix candidates in the solenoid field.  The paper only names the
+ * method (derived from the Run 2 HLT tracker); every internal rule implemented here is a
+ * reading of that description and is stated where it is implemented.
+ *
+ * Only the test suite, the smoke check and the CPU baseline of the benchmark use this
+ * code.  It shares no source with the GPU library.
+ *
+ * Precision: the grid and the neighbour links are defined in IEEE binary32 (round to
+ * nearest even, no contraction, correctly rounded division) in every build.  The Kalman
+ * part runs in `orc_real`, which is double in liborc_f64.so and float in liborc_f32.so.
+ * The API always exchanges doubles.
+ */
+#ifndef TPC_ORACLE_H
+#define TPC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t n_sectors;        /* sectors per frame (36)                          */
+    int32_t n_rows;           /* pad rows per sector (152)                       */
+    const float* row_x;       /* [n_rows] row plane positions (cm)               */
+    double bz;                /* solenoid field along z (T)                      */
+    /* neighbour links (binary32 by definition) */
+    float win_y, win_z;       /* rectangular window half-widths (cm)             */
+    float kink_max;           /* largest accepted slope change D                 */
+    /* Kalman filter and follow */
+    double sigma_y, sigma_z;  /* cluster errors (cm)                             */
+    double chi2_max;          /* largest accepted 2D chi2 of a followed cluster  */
+    double sinphi_max;        /* propagation stops at |sin(phi)| >= this         */
+    double nsig;              /* follow window in units of the predicted error   */
+    double c0[5];             /* initial covariance diagonal                     */
+    int32_t min_chain;        /* shortest chain that becomes a tracklet          */
+    int32_t min_track_hits;   /* fewest kept clusters of an accepted track       */
+    int32_t max_miss;         /* follow stops after more consecutive misses      */
+    /* grid (tuning: changes the grid tables only, never links or tracks) */
+    float bin_y, bin_z;
+    int32_t cap_mul, cap_add; /* a row of n clusters has at most cap_mul*n+cap_add bins */
+} orc_cfg;
+
+typedef struct {
+    int64_t cap_tracks, cap_hits;
+    int64_t n_tracks, n_hits;  /* written: the sizes the frame needs             */
+    double* params;            /* [cap_tracks][5] (y, z, sin phi, tan lambda, q/pT) */
+    double* cov;               /* [cap_tracks][15] lower triangle, row-major     */
+    double* x_ref;             /* [cap_tracks] x of the innermost cluster        */
+    double* chi2;              /* [cap_tracks]                                   */
+    int32_t* ndf;              /* [cap_tracks] 2*nhits - 5                       */
+    int32_t* nhits;            /* [cap_tracks]                                   */
+    int32_t* sector;           /* [cap_tracks]                                   */
+    int64_t* hit_off;          /* [cap_tracks+1]                                 */
+    int64_t* hit_ids;          /* [cap_hits] frame cluster index, inner to outer */
+    int32_t* cluster_track;    /* [N] track index or -1                          */
+} orc_tracks;
+
+typedef struct {               /* optional intermediate results; NULL = skip     */
+    /* grid, per frame row g = sector * n_rows + row */
+    float* g_ylo; float* g_zlo; float* g_by; float* g_bz;
+    int32_t* g_ny; int32_t* g_nz;
+    int64_t* g_bin_base;       /* offset of row g's table inside bin_start       */
+    uint32_t* bin_start;       /* concatenated, ny*nz+1 entries per row          */
+    int64_t bin_start_cap;
+    uint32_t* perm;            /* [N] in-row index of the k-th sorted cluster    */
+    int32_t* up; int32_t* dn;  /* [N] raw links (in-row index, -1 none)          */
+    int32_t* cup; int32_t* cdn;/* [N] cleaned links                              */
+    uint8_t* start;            /* [N] start-hit flags                            */
+    /* tracklets, one per start hit in frame cluster order */
+    int64_t cap_tracklets;
+    int64_t n_tracklets;       /* written                                        */
+    int64_t* tl_start;         /* [cap] frame index of the start hit             */
+    int32_t* tl_nhits;         /* [cap] 0 = no tracklet                          */
+    int32_t* tl_hits;          /* [cap][n_rows] in-row index per row, -1 none    */
+    uint64_t* W;               /* [N] selection weight per cluster               */
+} orc_debug;
+
+/* Track one frame.  y, z: [n] binary32 local coordinates grouped by (sector, row);
+ * row_off: [n_sectors*n_rows+1].  shuffle_seed != 0 visits tracklets in a pseudo-random
+ * order during selection (the result must not change).  Returns 0, or -1 on invalid
+ * input, -3 if an output or debug capacity is too small (sizes are still written). */
+int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
+                    const int64_t* row_off, orc_tracks* out, orc_debug* dbg,
+                    uint64_t shuffle_seed);
+
+/* Grid of one row (binary32).  bin_start has room for cap entries.  Returns 0 or -3. */
+int orc_grid_row(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
+                 float* ylo, float* zlo, float* by, float* bz, int32_t* ny, int32_t* nz,
+                 uint32_t* bin_start, int64_t cap, uint32_t* perm);
+
+/* Raw neighbour links of one sector.  row_off: [n_rows+1] absolute offsets into y, z;
+ * up/dn are indexed from row_off[0].  brute != 0 uses the all-pairs definition, else a
+ * y-sorted window scan (same result). */
+int orc_links_sector(const orc_cfg* cfg, const float* y, const float* z,
+                     const int64_t* row_off, int brute, int32_t* up, int32_t* dn);
+
+/* Helix propagation of (p, C) from x0 to x1; J receives the 5x5 Jacobian (row-major)
+ * if not NULL.  Returns 0, or -1 if |sin phi| would reach sinphi_max. */
+int orc_propagate(const orc_cfg* cfg, double x0, double x1, double* p, double* C, double* J);
+
+/* Three-point seed from clusters (x_i, y_i, z_i), i = 0, 1, 2, ordered by x. */
+int orc_seed(const orc_cfg* cfg, const double* x, const double* y, const double* z, double* p);
+
+/* Kalman update with measurement (my, mz); returns the chi2 increment. */
+double orc_update(const orc_cfg* cfg, double my, double mz, double* p, double* C);
+
+/* Final fit of an ordered cluster list (inner to outer): seed, outward pass from C0,
+ * inward pass from C0 keeping the parameters.  p, C at x[0]; p_outer receives the
+ * outward-pass state at x[n-1] if not NULL.  Returns 0 or -1 (propagation failure). */
+int orc_fit_hits(const orc_cfg* cfg, int32_t n, const double* x, const double* y,
+                 const double* z, double* p, double* C, double* chi2, double* p_outer);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
