@@ -1,0 +1,181 @@
+/*
+ * tpcsf — TPC sector track finding on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the standalone TPC track finding of arXiv:2009.07515, Sec. 6: in each
+ * of the 36 sectors, clusters on the 152 pad rows are sorted into per-row search grids,
+ * linked to their best neighbours in the adjacent rows, chained by a cellular automaton,
+ * and fitted and followed as helices with a 5-parameter Kalman filter in the solenoid
+ * field.  A whole continuous-readout time frame (or a batch of them) is processed at once
+ * (Sec. 7.1).  The paper names the method (derived from the Run 2 HLT tracker) but prints
+ * none of its rules; the rules this library implements are stated at the parameter
+ * structures below and in the kernels.
+ *
+ * Conventions shared by every call:
+ *   - Device pointers (marked [device]) must point to memory of the device that was
+ *     current when the context was created; host pointers are marked [host].
+ *   - Clusters are structure-of-arrays float32 in local sector coordinates (cm), grouped by
+ *     (time frame, sector, pad row): the clusters of global row
+ *     g = (tf * n_sectors + sector) * n_rows + row are [row_offsets[g], row_offsets[g+1]).
+ *     z is the drift coordinate, which in continuous readout carries the unknown
+ *     collision-time offset (Sec. 2); no z range is assumed.
+ *   - A track state is p = (y, z, sin(phi), tan(lambda), q/pT [c/GeV]) at the row plane
+ *     x = x_ref; the curvature is kappa = -0.00299792458 * bz * q/pT [1/cm].  Covariances
+ *     are the 15-element lower triangle, row-major: C00, C10, C11, C20, C21, C22, ...
+ *   - Calls are stream-ordered and asynchronous.  The returned status covers argument
+ *     validation and launch errors; errors found on the device (non-finite or out-of-range
+ *     coordinates, output capacity) are reported by tpcsf_sync().
+ *   - The caller owns every input and output buffer; the library owns only its scratch
+ *     arena (limited by the HBM budget given at creation).
+ *   - No function falls back to the CPU.
+ */
+#ifndef TPCSF_H
+#define TPCSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TPCSF_OK = 0,
+    TPCSF_E_INVALID = -1,   /* bad argument or malformed input                          */
+    TPCSF_E_NOMEM = -2,     /* scratch would exceed the HBM budget, or hipMalloc failed  */
+    TPCSF_E_CAPACITY = -3,  /* an output buffer is too small; required sizes are written */
+    TPCSF_E_HIP = -4,       /* HIP runtime error                                         */
+    TPCSF_E_BUSY = -5,      /* server: no free slot or budget right now                  */
+    TPCSF_E_TIMEOUT = -6    /* server: wait timed out                                    */
+} tpcsf_status;
+
+typedef struct tpcsf_ctx tpcsf_ctx;
+
+/* Detector geometry (inputs).  Sector s < n_sectors/2 is the A side.  Row r is the plane
+ * x = row_x[r] of the sector frame; rows must be strictly increasing in x. */
+typedef struct {
+    int32_t n_sectors;        /* sectors per time frame (36)                      */
+    int32_t n_rows;           /* pad rows per sector (152); 3 <= n_rows <= 256     */
+    const float* row_x;       /* [host] [n_rows] row plane positions (cm)           */
+    double bz;                /* solenoid field along z (T)                         */
+} tpcsf_geometry;
+
+/* Method constants: they define the result.
+ *   Neighbour links (binary32): a cluster c of row r+-1 is a candidate for cluster h of row
+ *   r when |y_c - y_h| <= win_y and |z_c - z_h| <= win_z; the pair (u in r+1, d in r-1)
+ *   with the least slope change D = (ty_u - ty_d)^2 + (tz_u - tz_d)^2 wins if
+ *   D <= kink_max (ties: smaller in-row index of u, then of d).  Links that are not
+ *   reciprocal are dropped; chains of >= min_chain clusters seed tracklets.
+ *   Kalman filter (binary64): cluster errors sigma_y/z, initial covariance diagonal c0,
+ *   propagation fails at |sin(phi)| >= sinphi_max; the follow step takes the least-chi2
+ *   cluster inside min(win, nsig * predicted error) if chi2 <= chi2_max and stops after
+ *   more than max_miss consecutive empty rows.  Tracks keep >= min_track_hits clusters. */
+typedef struct {
+    float win_y, win_z, kink_max;
+    double sigma_y, sigma_z, chi2_max, sinphi_max, nsig;
+    double c0[5];
+    int32_t min_chain, min_track_hits, max_miss;
+} tpcsf_params;
+
+/* Tuning: changes speed and the grid tables, never links or tracks.
+ *   bin_y, bin_z: grid bin size (cm); a row of n clusters gets at most cap_mul*n+cap_add
+ *   bins (the z bin, then the y bin, doubles until it fits).
+ *   block: threads per block of the row kernels (64..1024, multiple of 64).
+ *   tl_block: threads per block of the tracklet kernel (64..1024, multiple of 64).
+ *   chunk: starts a wave takes from the work queue at a time (>= 1). */
+typedef struct {
+    float bin_y, bin_z;
+    int32_t cap_mul, cap_add;
+    int32_t block, tl_block, chunk;
+} tpcsf_tuning;
+
+/* One batch of n_tf time frames in device memory. */
+typedef struct {
+    int32_t n_tf;                       /* time frames in the batch (>= 1)                */
+    int64_t n_clusters;                 /* total clusters (< 2^31)                       */
+    const float* y;                     /* [device] [n_clusters]                          */
+    const float* z;                     /* [device] [n_clusters]                          */
+    const int64_t* row_offsets;         /* [device] [n_tf*n_sectors*n_rows+1], [0] = 0    */
+    const int64_t* row_offsets_host;    /* [host] same values, used for validation and
+                                           planning; no row may hold 65535 clusters or more */
+} tpcsf_frame;
+
+/* Output buffers (caller-allocated device memory).  Tracks are ordered by (time frame,
+ * sector, rank of the chain's bottom cluster in frame order); each track's clusters are
+ * listed from the innermost row outward.  If the batch needs more than cap_tracks tracks
+ * or cap_hits clusters, only what fits is written, *n_tracks / *n_hits hold the required
+ * sizes and tpcsf_sync() returns TPCSF_E_CAPACITY. */
+typedef struct {
+    int64_t cap_tracks, cap_hits;
+    int64_t* n_tracks;                  /* [device] scalar                                 */
+    int64_t* n_hits;                    /* [device] scalar                                 */
+    double* params;                     /* [device] [cap_tracks][5] at x_ref               */
+    double* cov;                        /* [device] [cap_tracks][15]                       */
+    double* x_ref;                      /* [device] [cap_tracks] innermost cluster's row x */
+    double* chi2;                       /* [device] [cap_tracks]                           */
+    int32_t* ndf;                       /* [device] [cap_tracks] 2*nhits - 5               */
+    int32_t* nhits;                     /* [device] [cap_tracks]                           */
+    int32_t* sector;                    /* [device] [cap_tracks]                           */
+    int32_t* tf;                        /* [device] [cap_tracks] time frame in the batch   */
+    int64_t* hit_off;                   /* [device] [cap_tracks+1]                         */
+    int32_t* hit_ids;                   /* [device] [cap_hits] batch cluster index         */
+    int32_t* cluster_track;             /* [device] [n_clusters] track index or -1         */
+} tpcsf_tracks;
+
+/* Defaults of the method constants and of the tuning. */
+void tpcsf_default_params(tpcsf_params* p);
+void tpcsf_default_tuning(tpcsf_tuning* t);
+
+/* Create a context on the current device.  hbm_budget_bytes bounds the scratch arena
+ * (0 = no bound).  The geometry's row_x is copied. */
+tpcsf_status tpcsf_create(const tpcsf_geometry* geo, const tpcsf_params* params,
+                          const tpcsf_tuning* tuning, size_t hbm_budget_bytes, tpcsf_ctx** out);
+tpcsf_status tpcsf_destroy(tpcsf_ctx* ctx);
+
+/* Change the tuning of an existing context (result-invariant). */
+tpcsf_status tpcsf_set_tuning(tpcsf_ctx* ctx, const tpcsf_tuning* tuning);
+
+/* Scratch bytes a batch of n_clusters clusters in n_tf time frames needs. */
+size_t tpcsf_arena_bytes(const tpcsf_ctx* ctx, int64_t n_clusters, int32_t n_tf);
+
+/* Plain form: every stage launched separately for every (time frame, sector). */
+tpcsf_status tpcsf_track_plain(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_tracks* out,
+                               void* stream);
+
+/* Batched form: each stage is one launch over all (time frame, sector) of the batch, the
+ * variable-length tracklet work runs from a persistent work queue, and the sequence is
+ * captured once in a HIP graph and replayed while the batch shape and pointers repeat. */
+tpcsf_status tpcsf_track_batch(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_tracks* out,
+                               void* stream);
+
+/* Wait for the stream and report errors the device found since the last sync:
+ * TPCSF_E_INVALID (non-finite or |coordinate| > 1e5 cm), TPCSF_E_CAPACITY, or TPCSF_OK. */
+tpcsf_status tpcsf_sync(tpcsf_ctx* ctx, void* stream);
+
+/* Intermediate results of the last call, for verification (device pointers into the
+ * arena, valid until the next call on the context).  Layout:
+ *   row_lo[2*g], row_lo[2*g+1]   y_lo, z_lo of global row g        (float)
+ *   row_bin[2*g], row_bin[2*g+1] bin sizes b_y, b_z actually used     (float)
+ *   row_nb[2*g], row_nb[2*g+1]   ny, nz                               (int32)
+ *   bin_start + bin_base(g)      ny*nz+1 entries, bin_base(g) = cap_mul*row_offsets[g] +
+ *                                (cap_add+1)*g                        (uint32)
+ *   perm[row_offsets[g] + k]     in-row index of the k-th sorted cluster  (uint32)
+ *   up, dn, cup, cdn             raw and cleaned links, in-row index or -1 (int32)
+ *   n_starts                     number of chain bottoms (device scalar, int64)
+ *   start_row, start_idx         global row and in-row index of each start, rank order
+ *   tl_nhits                     clusters of the tracklet of each start (0 = none) (int32) */
+typedef struct {
+    const float* row_lo; const float* row_bin; const int32_t* row_nb;
+    const uint32_t* bin_start; const uint32_t* perm;
+    const int32_t* up; const int32_t* dn; const int32_t* cup; const int32_t* cdn;
+    const int64_t* n_starts; const int32_t* start_row; const int32_t* start_idx;
+    const int32_t* tl_nhits;
+} tpcsf_debug_view;
+tpcsf_status tpcsf_debug(const tpcsf_ctx* ctx, tpcsf_debug_view* view);
+
+/* Message of the last error on this context (static storage of the context). */
+const char* tpcsf_last_error(const tpcsf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,503 @@
+// Host runtime of libtpcsf: context, scratch arena under an HBM budget, input validation,
+// the plain (per time frame and sector) and batched (whole batch per launch, HIP graph)
+// execution plans, and the C ABI of include/tpcsf.h.
+#include "tpcsf.h"
+#include "tpcsf_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace tpcsf;
+
+namespace {
+
+constexpr double kCB = 0.00299792458;   // cm^-1 T^-1 GeV
+
+struct Layout {
+    size_t total = 0;
+    int64_t n = 0, R = 0, cap_starts = 0, cap_tl = 0, n_bins = 0;
+    size_t row_lo, row_bin, row_nb, row_nstart, row_sbase;
+    size_t bin_start, bin_fill, ys, zs, perm, up, dn, cup, cdn, W;
+    size_t start_row, start_idx, tl_n, tl_slot, trk_flag, hit_cnt, trk_idx, hit_pos;
+    size_t tl_hits, f_par, f_cov, f_chi2, f_xref, f_mask, scan_part;
+};
+
+struct GraphKey {
+    const void* y = nullptr; const void* z = nullptr; const void* off = nullptr;
+    int64_t n = -1; int64_t R = -1;
+    const void* arena = nullptr;
+    tpcsf_tracks out{};
+    tpcsf_tuning tuning{};
+    bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+
+}  // namespace
+
+struct tpcsf_ctx {
+    int device = 0;
+    int n_cu = 256;
+    int32_t n_sectors = 36, n_rows = 152;
+    std::vector<float> row_x;
+    double bz = 0.5;
+    tpcsf_params params{};
+    tpcsf_tuning tuning{};
+    size_t budget = 0;
+    float* d_rx = nullptr;
+    Counters* d_ctr = nullptr;
+    void* arena = nullptr;
+    size_t arena_size = 0;
+    Layout lay{};
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey{};
+    Batch last{};
+    bool have_last = false;
+    std::string err;
+};
+
+namespace {
+
+tpcsf_status fail(tpcsf_ctx* c, tpcsf_status st, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+tpcsf_status hip_fail(tpcsf_ctx* c, hipError_t e, const char* what)
+{
+    return fail(c, TPCSF_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
+{
+    Layout L;
+    L.n = n;
+    L.R = (int64_t)n_tf * c->n_sectors * c->n_rows;
+    L.n_bins = (int64_t)c->tuning.cap_mul * n + (int64_t)(c->tuning.cap_add + 1) * L.R;
+    L.cap_starts = n / 2 + 1;
+    const int mc = c->params.min_chain > 2 ? c->params.min_chain : 2;
+    L.cap_tl = n / mc + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    const size_t N = (size_t)n, R = (size_t)L.R, S = (size_t)L.cap_starts, T = (size_t)L.cap_tl;
+    L.row_lo = take(R * 8);
+    L.row_bin = take(R * 8);
+    L.row_nb = take(R * 8);
+    L.row_nstart = take(R * 8);
+    L.row_sbase = take(R * 8);
+    L.bin_start = take((size_t)L.n_bins * 4);
+    L.bin_fill = take((size_t)L.n_bins * 4);
+    L.ys = take(N * 4);
+    L.zs = take(N * 4);
+    L.perm = take(N * 4);
+    L.up = take(N * 4);
+    L.dn = take(N * 4);
+    L.cup = take(N * 4);
+    L.cdn = take(N * 4);
+    L.W = take(N * 8);
+    L.start_row = take(S * 4);
+    L.start_idx = take(S * 4);
+    L.tl_n = take(S * 4);
+    L.tl_slot = take(S * 4);
+    L.trk_flag = take(S * 4);
+    L.hit_cnt = take(S * 4);
+    L.trk_idx = take(S * 8);
+    L.hit_pos = take(S * 8);
+    L.tl_hits = take(T * (size_t)c->n_rows * 2);
+    L.f_par = take(T * 5 * 8);
+    L.f_cov = take(T * 15 * 8);
+    L.f_chi2 = take(T * 8);
+    L.f_xref = take(T * 8);
+    L.f_mask = take(T * 4 * 8);
+    L.scan_part = take((4 * kScanBlocks + 2) * 8);
+    L.total = o;
+    return L;
+}
+
+DevParams dev_params(const tpcsf_ctx* c)
+{
+    DevParams P;
+    const tpcsf_params& p = c->params;
+    P.win_y = p.win_y; P.win_z = p.win_z; P.kink_max = p.kink_max;
+    P.bin_y = c->tuning.bin_y; P.bin_z = c->tuning.bin_z;
+    P.cap_mul = c->tuning.cap_mul; P.cap_add = c->tuning.cap_add;
+    P.sy2 = p.sigma_y * p.sigma_y; P.sz2 = p.sigma_z * p.sigma_z;
+    P.chi2_max = p.chi2_max; P.sinphi_max = p.sinphi_max; P.nsig = p.nsig;
+    for (int i = 0; i < 5; ++i) P.c0[i] = p.c0[i];
+    P.a = -kCB * c->bz;
+    P.min_chain = p.min_chain; P.min_track_hits = p.min_track_hits; P.max_miss = p.max_miss;
+    P.n_rows = c->n_rows; P.n_sectors = c->n_sectors;
+    P.rx = c->d_rx;
+    return P;
+}
+
+LaunchCfg launch_cfg(const tpcsf_ctx* c)
+{
+    LaunchCfg L;
+    L.block = c->tuning.block;
+    L.tl_block = c->tuning.tl_block;
+    L.chunk = c->tuning.chunk;
+    L.n_cu = c->n_cu;
+    return L;
+}
+
+bool tuning_ok(const tpcsf_tuning* t)
+{
+    return t && t->bin_y >= 1e-3f && t->bin_z >= 1e-3f && t->bin_y <= 1e5f && t->bin_z <= 1e5f &&
+           t->cap_mul >= 1 && t->cap_mul <= 64 && t->cap_add >= 1 && t->cap_add <= 4096 &&
+           t->block >= 64 && t->block <= 1024 && t->block % 64 == 0 && t->tl_block >= 64 &&
+           t->tl_block <= 1024 && t->tl_block % 64 == 0 && t->chunk >= 1 && t->chunk <= 64;
+}
+
+bool params_ok(const tpcsf_params* p)
+{
+    if (!p) return false;
+    if (!(p->win_y > 0 && p->win_z > 0 && p->kink_max >= 0)) return false;
+    if (!(p->sigma_y > 0 && p->sigma_z > 0 && p->chi2_max > 0 && p->nsig > 0)) return false;
+    if (!(p->sinphi_max > 0 && p->sinphi_max < 1)) return false;
+    for (int i = 0; i < 5; ++i)
+        if (!(p->c0[i] > 0)) return false;
+    return p->min_chain >= 3 && p->min_track_hits >= 3 && p->max_miss >= 0;
+}
+
+// Validate a frame against the context and its outputs (host-side offsets).
+tpcsf_status check_frame(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks* o)
+{
+    if (!f || !o) return fail(c, TPCSF_E_INVALID, "null frame or output");
+    if (f->n_tf < 1) return fail(c, TPCSF_E_INVALID, "n_tf < 1");
+    if (f->n_clusters < 0 || f->n_clusters >= ((int64_t)1 << 31) - 1)
+        return fail(c, TPCSF_E_INVALID, "n_clusters out of range [0, 2^31-1)");
+    if (!f->row_offsets || !f->row_offsets_host) return fail(c, TPCSF_E_INVALID, "row offsets missing");
+    if (f->n_clusters > 0 && (!f->y || !f->z)) return fail(c, TPCSF_E_INVALID, "cluster arrays missing");
+    const int64_t R = (int64_t)f->n_tf * c->n_sectors * c->n_rows;
+    const int64_t* off = f->row_offsets_host;
+    if (off[0] != 0 || off[R] != f->n_clusters) return fail(c, TPCSF_E_INVALID, "row offsets do not span the clusters");
+    for (int64_t g = 0; g < R; ++g) {
+        const int64_t d = off[g + 1] - off[g];
+        if (d < 0) return fail(c, TPCSF_E_INVALID, "row offsets decrease");
+        if (d >= 65535) return fail(c, TPCSF_E_INVALID, "a row holds 65535 clusters or more");
+    }
+    if (o->cap_tracks < 0 || o->cap_hits < 0 || !o->n_tracks || !o->n_hits || !o->hit_off)
+        return fail(c, TPCSF_E_INVALID, "output descriptor incomplete");
+    if (o->cap_tracks > 0 && (!o->params || !o->cov || !o->x_ref || !o->chi2 || !o->ndf || !o->nhits ||
+                              !o->sector || !o->tf))
+        return fail(c, TPCSF_E_INVALID, "track output arrays missing");
+    if (o->cap_hits > 0 && !o->hit_ids) return fail(c, TPCSF_E_INVALID, "hit output array missing");
+    if (f->n_clusters > 0 && !o->cluster_track) return fail(c, TPCSF_E_INVALID, "cluster_track missing");
+    return TPCSF_OK;
+}
+
+tpcsf_status ensure_arena(tpcsf_ctx* c, const Layout& L)
+{
+    if (c->budget && L.total > c->budget)
+        return fail(c, TPCSF_E_NOMEM, "scratch of " + std::to_string(L.total) + " bytes exceeds the HBM budget");
+    if (c->arena && c->arena_size >= L.total) return TPCSF_OK;
+    hipError_t e;
+    if (c->arena) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+        if ((e = hipFree(c->arena)) != hipSuccess) return hip_fail(c, e, "hipFree");
+        c->arena = nullptr;
+        c->arena_size = 0;
+    }
+    const size_t want = L.total + L.total / 8;
+    const size_t sz = (c->budget && want > c->budget) ? L.total : want;
+    if ((e = hipMalloc(&c->arena, sz)) != hipSuccess) {
+        c->arena = nullptr;
+        return fail(c, TPCSF_E_NOMEM, std::string("hipMalloc of the arena: ") + hipGetErrorString(e));
+    }
+    c->arena_size = sz;
+    return TPCSF_OK;
+}
+
+Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcsf_tracks* o)
+{
+    char* a = (char*)c->arena;
+    Batch B;
+    B.y = f->y; B.z = f->z; B.off = f->row_offsets; B.n = f->n_clusters;
+    B.n_rows_total = (int32_t)L.R;
+    B.row_lo = (float2*)(a + L.row_lo);
+    B.row_bin = (float2*)(a + L.row_bin);
+    B.row_nb = (int2*)(a + L.row_nb);
+    B.bin_start = (uint32_t*)(a + L.bin_start);
+    B.bin_fill = (uint32_t*)(a + L.bin_fill);
+    B.ys = (float*)(a + L.ys);
+    B.zs = (float*)(a + L.zs);
+    B.perm = (uint32_t*)(a + L.perm);
+    B.up = (int32_t*)(a + L.up); B.dn = (int32_t*)(a + L.dn);
+    B.cup = (int32_t*)(a + L.cup); B.cdn = (int32_t*)(a + L.cdn);
+    B.row_nstart = (int64_t*)(a + L.row_nstart);
+    B.row_sbase = (int64_t*)(a + L.row_sbase);
+    B.start_row = (int32_t*)(a + L.start_row);
+    B.start_idx = (int32_t*)(a + L.start_idx);
+    B.tl_n = (int32_t*)(a + L.tl_n);
+    B.tl_slot = (int32_t*)(a + L.tl_slot);
+    B.trk_flag = (int32_t*)(a + L.trk_flag);
+    B.hit_cnt = (int32_t*)(a + L.hit_cnt);
+    B.trk_idx = (int64_t*)(a + L.trk_idx);
+    B.hit_pos = (int64_t*)(a + L.hit_pos);
+    B.cap_starts = L.cap_starts;
+    B.tl_hits = (uint16_t*)(a + L.tl_hits);
+    B.f_par = (double*)(a + L.f_par);
+    B.f_cov = (double*)(a + L.f_cov);
+    B.f_chi2 = (double*)(a + L.f_chi2);
+    B.f_xref = (double*)(a + L.f_xref);
+    B.f_mask = (uint64_t*)(a + L.f_mask);
+    B.cap_tl = (int32_t)L.cap_tl;
+    B.W = (unsigned long long*)(a + L.W);
+    B.scan_part = (int64_t*)(a + L.scan_part);
+    B.ctr = c->d_ctr;
+    B.cap_tracks = o->cap_tracks; B.cap_hits = o->cap_hits;
+    B.o_ntracks = o->n_tracks; B.o_nhits = o->n_hits;
+    B.o_par = o->params; B.o_cov = o->cov; B.o_xref = o->x_ref; B.o_chi2 = o->chi2;
+    B.o_ndf = o->ndf; B.o_nhits_trk = o->nhits; B.o_sector = o->sector; B.o_tf = o->tf;
+    B.o_hit_off = o->hit_off; B.o_hit_ids = o->hit_ids; B.o_cluster_track = o->cluster_track;
+    return B;
+}
+
+// The whole batch, one launch per stage.
+void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s)
+{
+    const DevParams P = dev_params(c);
+    const LaunchCfg LC = launch_cfg(c);
+    const int64_t R = B.n_rows_total;
+    launch_reset(B, s);
+    launch_grid(B, P, 0, R, LC, s);
+    launch_links(B, P, 0, R, LC, s);
+    launch_clean(B, P, 0, R, LC, s);
+    launch_row_scan(B, 0, R, s);
+    launch_starts(B, P, 0, R, LC, s);
+    launch_tracklets(B, P, LC, s);
+    launch_claim(B, P, LC, s);
+    launch_keepfit(B, P, LC, s);
+    launch_track_scan(B, s);
+    launch_emit(B, P, LC, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void tpcsf_default_params(tpcsf_params* p)
+{
+    if (!p) return;
+    p->win_y = 3.0f;
+    p->win_z = 3.0f;
+    p->kink_max = 1.0f;
+    p->sigma_y = 0.1;
+    p->sigma_z = 0.1;
+    p->chi2_max = 16.0;
+    p->sinphi_max = 0.99;
+    p->nsig = 5.0;
+    p->c0[0] = 1.0; p->c0[1] = 1.0; p->c0[2] = 1.0; p->c0[3] = 1.0; p->c0[4] = 100.0;
+    p->min_chain = 5;
+    p->min_track_hits = 20;
+    p->max_miss = 4;
+}
+
+void tpcsf_default_tuning(tpcsf_tuning* t)
+{
+    if (!t) return;
+    t->bin_y = 2.0f;
+    t->bin_z = 2.0f;
+    t->cap_mul = 2;
+    t->cap_add = 64;
+    t->block = 256;
+    t->tl_block = 256;
+    t->chunk = 1;
+}
+
+tpcsf_status tpcsf_create(const tpcsf_geometry* geo, const tpcsf_params* params, const tpcsf_tuning* tuning,
+                          size_t hbm_budget_bytes, tpcsf_ctx** out)
+{
+    if (!out) return TPCSF_E_INVALID;
+    *out = nullptr;
+    if (!geo || !geo->row_x || geo->n_sectors < 1 || geo->n_rows < 3 || geo->n_rows > kMaxRows) return TPCSF_E_INVALID;
+    for (int r = 0; r + 1 < geo->n_rows; ++r)
+        if (!(geo->row_x[r + 1] > geo->row_x[r])) return TPCSF_E_INVALID;
+    if (!(geo->bz == geo->bz) || geo->bz > 100.0 || geo->bz < -100.0) return TPCSF_E_INVALID;
+    tpcsf_params p;
+    tpcsf_tuning t;
+    if (params) p = *params; else tpcsf_default_params(&p);
+    if (tuning) t = *tuning; else tpcsf_default_tuning(&t);
+    if (!params_ok(&p) || !tuning_ok(&t)) return TPCSF_E_INVALID;
+    tpcsf_ctx* c = new tpcsf_ctx();
+    c->n_sectors = geo->n_sectors;
+    c->n_rows = geo->n_rows;
+    c->row_x.assign(geo->row_x, geo->row_x + geo->n_rows);
+    c->bz = geo->bz;
+    c->params = p;
+    c->tuning = t;
+    c->budget = hbm_budget_bytes;
+    hipError_t e;
+    if ((e = hipGetDevice(&c->device)) != hipSuccess) { delete c; return TPCSF_E_HIP; }
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, c->device)) != hipSuccess) { delete c; return TPCSF_E_HIP; }
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if ((e = hipMalloc(&c->d_rx, sizeof(float) * c->n_rows)) != hipSuccess) { delete c; return TPCSF_E_NOMEM; }
+    if ((e = hipMalloc(&c->d_ctr, sizeof(Counters))) != hipSuccess) {
+        (void)hipFree(c->d_rx);
+        delete c;
+        return TPCSF_E_NOMEM;
+    }
+    (void)hipMemcpy(c->d_rx, c->row_x.data(), sizeof(float) * c->n_rows, hipMemcpyHostToDevice);
+    Counters zero{};
+    (void)hipMemcpy(c->d_ctr, &zero, sizeof(Counters), hipMemcpyHostToDevice);
+    if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        (void)hipFree(c->d_rx);
+        (void)hipFree(c->d_ctr);
+        delete c;
+        return TPCSF_E_HIP;
+    }
+    *out = c;
+    return TPCSF_OK;
+}
+
+tpcsf_status tpcsf_destroy(tpcsf_ctx* c)
+{
+    if (!c) return TPCSF_E_INVALID;
+    (void)hipDeviceSynchronize();
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->d_rx) (void)hipFree(c->d_rx);
+    if (c->d_ctr) (void)hipFree(c->d_ctr);
+    delete c;
+    return TPCSF_OK;
+}
+
+tpcsf_status tpcsf_set_tuning(tpcsf_ctx* c, const tpcsf_tuning* t)
+{
+    if (!c) return TPCSF_E_INVALID;
+    if (!tuning_ok(t)) return fail(c, TPCSF_E_INVALID, "tuning out of range");
+    c->tuning = *t;
+    return TPCSF_OK;
+}
+
+size_t tpcsf_arena_bytes(const tpcsf_ctx* c, int64_t n_clusters, int32_t n_tf)
+{
+    if (!c || n_clusters < 0 || n_tf < 1) return 0;
+    return make_layout(c, n_clusters, n_tf).total;
+}
+
+tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks* o, void* stream)
+{
+    if (!c) return TPCSF_E_INVALID;
+    tpcsf_status st = check_frame(c, f, o);
+    if (st != TPCSF_OK) return st;
+    const Layout L = make_layout(c, f->n_clusters, f->n_tf);
+    if ((st = ensure_arena(c, L)) != TPCSF_OK) return st;
+    c->lay = L;
+    const Batch B = make_batch(c, L, f, o);
+    const DevParams P = dev_params(c);
+    const LaunchCfg LC = launch_cfg(c);
+    hipStream_t s = (hipStream_t)stream;
+    launch_reset(B, s);
+    for (int32_t tf = 0; tf < f->n_tf; ++tf)
+        for (int32_t sec = 0; sec < c->n_sectors; ++sec) {
+            const int64_t g0 = ((int64_t)tf * c->n_sectors + sec) * c->n_rows;
+            const int64_t g1 = g0 + c->n_rows;
+            launch_grid(B, P, g0, g1, LC, s);
+            launch_links(B, P, g0, g1, LC, s);
+            launch_clean(B, P, g0, g1, LC, s);
+            launch_row_scan(B, g0, g1, s);
+            launch_starts(B, P, g0, g1, LC, s);
+            launch_tracklets(B, P, LC, s);
+            launch_claim(B, P, LC, s);
+            launch_keepfit(B, P, LC, s);
+            launch_track_scan(B, s);
+            launch_emit(B, P, LC, s);
+        }
+    c->last = B;
+    c->have_last = true;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    return TPCSF_OK;
+}
+
+tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks* o, void* stream)
+{
+    if (!c) return TPCSF_E_INVALID;
+    tpcsf_status st = check_frame(c, f, o);
+    if (st != TPCSF_OK) return st;
+    const Layout L = make_layout(c, f->n_clusters, f->n_tf);
+    if ((st = ensure_arena(c, L)) != TPCSF_OK) return st;
+    c->lay = L;
+    const Batch B = make_batch(c, L, f, o);
+    GraphKey k;
+    std::memset(&k, 0, sizeof k);
+    k.y = f->y; k.z = f->z; k.off = f->row_offsets; k.n = f->n_clusters; k.R = L.R;
+    k.arena = c->arena;
+    k.out = *o;
+    k.tuning = c->tuning;
+    hipError_t e;
+    if (!c->gexec || !(k == c->gkey)) {
+        if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+        if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+        if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(c, e, "hipStreamBeginCapture");
+        enqueue_batch(c, B, c->cap_stream);
+        if ((e = hipStreamEndCapture(c->cap_stream, &c->graph)) != hipSuccess)
+            return hip_fail(c, e, "hipStreamEndCapture");
+        if ((e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(c->graph);
+            c->graph = nullptr;
+            c->gexec = nullptr;
+            return hip_fail(c, e, "hipGraphInstantiate");
+        }
+        c->gkey = k;
+    }
+    if ((e = hipGraphLaunch(c->gexec, (hipStream_t)stream)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    c->last = B;
+    c->have_last = true;
+    return TPCSF_OK;
+}
+
+tpcsf_status tpcsf_sync(tpcsf_ctx* c, void* stream)
+{
+    if (!c) return TPCSF_E_INVALID;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    int32_t err = 0;
+    if ((e = hipMemcpy(&err, &c->d_ctr->err, sizeof(err), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(c, e, "reading the error word");
+    if (err) {
+        const int32_t zero = 0;
+        (void)hipMemcpy(&c->d_ctr->err, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    }
+    if (err & kErrInvalid) return fail(c, TPCSF_E_INVALID, "non-finite or out-of-range cluster coordinates");
+    if (err & kErrOutCap) return fail(c, TPCSF_E_CAPACITY, "output capacity too small");
+    if (err & kErrTrackletCap) return fail(c, TPCSF_E_CAPACITY, "tracklet slots exhausted");
+    return TPCSF_OK;
+}
+
+tpcsf_status tpcsf_debug(const tpcsf_ctx* c, tpcsf_debug_view* v)
+{
+    if (!c || !v || !c->have_last) return TPCSF_E_INVALID;
+    const Batch& B = c->last;
+    v->row_lo = (const float*)B.row_lo;
+    v->row_bin = (const float*)B.row_bin;
+    v->row_nb = (const int32_t*)B.row_nb;
+    v->bin_start = B.bin_start;
+    v->perm = B.perm;
+    v->up = B.up; v->dn = B.dn; v->cup = B.cup; v->cdn = B.cdn;
+    v->n_starts = &c->d_ctr->start_base;
+    v->start_row = B.start_row;
+    v->start_idx = B.start_idx;
+    v->tl_nhits = B.tl_n;
+    return TPCSF_OK;
+}
+
+const char* tpcsf_last_error(const tpcsf_ctx* c)
+{
+    return c ? c->err.c_str() : "null context";
+}
+
+}  // extern "C"

@@ -1,0 +1,326 @@
+"""Python binding of libtpcsf (include/tpcsf.h): argument marshalling only.
+
+Every step of the tracking runs in the HIP kernels of libtpcsf.so; this module passes
+torch device pointers, sizes and the current HIP stream through the C ABI, and wraps the
+results as torch tensors.  There is no CPU fallback: if the library is missing or no GPU
+is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpcsf.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "tpcsf.h")
+
+OK, E_INVALID, E_NOMEM, E_CAPACITY, E_HIP, E_BUSY, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_CAPACITY", -4: "E_HIP", -5: "E_BUSY",
+          -6: "E_TIMEOUT"}
+
+
+class TpcsfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tpcsf {_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geometry(C.Structure):
+    _fields_ = [("n_sectors", C.c_int32), ("n_rows", C.c_int32), ("row_x", C.c_void_p), ("bz", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("win_y", C.c_float), ("win_z", C.c_float), ("kink_max", C.c_float),
+                ("sigma_y", C.c_double), ("sigma_z", C.c_double), ("chi2_max", C.c_double),
+                ("sinphi_max", C.c_double), ("nsig", C.c_double), ("c0", C.c_double * 5),
+                ("min_chain", C.c_int32), ("min_track_hits", C.c_int32), ("max_miss", C.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["c0"] = tuple(self.c0)
+        return d
+
+
+class Tuning(C.Structure):
+    _fields_ = [("bin_y", C.c_float), ("bin_z", C.c_float), ("cap_mul", C.c_int32), ("cap_add", C.c_int32),
+                ("block", C.c_int32), ("tl_block", C.c_int32), ("chunk", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FrameDesc(C.Structure):
+    _fields_ = [("n_tf", C.c_int32), ("n_clusters", C.c_int64), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("row_offsets", C.c_void_p), ("row_offsets_host", C.c_void_p)]
+
+
+class TracksDesc(C.Structure):
+    _fields_ = [("cap_tracks", C.c_int64), ("cap_hits", C.c_int64), ("n_tracks", C.c_void_p),
+                ("n_hits", C.c_void_p), ("params", C.c_void_p), ("cov", C.c_void_p), ("x_ref", C.c_void_p),
+                ("chi2", C.c_void_p), ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p),
+                ("tf", C.c_void_p), ("hit_off", C.c_void_p), ("hit_ids", C.c_void_p),
+                ("cluster_track", C.c_void_p)]
+
+
+class DebugView(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("row_lo", "row_bin", "row_nb", "bin_start", "perm", "up", "dn",
+                                           "cup", "cdn", "n_starts", "start_row", "start_idx", "tl_nhits")]
+
+
+_lib = None
+
+
+def load():
+    """Load libtpcsf.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # torch ships its own HIP runtime under the same soname; load it first so that the
+    # library and torch's allocator and streams share one runtime in this process
+    import torch  # noqa: F401
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.tpcsf_default_params.argtypes = [C.POINTER(Params)]
+    lib.tpcsf_default_params.restype = None
+    lib.tpcsf_default_tuning.argtypes = [C.POINTER(Tuning)]
+    lib.tpcsf_default_tuning.restype = None
+    lib.tpcsf_create.argtypes = [C.POINTER(Geometry), C.POINTER(Params), C.POINTER(Tuning), C.c_size_t,
+                                 C.POINTER(vp)]
+    lib.tpcsf_create.restype = C.c_int
+    lib.tpcsf_destroy.argtypes = [vp]
+    lib.tpcsf_destroy.restype = C.c_int
+    lib.tpcsf_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    lib.tpcsf_set_tuning.restype = C.c_int
+    lib.tpcsf_arena_bytes.argtypes = [vp, C.c_int64, C.c_int32]
+    lib.tpcsf_arena_bytes.restype = C.c_size_t
+    for fn in ("tpcsf_track_plain", "tpcsf_track_batch"):
+        getattr(lib, fn).argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), vp]
+        getattr(lib, fn).restype = C.c_int
+    lib.tpcsf_sync.argtypes = [vp, vp]
+    lib.tpcsf_sync.restype = C.c_int
+    lib.tpcsf_debug.argtypes = [vp, C.POINTER(DebugView)]
+    lib.tpcsf_debug.restype = C.c_int
+    lib.tpcsf_last_error.argtypes = [vp]
+    lib.tpcsf_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def header_symbols():
+    """Function names declared in include/tpcsf.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(tpcsf_[a-z_]+)\s*\(", txt)))
+
+
+def default_params():
+    p = Params()
+    load().tpcsf_default_params(C.byref(p))
+    return p
+
+
+def default_tuning():
+    t = Tuning()
+    load().tpcsf_default_tuning(C.byref(t))
+    return t
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class DeviceFrame:
+    """A batch of time frames resident in device memory (torch tensors) plus the host copy
+    of the row offsets the library validates."""
+
+    def __init__(self, y, z, row_off, row_off_host, n_tf):
+        self.y, self.z, self.row_off = y, z, row_off
+        self.row_off_host = np.ascontiguousarray(row_off_host, dtype=np.int64)
+        self.n_tf = int(n_tf)
+
+    @property
+    def n_clusters(self):
+        return int(self.y.shape[0])
+
+    @classmethod
+    def from_numpy(cls, y, z, row_off, n_tf=1, device="cuda"):
+        import torch
+        y = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(device)
+        z = torch.from_numpy(np.ascontiguousarray(z, dtype=np.float32)).to(device)
+        ro = np.ascontiguousarray(row_off, dtype=np.int64)
+        return cls(y, z, torch.from_numpy(ro).to(device), ro, n_tf)
+
+    def desc(self):
+        d = FrameDesc()
+        d.n_tf = self.n_tf
+        d.n_clusters = self.n_clusters
+        d.y = _ptr(self.y) if self.n_clusters else None
+        d.z = _ptr(self.z) if self.n_clusters else None
+        d.row_offsets = _ptr(self.row_off)
+        d.row_offsets_host = self.row_off_host.ctypes.data_as(C.c_void_p)
+        return d
+
+
+class TrackBuffers:
+    """Caller-owned output buffers (device).  Default capacities are exact upper bounds:
+    a track keeps >= min_track_hits clusters and no cluster is in two tracks."""
+
+    def __init__(self, n_clusters, cap_tracks=None, cap_hits=None, min_track_hits=20, device="cuda"):
+        import torch
+        n = int(n_clusters)
+        self.cap_tracks = int(cap_tracks if cap_tracks is not None else n // max(1, min_track_hits) + 1)
+        self.cap_hits = int(cap_hits if cap_hits is not None else n)
+        T, H = self.cap_tracks, self.cap_hits
+        kw = dict(device=device)
+        self.n_tracks = torch.zeros(1, dtype=torch.int64, **kw)
+        self.n_hits = torch.zeros(1, dtype=torch.int64, **kw)
+        self.params = torch.empty((max(T, 1), 5), dtype=torch.float64, **kw)
+        self.cov = torch.empty((max(T, 1), 15), dtype=torch.float64, **kw)
+        self.x_ref = torch.empty(max(T, 1), dtype=torch.float64, **kw)
+        self.chi2 = torch.empty(max(T, 1), dtype=torch.float64, **kw)
+        self.ndf = torch.empty(max(T, 1), dtype=torch.int32, **kw)
+        self.nhits = torch.empty(max(T, 1), dtype=torch.int32, **kw)
+        self.sector = torch.empty(max(T, 1), dtype=torch.int32, **kw)
+        self.tf = torch.empty(max(T, 1), dtype=torch.int32, **kw)
+        self.hit_off = torch.zeros(T + 1, dtype=torch.int64, **kw)
+        self.hit_ids = torch.empty(max(H, 1), dtype=torch.int32, **kw)
+        self.cluster_track = torch.empty(max(n, 1), dtype=torch.int32, **kw)
+
+    def desc(self):
+        d = TracksDesc()
+        d.cap_tracks, d.cap_hits = self.cap_tracks, self.cap_hits
+        for k in ("n_tracks", "n_hits", "params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector", "tf",
+                  "hit_off", "hit_ids", "cluster_track"):
+            setattr(d, k, _ptr(getattr(self, k)))
+        return d
+
+    def result(self, n_clusters):
+        """Slices of the buffers holding the last call's tracks (after a sync)."""
+        T = int(self.n_tracks.item())
+        H = int(self.n_hits.item())
+        return dict(n_tracks=T, n_hits=H, params=self.params[:T], cov=self.cov[:T], x_ref=self.x_ref[:T],
+                    chi2=self.chi2[:T], ndf=self.ndf[:T], nhits=self.nhits[:T], sector=self.sector[:T],
+                    tf=self.tf[:T], hit_off=self.hit_off[:T + 1], hit_ids=self.hit_ids[:H],
+                    cluster_track=self.cluster_track[:n_clusters])
+
+
+class Tracker:
+    """A tpcsf context on the current HIP device."""
+
+    def __init__(self, row_x, bz=0.5, n_sectors=36, params=None, tuning=None, hbm_budget=0):
+        lib = load()
+        self.lib = lib
+        self.row_x = np.ascontiguousarray(row_x, dtype=np.float32)
+        self.n_sectors = int(n_sectors)
+        self.n_rows = int(self.row_x.shape[0])
+        geo = Geometry(self.n_sectors, self.n_rows, self.row_x.ctypes.data_as(C.c_void_p), float(bz))
+        p = default_params()
+        for k, v in (params or {}).items():
+            if k == "c0":
+                p.c0 = (C.c_double * 5)(*v)
+            else:
+                setattr(p, k, v)
+        t = default_tuning()
+        for k, v in (tuning or {}).items():
+            setattr(t, k, v)
+        self.params, self.tuning = p, t
+        h = C.c_void_p()
+        st = lib.tpcsf_create(C.byref(geo), C.byref(p), C.byref(t), int(hbm_budget), C.byref(h))
+        if st != OK:
+            raise TpcsfError(st, "tpcsf_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tpcsf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise TpcsfError(st, self.lib.tpcsf_last_error(self.h).decode())
+
+    def set_tuning(self, **kw):
+        t = Tuning.from_buffer_copy(self.tuning)
+        for k, v in kw.items():
+            setattr(t, k, v)
+        self._check(self.lib.tpcsf_set_tuning(self.h, C.byref(t)))
+        self.tuning = t
+
+    def arena_bytes(self, n_clusters, n_tf=1):
+        return int(self.lib.tpcsf_arena_bytes(self.h, int(n_clusters), int(n_tf)))
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return C.c_void_p(s.cuda_stream)
+
+    def launch(self, frame: DeviceFrame, out: TrackBuffers, mode="batch", stream=None):
+        """Enqueue one tracking call (no sync)."""
+        fd, od = frame.desc(), out.desc()
+        fn = self.lib.tpcsf_track_batch if mode == "batch" else self.lib.tpcsf_track_plain
+        self._check(fn(self.h, C.byref(fd), C.byref(od), self._stream(stream)))
+
+    def sync(self, stream=None):
+        self._check(self.lib.tpcsf_sync(self.h, self._stream(stream)))
+
+    def track(self, frame: DeviceFrame, mode="batch", out=None, stream=None):
+        """Track a batch and return the result tensors (synchronises)."""
+        if out is None:
+            out = TrackBuffers(frame.n_clusters, min_track_hits=self.params.min_track_hits)
+        self.launch(frame, out, mode, stream)
+        self.sync(stream)
+        return out.result(frame.n_clusters)
+
+    def debug(self, frame: DeviceFrame):
+        """Copies of the last call's intermediate arrays (grid, links, starts)."""
+        import torch
+        v = DebugView()
+        self._check(self.lib.tpcsf_debug(self.h, C.byref(v)))
+        n, R = frame.n_clusters, frame.n_tf * self.n_sectors * self.n_rows
+
+        torch.cuda.synchronize()
+
+        def dev(ptr, count, dtype):
+            buf = np.empty(count, dtype=dtype)
+            if count:
+                _memcpy_d2h(buf.ctypes.data, ptr, buf.nbytes)
+            return buf
+
+        ns = int(dev(v.n_starts, 1, np.int64)[0])
+        res = dict(row_lo=dev(v.row_lo, 2 * R, np.float32).reshape(R, 2),
+                   row_bin=dev(v.row_bin, 2 * R, np.float32).reshape(R, 2),
+                   row_nb=dev(v.row_nb, 2 * R, np.int32).reshape(R, 2),
+                   perm=dev(v.perm, n, np.uint32), up=dev(v.up, n, np.int32), dn=dev(v.dn, n, np.int32),
+                   cup=dev(v.cup, n, np.int32), cdn=dev(v.cdn, n, np.int32), n_starts=ns,
+                   start_row=dev(v.start_row, ns, np.int32), start_idx=dev(v.start_idx, ns, np.int32),
+                   tl_nhits=dev(v.tl_nhits, ns, np.int32))
+        t = self.tuning
+        nb_total = int(t.cap_mul) * n + (int(t.cap_add) + 1) * R
+        res["bin_start"] = dev(v.bin_start, nb_total, np.uint32)
+        return res
+
+
+_hip = None
+
+
+def _memcpy_d2h(dst, src, nbytes):
+    """hipMemcpy device-to-host (used only to read the debug view of the arena)."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 2)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
