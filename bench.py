@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of TPC sector track finding on one MI355X.
+
+Workload: one 2 ms continuous-readout Pb-Pb time frame (Poisson 50 kHz collisions,
+Exp(1500) primaries each, 10% secondaries, 5% noise, z shifted by the drift velocity
+times the collision time), all 36 sectors x 152 rows, generated with a fixed seed.  The
+paper's Run 3 time frames are not available; this synthetic frame has their shape.
+
+A step is one batched tracking call over the whole time frame (every stage, every
+sector, one HIP graph replay) with the clusters already resident in HBM.  The plain form
+(every stage launched per sector) is timed beside it on the same input.  The reference
+oracle is timed on a bounded sample of the same frame on the host cores.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TPC clusters tracked/sec on 1 MI355X (batched vs plain) + p99 time-frame latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_bytes(c):
+    """Algorithmic HBM bytes of each stage: every stage-boundary array written once and
+    read once where a later stage needs it (no re-reads, no atomics' extra traffic).
+    c: counts N clusters, R rows, B bin entries, S starts, K tracklets, H_t tracklet
+    clusters, H_c clusters of tracklets taking part in the selection, H_a accepted
+    clusters, T tracks, nr rows per sector."""
+    N, R, B, S, K, Ht, Hc, Ha, T, nr = (c[k] for k in ("N", "R", "B", "S", "K", "Ht", "Hc", "Ha", "T", "nr"))
+    return {
+        "reset": 0,
+        # read y, z; write sorted y, z, perm, bin_start; clear W and cluster_track
+        "grid": 8 * N + 12 * N + 4 * B + 12 * N,
+        # read sorted y, z, perm, bin_start; write up, dn
+        "links": 12 * N + 4 * B + 8 * N,
+        # read up, dn; write cleaned links; per-row start counts
+        "clean": 16 * N + 8 * R,
+        "row_scan": 16 * R,
+        # read cleaned links; write (row, index) of every start
+        "starts": 8 * N + 8 * S,
+        # read starts, chain links and the coordinates of every tracklet cluster; write
+        # the row-indexed tracklet table and sizes
+        "tracklets": 12 * S + 12 * Ht + 2 * nr * K,
+        # read sizes and tables; read-modify-write one 8-byte weight per cluster
+        "claim": 4 * S + 2 * nr * K + 16 * Hc,
+        # read sizes, tables, weights, kept coordinates; write flags and fit results
+        "keepfit": 4 * S + 2 * nr * K + 8 * Hc + 8 * Ha + 8 * S + 208 * T,
+        "track_scan": 24 * S,
+        # read fit results; write track records, hit lists and the cluster->track map
+        "emit": 208 * T + 200 * T + 8 * Ha,
+    }
+
+
+def counts_from(trk, frame, res, nr):
+    d = trk.debug(frame)
+    nb = d["row_nb"].astype(np.int64)
+    tl = d["tl_nhits"].astype(np.int64)
+    return dict(N=frame.n_clusters, R=int(nb.shape[0]), B=int((nb[:, 0] * nb[:, 1] + 1).sum()),
+                S=int(d["n_starts"]), K=int((tl > 0).sum()), Ht=int(tl.sum()), Hc=int(tl[tl >= 20].sum()),
+                Ha=int(res["n_hits"]), T=int(res["n_tracks"]), nr=nr)
+
+
+def cpu_baseline(f, budget_s, max_sectors):
+    """The FP64 oracle on whole sectors of the same frame until ~budget_s of CPU time."""
+    import oracle
+    from paper_2009_07515_amd import synth
+    o = oracle.Oracle(synth.row_x())
+    R = 36 * 152
+    counts = np.diff(f.row_off)
+    done_cl, done_t, sectors = 0, 0.0, []
+    order = [0, 18, 9, 27, 4, 22, 13, 31, 2, 20, 11, 29]
+    for s in order[:max_sectors]:
+        sub = np.zeros(R, np.int64)
+        sub[s * 152:(s + 1) * 152] = counts[s * 152:(s + 1) * 152]
+        a, b = f.row_off[s * 152], f.row_off[(s + 1) * 152]
+        ro = np.concatenate([[0], np.cumsum(sub)]).astype(np.int64)
+        t0 = time.perf_counter()
+        o.track_frame(f.y[a:b], f.z[a:b], ro)
+        done_t += time.perf_counter() - t0
+        done_cl += int(b - a)
+        sectors.append(s)
+        log(f"oracle sector {s}: {b - a} clusters, cumulative {done_t:.1f} s")
+        if done_t >= budget_s:
+            break
+    return dict(value=done_cl / done_t, unit="clusters/s", cores=1, kind="oracle",
+                sample=f"FP64 oracle, 1 thread, sectors {sectors} of the same time frame "
+                       f"({done_cl} clusters, {done_t:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--tf-us", type=float, default=2000.0, help="time-frame length (us)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
+    ap.add_argument("--cpu-sectors", type=int, default=6)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tuning", type=str, default="", help="JSON dict of tuning overrides")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (for byte-counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        if int(os.environ.get("RANK", "0")) == 0:
+            print("bench.py: this build measures one GPU only; --gpus must be 1 "
+                  "(time frames are independent and would shard across GPUs without communication)",
+                  file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2009_07515_amd import synth, tpcsf
+
+    log("generating the time frame")
+    t0 = time.perf_counter()
+    f = synth.config3_time_frame(length_us=args.tf_us)
+    N = f.n_clusters
+    log(f"{N} clusters, {f.n_events} collisions, generated in {time.perf_counter() - t0:.1f} s")
+
+    torch.cuda.set_device(0)
+    frame = tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off, device="cuda:0")
+    tuning = json.loads(args.tuning) if args.tuning else None
+    trk = tpcsf.Tracker(synth.row_x(), tuning=tuning)
+    out = tpcsf.TrackBuffers(N)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    # reference result of this input (also warms the graph)
+    res0 = trk.track(frame, out=out, mode="batch")
+    T0, H0 = res0["n_tracks"], res0["n_hits"]
+    log(f"{T0} tracks, {H0} assigned clusters")
+    for _ in range(args.warmup):
+        trk.launch(frame, out, "batch")
+    torch.cuda.synchronize()
+
+    # timed region: K batched steps back to back
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record(stream)
+        trk.launch(frame, out, "batch")
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    trk.sync()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    ms = wall * 1e3 / K
+    value = N / (wall / K)
+    assert int(out.n_tracks.item()) == T0 and int(out.n_hits.item()) == H0
+    log(f"batched: {ms:.3f} ms/step, {value / 1e9:.3f} G clusters/s")
+
+    # plain per-sector form on the same input
+    plain = None
+    if args.plain_steps > 0:
+        trk.track(frame, out=out, mode="plain")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            trk.launch(frame, out, "plain")
+        torch.cuda.synchronize()
+        wall_p = time.perf_counter() - t0
+        trk.sync()
+        assert int(out.n_tracks.item()) == T0 and int(out.n_hits.item()) == H0
+        ms_p = wall_p * 1e3 / args.plain_steps
+        plain = {"value": N / (wall_p / args.plain_steps), "ms_per_step": ms_p, "steps": args.plain_steps}
+        log(f"plain: {ms_p:.3f} ms/step, {plain['value'] / 1e9:.3f} G clusters/s")
+
+    # calibration copy for hardware byte counters: one device copy of a known size
+    if args.calib_copy_mib > 0:
+        n_el = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n_el, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del a, b
+
+    # stage timing: event nodes inside the same graph, K more timed replays
+    trk.set_stage_timing(True)
+    trk.track(frame, out=out, mode="batch")
+    acc = None
+    for _ in range(K):
+        trk.launch(frame, out, "batch")
+        trk.sync()
+        st = trk.stage_times()
+        acc = st if acc is None else {k: acc[k] + st[k] for k in st}
+    stages = {k: v / K for k, v in acc.items()}
+    res = out.result(N)
+    cnt = counts_from(trk, frame, res, 152)
+    sb = stage_bytes(cnt)
+    dom = max((k for k in stages if k != "reset"), key=lambda k: stages[k])
+    achieved = sb[dom] / (stages[dom] * 1e-3) / 1e9
+    path_bytes = sum(sb.values())
+    log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32+fp64",
+        "data": "synthetic",
+        "config": {"workload": f"one {args.tf_us / 1000:g} ms continuous-readout Pb-Pb time frame, 36 sectors x 152 rows",
+                   "clusters": N, "collisions": f.n_events, "tracks": T0, "batch_time_frames": 1,
+                   "tuning": trk.tuning.as_dict()},
+        "plain": plain,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "stages_ms": stages,
+        "counts": cnt,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": sb[dom]},
+        "path_hbm": {"bytes_per_cluster": path_bytes / N,
+                     "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
+                     "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(f, args.cpu_budget, args.cpu_sectors)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

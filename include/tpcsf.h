@@ -172,6 +172,16 @@ typedef struct {
 } tpcsf_debug_view;
 tpcsf_status tpcsf_debug(const tpcsf_ctx* ctx, tpcsf_debug_view* view);
 
+/* Stage timing (tracing).  When on, tpcsf_track_batch() enqueues the same launch sequence
+ * as its graph, but eagerly on the caller's stream with a HIP event before each stage and
+ * after the last one.  After tpcsf_sync(), tpcsf_stage_times() writes the duration (ms) of
+ * each stage of the last batched call into ms[0 .. min(n, tpcsf_stage_count())).
+ * Stage names come from tpcsf_stage_name(i) (static strings). */
+tpcsf_status tpcsf_set_stage_timing(tpcsf_ctx* ctx, int32_t on);
+int32_t tpcsf_stage_count(void);
+const char* tpcsf_stage_name(int32_t stage);
+tpcsf_status tpcsf_stage_times(tpcsf_ctx* ctx, float* ms, int32_t n);
+
 /* Message of the last error on this context (static storage of the context). */
 const char* tpcsf_last_error(const tpcsf_ctx* ctx);
 

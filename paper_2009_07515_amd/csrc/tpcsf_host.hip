@@ -26,6 +26,10 @@ struct Layout {
     size_t tl_hits, f_par, f_cov, f_chi2, f_xref, f_mask, scan_part;
 };
 
+constexpr int kStages = 11;
+const char* const kStageNames[kStages] = {"reset", "grid", "links", "clean", "row_scan", "starts",
+                                          "tracklets", "claim", "keepfit", "track_scan", "emit"};
+
 struct GraphKey {
     const void* y = nullptr; const void* z = nullptr; const void* off = nullptr;
     int64_t n = -1; int64_t R = -1;
@@ -55,6 +59,9 @@ struct tpcsf_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     GraphKey gkey{};
+    int32_t timing = 0;
+    hipEvent_t ev[kStages + 1] = {};
+    bool timed_last = false;
     Batch last{};
     bool have_last = false;
     std::string err;
@@ -261,23 +268,30 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     return B;
 }
 
-// The whole batch, one launch per stage.
-void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s)
+// The whole batch, one launch per stage; with `ev`, an event before each stage and after
+// the last one (used only outside graph capture).
+void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t* ev)
 {
     const DevParams P = dev_params(c);
     const LaunchCfg LC = launch_cfg(c);
     const int64_t R = B.n_rows_total;
-    launch_reset(B, s);
-    launch_grid(B, P, 0, R, LC, s);
-    launch_links(B, P, 0, R, LC, s);
-    launch_clean(B, P, 0, R, LC, s);
-    launch_row_scan(B, 0, R, s);
-    launch_starts(B, P, 0, R, LC, s);
-    launch_tracklets(B, P, LC, s);
-    launch_claim(B, P, LC, s);
-    launch_keepfit(B, P, LC, s);
-    launch_track_scan(B, s);
-    launch_emit(B, P, LC, s);
+    int k = 0;
+    auto mark = [&]() {
+        if (ev) (void)hipEventRecord(ev[k], s);
+        ++k;
+    };
+    mark(); launch_reset(B, s);
+    mark(); launch_grid(B, P, 0, R, LC, s);
+    mark(); launch_links(B, P, 0, R, LC, s);
+    mark(); launch_clean(B, P, 0, R, LC, s);
+    mark(); launch_row_scan(B, 0, R, s);
+    mark(); launch_starts(B, P, 0, R, LC, s);
+    mark(); launch_tracklets(B, P, LC, s);
+    mark(); launch_claim(B, P, LC, s);
+    mark(); launch_keepfit(B, P, LC, s);
+    mark(); launch_track_scan(B, s);
+    mark(); launch_emit(B, P, LC, s);
+    mark();
 }
 
 }  // namespace
@@ -367,6 +381,8 @@ tpcsf_status tpcsf_destroy(tpcsf_ctx* c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->arena) (void)hipFree(c->arena);
+    for (int i = 0; i <= kStages; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->d_rx) (void)hipFree(c->d_rx);
     if (c->d_ctr) (void)hipFree(c->d_ctr);
     delete c;
@@ -417,6 +433,7 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
         }
     c->last = B;
     c->have_last = true;
+    c->timed_last = false;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
     return TPCSF_OK;
@@ -438,12 +455,22 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
     k.out = *o;
     k.tuning = c->tuning;
     hipError_t e;
+    if (c->timing) {
+        // timed calls run the same launch sequence eagerly on the caller's stream, with an
+        // event between stages (event timing is not available inside graphs here)
+        enqueue_batch(c, B, (hipStream_t)stream, c->ev);
+        c->timed_last = true;
+        c->last = B;
+        c->have_last = true;
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "kernel launch");
+        return TPCSF_OK;
+    }
     if (!c->gexec || !(k == c->gkey)) {
         if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
         if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
         if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(c, e, "hipStreamBeginCapture");
-        enqueue_batch(c, B, c->cap_stream);
+        enqueue_batch(c, B, c->cap_stream, nullptr);
         if ((e = hipStreamEndCapture(c->cap_stream, &c->graph)) != hipSuccess)
             return hip_fail(c, e, "hipStreamEndCapture");
         if ((e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0)) != hipSuccess) {
@@ -455,6 +482,7 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
         c->gkey = k;
     }
     if ((e = hipGraphLaunch(c->gexec, (hipStream_t)stream)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    c->timed_last = false;
     c->last = B;
     c->have_last = true;
     return TPCSF_OK;
@@ -492,6 +520,34 @@ tpcsf_status tpcsf_debug(const tpcsf_ctx* c, tpcsf_debug_view* v)
     v->start_row = B.start_row;
     v->start_idx = B.start_idx;
     v->tl_nhits = B.tl_n;
+    return TPCSF_OK;
+}
+
+tpcsf_status tpcsf_set_stage_timing(tpcsf_ctx* c, int32_t on)
+{
+    if (!c) return TPCSF_E_INVALID;
+    if (on && !c->ev[0]) {
+        for (int i = 0; i <= kStages; ++i) {
+            hipError_t e = hipEventCreate(&c->ev[i]);
+            if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+        }
+    }
+    c->timing = on ? 1 : 0;
+    return TPCSF_OK;
+}
+
+int32_t tpcsf_stage_count(void) { return kStages; }
+
+const char* tpcsf_stage_name(int32_t i) { return (i >= 0 && i < kStages) ? kStageNames[i] : ""; }
+
+tpcsf_status tpcsf_stage_times(tpcsf_ctx* c, float* ms, int32_t n)
+{
+    if (!c || !ms) return TPCSF_E_INVALID;
+    if (!c->timed_last) return fail(c, TPCSF_E_INVALID, "the last call was not a timed batched call");
+    for (int i = 0; i < kStages && i < n; ++i) {
+        hipError_t e = hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+    }
     return TPCSF_OK;
 }
 

@@ -105,6 +105,14 @@ def load():
     lib.tpcsf_sync.restype = C.c_int
     lib.tpcsf_debug.argtypes = [vp, C.POINTER(DebugView)]
     lib.tpcsf_debug.restype = C.c_int
+    lib.tpcsf_set_stage_timing.argtypes = [vp, C.c_int32]
+    lib.tpcsf_set_stage_timing.restype = C.c_int
+    lib.tpcsf_stage_count.argtypes = []
+    lib.tpcsf_stage_count.restype = C.c_int32
+    lib.tpcsf_stage_name.argtypes = [C.c_int32]
+    lib.tpcsf_stage_name.restype = C.c_char_p
+    lib.tpcsf_stage_times.argtypes = [vp, C.POINTER(C.c_float), C.c_int32]
+    lib.tpcsf_stage_times.restype = C.c_int
     lib.tpcsf_last_error.argtypes = [vp]
     lib.tpcsf_last_error.restype = C.c_char_p
     _lib = lib
@@ -281,6 +289,19 @@ class Tracker:
         self.launch(frame, out, mode, stream)
         self.sync(stream)
         return out.result(frame.n_clusters)
+
+    def set_stage_timing(self, on=True):
+        self._check(self.lib.tpcsf_set_stage_timing(self.h, 1 if on else 0))
+
+    def stage_names(self):
+        return [self.lib.tpcsf_stage_name(i).decode() for i in range(self.lib.tpcsf_stage_count())]
+
+    def stage_times(self):
+        """{stage: ms} of the last timed batched call (after a sync)."""
+        n = self.lib.tpcsf_stage_count()
+        buf = (C.c_float * n)()
+        self._check(self.lib.tpcsf_stage_times(self.h, buf, n))
+        return dict(zip(self.stage_names(), [float(v) for v in buf]))
 
     def debug(self, frame: DeviceFrame):
         """Copies of the last call's intermediate arrays (grid, links, starts)."""
