@@ -34,32 +34,38 @@ def log(msg):
 
 def stage_bytes(c):
     """Algorithmic HBM bytes of each stage: every stage-boundary array written once and
-    read once where a later stage needs it (no re-reads, no atomics' extra traffic).
-    c: counts N clusters, R rows, B bin entries, S starts, K tracklets, H_t tracklet
-    clusters, H_c clusters of tracklets taking part in the selection, H_a accepted
-    clusters, T tracks, nr rows per sector."""
-    N, R, B, S, K, Ht, Hc, Ha, T, nr = (c[k] for k in ("N", "R", "B", "S", "K", "Ht", "Hc", "Ha", "T", "nr"))
+    read once where a later stage needs it (no re-reads, no atomics' extra traffic, no
+    candidate scans).  c holds the counts of the measured input: N clusters, R rows, B bin
+    entries, C clusters on cleaned chains, S starts, K tracklets, H_t tracklet clusters,
+    H_c clusters of tracklets in the selection, F track candidates, H_a accepted clusters,
+    T tracks, nr rows per sector."""
+    N, R, B, C, S, K, Ht, Hc, F, Ha, T, nr = (c[k] for k in ("N", "R", "B", "C", "S", "K", "Ht", "Hc", "F", "Ha",
+                                                             "T", "nr"))
     return {
         "reset": 0,
-        # read y, z; write sorted y, z, perm, bin_start; clear W and cluster_track
-        "grid": 8 * N + 12 * N + 4 * B + 12 * N,
-        # read sorted y, z, perm, bin_start; write up, dn
+        # read y, z; write sorted (y, z), perm, inverse perm, bin table; clear W and cluster_track
+        "grid": 8 * N + 16 * N + 4 * B + 8 * N,
+        # read sorted (y, z), perm, bin tables; write up, dn
         "links": 12 * N + 4 * B + 8 * N,
         # read up, dn; write cleaned links; per-row start counts
         "clean": 16 * N + 8 * R,
         "row_scan": 16 * R,
-        # read cleaned links; write (row, index) of every start
-        "starts": 8 * N + 8 * S,
-        # read starts, chain links and the coordinates of every tracklet cluster; write
-        # the row-indexed tracklet table and sizes
-        "tracklets": 12 * S + 12 * Ht + 2 * nr * K,
-        # read sizes and tables; read-modify-write one 8-byte weight per cluster
-        "claim": 4 * S + 2 * nr * K + 16 * Hc,
-        # read sizes, tables, weights, kept coordinates; write flags and fit results
-        "keepfit": 4 * S + 2 * nr * K + 8 * Hc + 8 * Ha + 8 * S + 208 * T,
+        # read cleaned links and the inverse perm; write (row, position, rank) of every start
+        "starts": 12 * N + 12 * S,
+        # read starts and the chain links; write chain rows of the hit table, lengths, order
+        "walk": 8 * S + 4 * C + 2 * C + 8 * S + 4 * K,
+        # read order, start, chain coordinates (twice: fit and refit); write the hit table rows
+        # outside the chain and the tracklet record
+        "tracklets": 16 * K + 16 * Ht + 2 * nr * K,
+        # read tracklet records and tables; read-modify-write one 4-byte weight per cluster
+        "claim": 12 * K + 2 * nr * K + 8 * Hc,
+        # read records, tables and weights; write kept masks and the candidate list
+        "keep": 12 * K + 2 * nr * K + 4 * Hc + 40 * F,
+        # read candidates, masks, kept coordinates (twice); write the fit results
+        "fit": 44 * F + 16 * Ha + 2 * Ha + 176 * F,
         "track_scan": 24 * S,
         # read fit results; write track records, hit lists and the cluster->track map
-        "emit": 208 * T + 200 * T + 8 * Ha,
+        "emit": 176 * T + 48 * T + 8 * Ha + 6 * Ha,
     }
 
 
@@ -67,9 +73,10 @@ def counts_from(trk, frame, res, nr):
     d = trk.debug(frame)
     nb = d["row_nb"].astype(np.int64)
     tl = d["tl_nhits"].astype(np.int64)
-    return dict(N=frame.n_clusters, R=int(nb.shape[0]), B=int((nb[:, 0] * nb[:, 1] + 1).sum()),
+    linked = int(((d["cup"] >= 0) | (d["cdn"] >= 0)).sum())
+    return dict(N=frame.n_clusters, R=int(nb.shape[0]), B=int((nb[:, 0] * nb[:, 1] + 1).sum()), C=linked,
                 S=int(d["n_starts"]), K=int((tl > 0).sum()), Ht=int(tl.sum()), Hc=int(tl[tl >= 20].sum()),
-                Ha=int(res["n_hits"]), T=int(res["n_tracks"]), nr=nr)
+                F=int(res["n_tracks"]), Ha=int(res["n_hits"]), T=int(res["n_tracks"]), nr=nr)
 
 
 def cpu_baseline(f, budget_s, max_sectors):

@@ -152,7 +152,8 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_t
 tpcsf_status tpcsf_sync(tpcsf_ctx* ctx, void* stream);
 
 /* Intermediate results of the last call, for verification (device pointers into the
- * arena, valid until the next call on the context).  Layout:
+ * arena, valid until the next call on the context).  The call synchronises the device
+ * and converts the working arrays (kept in sorted bin order) to input order.  Layout:
  *   row_lo[2*g], row_lo[2*g+1]   y_lo, z_lo of global row g        (float)
  *   row_bin[2*g], row_bin[2*g+1] bin sizes b_y, b_z actually used     (float)
  *   row_nb[2*g], row_nb[2*g+1]   ny, nz                               (int32)
@@ -170,7 +171,7 @@ typedef struct {
     const int64_t* n_starts; const int32_t* start_row; const int32_t* start_idx;
     const int32_t* tl_nhits;
 } tpcsf_debug_view;
-tpcsf_status tpcsf_debug(const tpcsf_ctx* ctx, tpcsf_debug_view* view);
+tpcsf_status tpcsf_debug(tpcsf_ctx* ctx, tpcsf_debug_view* view);
 
 /* Stage timing (tracing).  When on, tpcsf_track_batch() enqueues the same launch sequence
  * as its graph, but eagerly on the caller's stream with a HIP event before each stage and

@@ -19,16 +19,19 @@ constexpr double kCB = 0.00299792458;   // cm^-1 T^-1 GeV
 
 struct Layout {
     size_t total = 0;
-    int64_t n = 0, R = 0, cap_starts = 0, cap_tl = 0, n_bins = 0;
+    int64_t n = 0, R = 0, cap_starts = 0, cap_fit = 0, n_bins = 0;
     size_t row_lo, row_bin, row_nb, row_nstart, row_sbase;
-    size_t bin_start, bin_fill, ys, zs, perm, up, dn, cup, cdn, W;
-    size_t start_row, start_idx, tl_n, tl_slot, trk_flag, hit_cnt, trk_idx, hit_pos;
-    size_t tl_hits, f_par, f_cov, f_chi2, f_xref, f_mask, scan_part;
+    size_t bin_start, bin_fill, yz, perm, iperm, upk, dnk, cupk, cdnk, rank_at, W;
+    size_t st_row, st_k, st_rank, tl_len, order, tl_n, tl_rlo, tl_rhi, tl_hits;
+    size_t keep_n, keep_mask, fit_list, buckets;
+    size_t trk_flag, hit_cnt, trk_idx, hit_pos;
+    size_t f_par, f_cov, f_chi2, f_xref, scan_part;
+    size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n;
 };
 
-constexpr int kStages = 11;
-const char* const kStageNames[kStages] = {"reset", "grid", "links", "clean", "row_scan", "starts",
-                                          "tracklets", "claim", "keepfit", "track_scan", "emit"};
+constexpr int kStages = 13;
+const char* const kStageNames[kStages] = {"reset", "grid",  "links", "clean", "row_scan",   "starts", "walk",
+                                          "tracklets", "claim", "keep", "fit", "track_scan", "emit"};
 
 struct GraphKey {
     const void* y = nullptr; const void* z = nullptr; const void* off = nullptr;
@@ -88,12 +91,13 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.n = n;
     L.R = (int64_t)n_tf * c->n_sectors * c->n_rows;
     L.n_bins = (int64_t)c->tuning.cap_mul * n + (int64_t)(c->tuning.cap_add + 1) * L.R;
+    // every start has a cleaned up-link and chains are vertex-disjoint: starts <= n/2;
+    // kept cluster sets are disjoint: fitted candidates <= n / min_track_hits
     L.cap_starts = n / 2 + 1;
-    const int mc = c->params.min_chain > 2 ? c->params.min_chain : 2;
-    L.cap_tl = n / mc + 1;
+    L.cap_fit = n / (c->params.min_track_hits > 1 ? c->params.min_track_hits : 1) + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
-    const size_t N = (size_t)n, R = (size_t)L.R, S = (size_t)L.cap_starts, T = (size_t)L.cap_tl;
+    const size_t N = (size_t)n, R = (size_t)L.R, S = (size_t)L.cap_starts, F = (size_t)L.cap_fit;
     L.row_lo = take(R * 8);
     L.row_bin = take(R * 8);
     L.row_nb = take(R * 8);
@@ -101,29 +105,44 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.row_sbase = take(R * 8);
     L.bin_start = take((size_t)L.n_bins * 4);
     L.bin_fill = take((size_t)L.n_bins * 4);
-    L.ys = take(N * 4);
-    L.zs = take(N * 4);
+    L.yz = take(N * 8);
     L.perm = take(N * 4);
-    L.up = take(N * 4);
-    L.dn = take(N * 4);
-    L.cup = take(N * 4);
-    L.cdn = take(N * 4);
-    L.W = take(N * 8);
-    L.start_row = take(S * 4);
-    L.start_idx = take(S * 4);
+    L.iperm = take(N * 4);
+    L.upk = take(N * 4);
+    L.dnk = take(N * 4);
+    L.cupk = take(N * 4);
+    L.cdnk = take(N * 4);
+    L.rank_at = take(N * 4);
+    L.W = take(N * 4);
+    L.st_row = take(S * 4);
+    L.st_k = take(S * 4);
+    L.st_rank = take(S * 4);
+    L.tl_len = take(S * 4);
+    L.order = take(S * 4);
     L.tl_n = take(S * 4);
-    L.tl_slot = take(S * 4);
+    L.tl_rlo = take(S * 2);
+    L.tl_rhi = take(S * 2);
+    L.tl_hits = take(S * (size_t)c->n_rows * 2);
+    L.keep_n = take(S * 4);
+    L.keep_mask = take(S * 4 * 8);
+    L.fit_list = take(F * 4);
+    L.buckets = take(sizeof(Buckets));
     L.trk_flag = take(S * 4);
     L.hit_cnt = take(S * 4);
     L.trk_idx = take(S * 8);
     L.hit_pos = take(S * 8);
-    L.tl_hits = take(T * (size_t)c->n_rows * 2);
-    L.f_par = take(T * 5 * 8);
-    L.f_cov = take(T * 15 * 8);
-    L.f_chi2 = take(T * 8);
-    L.f_xref = take(T * 8);
-    L.f_mask = take(T * 4 * 8);
+    L.f_par = take(F * 5 * 8);
+    L.f_cov = take(F * 15 * 8);
+    L.f_chi2 = take(F * 8);
+    L.f_xref = take(F * 8);
     L.scan_part = take((4 * kScanBlocks + 2) * 8);
+    L.d_up = take(N * 4);
+    L.d_dn = take(N * 4);
+    L.d_cup = take(N * 4);
+    L.d_cdn = take(N * 4);
+    L.d_start_row = take(S * 4);
+    L.d_start_idx = take(S * 4);
+    L.d_tl_n = take(S * 4);
     L.total = o;
     return L;
 }
@@ -234,30 +253,38 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.row_nb = (int2*)(a + L.row_nb);
     B.bin_start = (uint32_t*)(a + L.bin_start);
     B.bin_fill = (uint32_t*)(a + L.bin_fill);
-    B.ys = (float*)(a + L.ys);
-    B.zs = (float*)(a + L.zs);
+    B.yz = (float2*)(a + L.yz);
     B.perm = (uint32_t*)(a + L.perm);
-    B.up = (int32_t*)(a + L.up); B.dn = (int32_t*)(a + L.dn);
-    B.cup = (int32_t*)(a + L.cup); B.cdn = (int32_t*)(a + L.cdn);
+    B.iperm = (uint32_t*)(a + L.iperm);
+    B.upk = (int32_t*)(a + L.upk); B.dnk = (int32_t*)(a + L.dnk);
+    B.cupk = (int32_t*)(a + L.cupk); B.cdnk = (int32_t*)(a + L.cdnk);
     B.row_nstart = (int64_t*)(a + L.row_nstart);
     B.row_sbase = (int64_t*)(a + L.row_sbase);
-    B.start_row = (int32_t*)(a + L.start_row);
-    B.start_idx = (int32_t*)(a + L.start_idx);
-    B.tl_n = (int32_t*)(a + L.tl_n);
-    B.tl_slot = (int32_t*)(a + L.tl_slot);
-    B.trk_flag = (int32_t*)(a + L.trk_flag);
-    B.hit_cnt = (int32_t*)(a + L.hit_cnt);
-    B.trk_idx = (int64_t*)(a + L.trk_idx);
-    B.hit_pos = (int64_t*)(a + L.hit_pos);
+    B.rank_at = (int32_t*)(a + L.rank_at);
+    B.st_row = (int32_t*)(a + L.st_row);
+    B.st_k = (int32_t*)(a + L.st_k);
+    B.st_rank = (int32_t*)(a + L.st_rank);
     B.cap_starts = L.cap_starts;
+    B.tl_len = (int32_t*)(a + L.tl_len);
+    B.order = (int32_t*)(a + L.order);
+    B.tl_n = (int32_t*)(a + L.tl_n);
+    B.tl_rlo = (int16_t*)(a + L.tl_rlo);
+    B.tl_rhi = (int16_t*)(a + L.tl_rhi);
     B.tl_hits = (uint16_t*)(a + L.tl_hits);
+    B.keep_n = (int32_t*)(a + L.keep_n);
+    B.keep_mask = (uint64_t*)(a + L.keep_mask);
+    B.fit_list = (int32_t*)(a + L.fit_list);
+    B.bk = (Buckets*)(a + L.buckets);
     B.f_par = (double*)(a + L.f_par);
     B.f_cov = (double*)(a + L.f_cov);
     B.f_chi2 = (double*)(a + L.f_chi2);
     B.f_xref = (double*)(a + L.f_xref);
-    B.f_mask = (uint64_t*)(a + L.f_mask);
-    B.cap_tl = (int32_t)L.cap_tl;
-    B.W = (unsigned long long*)(a + L.W);
+    B.cap_fit = (int32_t)L.cap_fit;
+    B.trk_flag = (int32_t*)(a + L.trk_flag);
+    B.hit_cnt = (int32_t*)(a + L.hit_cnt);
+    B.trk_idx = (int64_t*)(a + L.trk_idx);
+    B.hit_pos = (int64_t*)(a + L.hit_pos);
+    B.W = (uint32_t*)(a + L.W);
     B.scan_part = (int64_t*)(a + L.scan_part);
     B.ctr = c->d_ctr;
     B.cap_tracks = o->cap_tracks; B.cap_hits = o->cap_hits;
@@ -265,6 +292,11 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.o_par = o->params; B.o_cov = o->cov; B.o_xref = o->x_ref; B.o_chi2 = o->chi2;
     B.o_ndf = o->ndf; B.o_nhits_trk = o->nhits; B.o_sector = o->sector; B.o_tf = o->tf;
     B.o_hit_off = o->hit_off; B.o_hit_ids = o->hit_ids; B.o_cluster_track = o->cluster_track;
+    B.d_up = (int32_t*)(a + L.d_up); B.d_dn = (int32_t*)(a + L.d_dn);
+    B.d_cup = (int32_t*)(a + L.d_cup); B.d_cdn = (int32_t*)(a + L.d_cdn);
+    B.d_start_row = (int32_t*)(a + L.d_start_row);
+    B.d_start_idx = (int32_t*)(a + L.d_start_idx);
+    B.d_tl_n = (int32_t*)(a + L.d_tl_n);
     return B;
 }
 
@@ -286,9 +318,11 @@ void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t
     mark(); launch_clean(B, P, 0, R, LC, s);
     mark(); launch_row_scan(B, 0, R, s);
     mark(); launch_starts(B, P, 0, R, LC, s);
+    mark(); launch_walk(B, P, LC, s);
     mark(); launch_tracklets(B, P, LC, s);
     mark(); launch_claim(B, P, LC, s);
-    mark(); launch_keepfit(B, P, LC, s);
+    mark(); launch_keep(B, P, LC, s);
+    mark(); launch_fit(B, P, LC, s);
     mark(); launch_track_scan(B, s);
     mark(); launch_emit(B, P, LC, s);
     mark();
@@ -425,9 +459,11 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
             launch_clean(B, P, g0, g1, LC, s);
             launch_row_scan(B, g0, g1, s);
             launch_starts(B, P, g0, g1, LC, s);
+            launch_walk(B, P, LC, s);
             launch_tracklets(B, P, LC, s);
             launch_claim(B, P, LC, s);
-            launch_keepfit(B, P, LC, s);
+            launch_keep(B, P, LC, s);
+            launch_fit(B, P, LC, s);
             launch_track_scan(B, s);
             launch_emit(B, P, LC, s);
         }
@@ -459,6 +495,7 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
         // timed calls run the same launch sequence eagerly on the caller's stream, with an
         // event between stages (event timing is not available inside graphs here)
         enqueue_batch(c, B, (hipStream_t)stream, c->ev);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "kernel launch");
         c->timed_last = true;
         c->last = B;
         c->have_last = true;
@@ -471,8 +508,14 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
         if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(c, e, "hipStreamBeginCapture");
         enqueue_batch(c, B, c->cap_stream, nullptr);
+        const hipError_t le = hipGetLastError();
         if ((e = hipStreamEndCapture(c->cap_stream, &c->graph)) != hipSuccess)
             return hip_fail(c, e, "hipStreamEndCapture");
+        if (le != hipSuccess) {
+            (void)hipGraphDestroy(c->graph);
+            c->graph = nullptr;
+            return hip_fail(c, le, "kernel launch during capture");
+        }
         if ((e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0)) != hipSuccess) {
             (void)hipGraphDestroy(c->graph);
             c->graph = nullptr;
@@ -506,20 +549,25 @@ tpcsf_status tpcsf_sync(tpcsf_ctx* c, void* stream)
     return TPCSF_OK;
 }
 
-tpcsf_status tpcsf_debug(const tpcsf_ctx* c, tpcsf_debug_view* v)
+tpcsf_status tpcsf_debug(tpcsf_ctx* c, tpcsf_debug_view* v)
 {
     if (!c || !v || !c->have_last) return TPCSF_E_INVALID;
     const Batch& B = c->last;
+    // the working arrays are in sorted (bin) order; convert to input order on request
+    hipError_t e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    launch_debug_views(B, dev_params(c), launch_cfg(c), c->cap_stream);
+    if ((e = hipStreamSynchronize(c->cap_stream)) != hipSuccess) return hip_fail(c, e, "debug views");
     v->row_lo = (const float*)B.row_lo;
     v->row_bin = (const float*)B.row_bin;
     v->row_nb = (const int32_t*)B.row_nb;
     v->bin_start = B.bin_start;
     v->perm = B.perm;
-    v->up = B.up; v->dn = B.dn; v->cup = B.cup; v->cdn = B.cdn;
+    v->up = B.d_up; v->dn = B.d_dn; v->cup = B.d_cup; v->cdn = B.d_cdn;
     v->n_starts = &c->d_ctr->start_base;
-    v->start_row = B.start_row;
-    v->start_idx = B.start_idx;
-    v->tl_nhits = B.tl_n;
+    v->start_row = B.d_start_row;
+    v->start_idx = B.d_start_idx;
+    v->tl_nhits = B.d_tl_n;
     return TPCSF_OK;
 }
 

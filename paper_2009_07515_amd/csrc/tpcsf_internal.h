@@ -35,13 +35,28 @@ struct Counters {
     int64_t rank_lo, rank_hi;       // rank range of the starts of the current launch set
     int64_t track_base;             // tracks emitted so far
     int64_t hit_base;               // hits emitted so far
-    int32_t tl_count;               // tracklet slots taken
+    int32_t n_order;                // tracklets to build (chains of >= min_chain)
+    int32_t n_fit;                  // tracks to fit (>= min_track_hits kept)
     int32_t queue;                  // tracklet work-queue head
     int32_t err;                    // error bits
-    int32_t pad;
+};
+
+// Length buckets used to order variable-length work (longest first): histogram, fill
+// counters and offsets, one set for chains and one for kept cluster counts.
+constexpr int kBuckets = kMaxRows + 1;
+struct Buckets {
+    int32_t hist[2][kBuckets];
+    int32_t fill[2][kBuckets];
+    int32_t off[2][kBuckets];
 };
 
 // Device pointers of one batch: inputs, arena and outputs.
+//
+// Working space.  After the grid stage every per-cluster array is indexed by the
+// cluster's position in its row's sorted (bin) order, at row_first + k; `perm` maps a
+// sorted position to the in-row index of the input, `iperm` the other way.  The method's
+// tie-breaks and ranks are still taken on in-row indices.  Starts are processed in
+// (row, sorted position) order ("p" below) for locality; each carries its rank.
 struct Batch {
     // inputs
     const float* y;
@@ -55,36 +70,46 @@ struct Batch {
     int2* row_nb;                   // [R] ny, nz
     uint32_t* bin_start;            // [cap_mul*N + (cap_add+1)*R]
     uint32_t* bin_fill;             // same size
-    float* ys;                      // [N] sorted y
-    float* zs;                      // [N] sorted z
-    uint32_t* perm;                 // [N] in-row index of sorted position
-    // links
-    int32_t* up; int32_t* dn;       // [N] raw
-    int32_t* cup; int32_t* cdn;     // [N] cleaned
+    float2* yz;                     // [N] sorted (y, z)
+    uint32_t* perm;                 // [N] sorted position -> in-row index
+    uint32_t* iperm;                // [N] in-row index -> sorted position
+    // links, sorted positions
+    int32_t* upk; int32_t* dnk;     // [N] raw
+    int32_t* cupk; int32_t* cdnk;   // [N] cleaned
     int64_t* row_nstart;            // [R] starts per row
     int64_t* row_sbase;             // [R] exclusive prefix (rank of the row's first start)
-    // starts and tracklets (rank indexed)
-    int32_t* start_row;             // [cap_starts]
-    int32_t* start_idx;             // [cap_starts]
-    int32_t* tl_n;                  // [cap_starts] tracklet clusters, 0 = none
-    int32_t* tl_slot;               // [cap_starts]
-    int32_t* trk_flag;              // [cap_starts] 1 = accepted and fitted
-    int32_t* hit_cnt;               // [cap_starts] kept clusters of accepted tracks
-    int64_t* trk_idx;               // [cap_starts] output track index
-    int64_t* hit_pos;               // [cap_starts] output hit offset
+    int32_t* rank_at;               // [N] scratch: rank of the start at a sorted position
+    // starts in processing order p
+    int32_t* st_row;                // [cap_starts] global row
+    int32_t* st_k;                  // [cap_starts] sorted position
+    int32_t* st_rank;               // [cap_starts] rank
     int64_t cap_starts;
-    // tracklet slots
-    uint16_t* tl_hits;              // [cap_tl][n_rows] in-row index per row
-    double* f_par;                  // [cap_tl][5]
-    double* f_cov;                  // [cap_tl][15]
-    double* f_chi2;                 // [cap_tl]
-    double* f_xref;                 // [cap_tl]
-    uint64_t* f_mask;               // [cap_tl][4] kept rows
-    int32_t cap_tl;
-    // selection
-    unsigned long long* W;          // [N]
+    // tracklets (p indexed); the hit table is row-major: H[r * cap_starts + p]
+    int32_t* tl_len;                // chain length
+    int32_t* order;                 // [cap_starts] tracklets to build, longest chain first
+    int32_t* tl_n;                  // clusters, 0 = none
+    int16_t* tl_rlo;                // first row holding a cluster
+    int16_t* tl_rhi;                // last row holding a cluster
+    uint16_t* tl_hits;              // sorted position per row, kNoHit if none
+    // keep and final fit: candidates listed densely, most kept clusters first
+    int32_t* keep_n;                // [cap_starts] (p indexed) kept clusters, 0 = not a track
+    uint64_t* keep_mask;            // [cap_starts][4] (p indexed) kept rows
+    int32_t* fit_list;              // [cap_fit] p of every candidate
+    double* f_par;                  // [cap_fit][5]
+    double* f_cov;                  // [cap_fit][15]
+    double* f_chi2;                 // [cap_fit]
+    double* f_xref;                 // [cap_fit]
+    int32_t cap_fit;
+    Buckets* bk;
+    // rank indexed
+    int32_t* trk_flag;              // 1 = accepted and fitted
+    int32_t* hit_cnt;               // kept clusters of accepted tracks
+    int64_t* trk_idx;               // output track index
+    int64_t* hit_pos;               // output hit offset
+    // selection (sorted positions)
+    uint32_t* W;                    // [N]
     // scan scratch
-    int64_t* scan_part;             // [kScanBlocks * 2]
+    int64_t* scan_part;             // [4 * kScanBlocks + 2]
     Counters* ctr;
     // outputs
     int64_t cap_tracks, cap_hits;
@@ -92,6 +117,9 @@ struct Batch {
     double* o_par; double* o_cov; double* o_xref; double* o_chi2;
     int32_t* o_ndf; int32_t* o_nhits_trk; int32_t* o_sector; int32_t* o_tf;
     int64_t* o_hit_off; int32_t* o_hit_ids; int32_t* o_cluster_track;
+    // verification views in input order (filled only by launch_debug_views)
+    int32_t* d_up; int32_t* d_dn; int32_t* d_cup; int32_t* d_cdn;   // [N]
+    int32_t* d_start_row; int32_t* d_start_idx; int32_t* d_tl_n;     // [cap_starts] by rank
 };
 
 struct LaunchCfg {
@@ -108,10 +136,13 @@ void launch_links(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, co
 void launch_clean(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
 void launch_row_scan(const Batch& b, int64_t g0, int64_t g1, hipStream_t s);
 void launch_starts(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
+void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_claim(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
-void launch_keepfit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
+void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
+void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_track_scan(const Batch& b, hipStream_t s);
 void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
+void launch_debug_views(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 
 }  // namespace tpcsf

@@ -104,6 +104,8 @@ __device__ __forceinline__ int bin_of(float v, float lo, float b, int nb)
 // ------------------------------------------------------------------------------------
 __global__ void k_reset(Batch B)
 {
+    int32_t* bk = &B.bk->hist[0][0];
+    for (int i = threadIdx.x; i < 4 * kBuckets; i += blockDim.x) bk[i] = 0;   // hist and fill
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         Counters* c = B.ctr;
         c->start_base = 0;
@@ -111,7 +113,8 @@ __global__ void k_reset(Batch B)
         c->rank_hi = 0;
         c->track_base = 0;
         c->hit_base = 0;
-        c->tl_count = 0;
+        c->n_order = 0;
+        c->n_fit = 0;
         c->queue = 0;
         *B.o_ntracks = 0;
         *B.o_nhits = 0;
@@ -125,7 +128,8 @@ __global__ void k_reset(Batch B)
 // (once nz == 1 the y bin) doubles.  Clusters are ordered by bin iz*ny + iy, ties by
 // in-row index (stable counting sort: histogram, scan, then placement chunk by chunk in
 // index order, each chunk ranked inside the wave by a ballot match on the bin key).
-// The same pass clears the selection weights and the cluster->track map of the row.
+// Writes the sorted (y, z) pairs, perm (sorted -> in-row index) and its inverse.  The
+// same pass clears the selection weights and the cluster->track map of the row.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0, int64_t g1)
 {
@@ -143,7 +147,7 @@ __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0,
             bad |= !(fabsf(y) <= 1.0e5f) || !(fabsf(z) <= 1.0e5f);
             ylo = fminf(ylo, y); yhi = fmaxf(yhi, y);
             zlo = fminf(zlo, z); zhi = fmaxf(zhi, z);
-            B.W[base + i] = 0ull;
+            B.W[base + i] = 0u;
             B.o_cluster_track[base + i] = -1;
         }
 #pragma unroll
@@ -216,9 +220,9 @@ __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0,
             old = __shfl(old, leader, 64);
             if (valid) {
                 const uint32_t pos = ld_rlx(bs + bin) + old + (uint32_t)rank;
-                B.ys[base + pos] = y;
-                B.zs[base + pos] = z;
+                B.yz[base + pos] = make_float2(y, z);
                 B.perm[base + pos] = (uint32_t)i;
+                B.iperm[base + i] = pos;
             }
         }
     }
@@ -231,11 +235,16 @@ __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0,
 // |y_c - y_h| <= win_y and |z_c - z_h| <= win_z; the grid bins visited cover the window
 // widened by a few ulps, and every candidate is then tested exactly.  The pair with the
 // least slope change D wins if D <= kink_max; ties go to the smaller u, then the
-// smaller d (in-row indices).
+// smaller d (in-row indices).  Results are stored as sorted positions.
+//
+// The qualifying candidates of each side are first gathered into registers (slopes
+// computed once per candidate), then all pairs are scored from registers.  A lane with
+// more than kMaxCand candidates on a side scores every pair straight from memory.
 // ------------------------------------------------------------------------------------
 struct RowView {
     int64_t first;            // first cluster of the row
     float ylo, zlo, by, bz;
+    float iby, ibz;           // reciprocals, for conservative window bins only
     int ny, nz;
     const uint32_t* bs;       // bin_start of the row
 };
@@ -247,23 +256,70 @@ __device__ __forceinline__ RowView row_view(const Batch& B, const DevParams& P, 
     const float2 lo = B.row_lo[g], bn = B.row_bin[g];
     const int2 nb = B.row_nb[g];
     v.ylo = lo.x; v.zlo = lo.y; v.by = bn.x; v.bz = bn.y; v.ny = nb.x; v.nz = nb.y;
+    v.iby = 1.0f / bn.x;
+    v.ibz = 1.0f / bn.y;
     v.bs = B.bin_start + bin_base(P, v.first, g);
     return v;
 }
 
-__device__ __forceinline__ void window_bins(const RowView& v, float yq, float zq, float wy, float wz,
-                                            int& iy0, int& iy1, int& iz0, int& iz1)
+// Bin index range of [q - w, q + w] (clamped).  Visiting a superset of the bins suffices:
+// every candidate is tested exactly.  The window is widened by a relative margin that
+// covers the rounding of |c - q|, of q -+ w and of the reciprocal bin size.
+__device__ __forceinline__ void bin_span(float q, float w, float lo, float ib, int nb, int& i0, int& i1)
 {
-    // widen by a relative margin that exceeds the rounding of |c - q| and of q -+ w
-    const float ey = (fabsf(yq) + wy + 1.0f) * 4.0e-6f;
-    const float ez = (fabsf(zq) + wz + 1.0f) * 4.0e-6f;
-    iy0 = bin_of(yq - (wy + ey), v.ylo, v.by, v.ny);
-    iy1 = bin_of(yq + (wy + ey), v.ylo, v.by, v.ny);
-    iz0 = bin_of(zq - (wz + ez), v.zlo, v.bz, v.nz);
-    iz1 = bin_of(zq + (wz + ez), v.zlo, v.bz, v.nz);
+    const float e = (fabsf(q) + fabsf(lo) + w + 1.0f) * 8.0e-6f;
+    const float f0 = (q - (w + e) - lo) * ib;
+    const float f1 = (q + (w + e) - lo) * ib;
+    i0 = (f0 < (float)nb) ? (int)fmaxf(f0, 0.0f) : nb - 1;
+    i1 = (f1 < (float)nb) ? (int)fmaxf(f1, 0.0f) : nb - 1;
 }
 
-__global__ void __launch_bounds__(1024) k_links(Batch B, DevParams P, int64_t g0, int64_t g1)
+constexpr int kMaxCand = 6;
+
+struct LinkBest {
+    float D;
+    int ku, kd;      // sorted positions
+    int uo, dd;      // in-row indices (tie-breaks)
+};
+
+__device__ __forceinline__ void link_consider(LinkBest& b, float Dk, int ku, int kd, int uo, int dd, float kmax)
+{
+    if (!(Dk <= kmax)) return;
+    const bool better = b.ku < 0 || Dk < b.D || (Dk == b.D && (uo < b.uo || (uo == b.uo && dd < b.dd)));
+    if (better) { b.D = Dk; b.ku = ku; b.kd = kd; b.uo = uo; b.dd = dd; }
+}
+
+// Qualifying candidates of one neighbour row for the cluster (yh, zh): skips the first
+// `skip`, keeps up to kMaxCand (slope, sorted position, in-row index), returns how many
+// qualify in all.  sgn = +1 for the row above (slope (c - h)/dx), -1 below ((h - c)/dx).
+__device__ __forceinline__ int gather_cands(const RowView& V, const float2* yz, const uint32_t* perm,
+                                            int iy0, int iy1, int iz0, int iz1, float yh, float zh,
+                                            float wy, float wz, float dx, bool above, int skip,
+                                            float* ty, float* tz, int* kk, int* oo)
+{
+#pragma clang fp contract(off)
+    int cnt = 0;
+    for (int iz = iz0; iz <= iz1; ++iz) {
+        const uint32_t ka = V.bs[iz * V.ny + iy0], kb = V.bs[iz * V.ny + iy1 + 1];
+        for (uint32_t q = ka; q < kb; ++q) {
+            const float2 c = yz[q];
+            if (!(fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz)) continue;
+            const int slot = cnt - skip;
+            if (slot >= 0 && slot < kMaxCand) {
+                const float sy = above ? (c.x - yh) / dx : (yh - c.x) / dx;
+                const float sz = above ? (c.y - zh) / dx : (zh - c.y) / dx;
+                const int o = (int)perm[q];
+#pragma unroll
+                for (int j = 0; j < kMaxCand; ++j)
+                    if (j == slot) { ty[j] = sy; tz[j] = sz; kk[j] = (int)q; oo[j] = o; }
+            }
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+__global__ void __launch_bounds__(256) k_links(Batch B, DevParams P, int64_t g0, int64_t g1)
 {
 #pragma clang fp contract(off)
     const int nr = P.n_rows;
@@ -273,55 +329,63 @@ __global__ void __launch_bounds__(1024) k_links(Batch B, DevParams P, int64_t g0
         const int n = (int)(B.off[g + 1] - base);
         if (r == 0 || r == nr - 1) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                B.up[base + i] = -1;
-                B.dn[base + i] = -1;
+                B.upk[base + i] = -1;
+                B.dnk[base + i] = -1;
             }
             continue;
         }
         const RowView U = row_view(B, P, g + 1);
         const RowView D = row_view(B, P, g - 1);
+        const float2* yzu = B.yz + U.first;
+        const float2* yzd = B.yz + D.first;
+        const uint32_t* pu = B.perm + U.first;
+        const uint32_t* pd = B.perm + D.first;
         const float dxu = P.rx[r + 1] - P.rx[r];
         const float dxd = P.rx[r] - P.rx[r - 1];
         const float wy = P.win_y, wz = P.win_z, kmax = P.kink_max;
         for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            const float yh = B.ys[base + k], zh = B.zs[base + k];
-            const int h = (int)B.perm[base + k];
+            const float2 h = B.yz[base + k];
+            const float yh = h.x, zh = h.y;
             int uy0, uy1, uz0, uz1, dy0, dy1, dz0, dz1;
-            window_bins(U, yh, zh, wy, wz, uy0, uy1, uz0, uz1);
-            window_bins(D, yh, zh, wy, wz, dy0, dy1, dz0, dz1);
-            float bD = 0.0f;
-            int bu = -1, bd = -1;
-            for (int iz = uz0; iz <= uz1; ++iz) {
-                const uint32_t ka = U.bs[iz * U.ny + uy0], kb = U.bs[iz * U.ny + uy1 + 1];
-                for (uint32_t ku = ka; ku < kb; ++ku) {
-                    const float yu = B.ys[U.first + ku], zu = B.zs[U.first + ku];
-                    if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
-                    const int u = (int)B.perm[U.first + ku];
-                    const float tuy = (yu - yh) / dxu;
-                    const float tuz = (zu - zh) / dxu;
-                    for (int jz = dz0; jz <= dz1; ++jz) {
-                        const uint32_t ma = D.bs[jz * D.ny + dy0], mb = D.bs[jz * D.ny + dy1 + 1];
-                        for (uint32_t kd = ma; kd < mb; ++kd) {
-                            const float yd = B.ys[D.first + kd], zd = B.zs[D.first + kd];
-                            if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
-                            const int d = (int)B.perm[D.first + kd];
-                            const float tdy = (yh - yd) / dxd;
-                            const float tdz = (zh - zd) / dxd;
-                            const float ay = tuy - tdy;
-                            const float az = tuz - tdz;
-                            const float sy = ay * ay;
-                            const float sz = az * az;
-                            const float Dk = sy + sz;
-                            if (!(Dk <= kmax)) continue;
-                            const bool better = bu < 0 || Dk < bD ||
-                                                (Dk == bD && (u < bu || (u == bu && d < bd)));
-                            if (better) { bD = Dk; bu = u; bd = d; }
+            bin_span(yh, wy, U.ylo, U.iby, U.ny, uy0, uy1);
+            bin_span(zh, wz, U.zlo, U.ibz, U.nz, uz0, uz1);
+            bin_span(yh, wy, D.ylo, D.iby, D.ny, dy0, dy1);
+            bin_span(zh, wz, D.zlo, D.ibz, D.nz, dz0, dz1);
+            float uty[kMaxCand], utz[kMaxCand], dty[kMaxCand], dtz[kMaxCand];
+            int uk[kMaxCand], uo[kMaxCand], dk[kMaxCand], dd[kMaxCand];
+            LinkBest best = {0.0f, -1, -1, -1, -1};
+            // all (u, d) pairs, kMaxCand x kMaxCand at a time from registers
+            for (int us = 0;; us += kMaxCand) {
+                const int nu_all = gather_cands(U, yzu, pu, uy0, uy1, uz0, uz1, yh, zh, wy, wz, dxu, true, us,
+                                                uty, utz, uk, uo);
+                const int nu = min(kMaxCand, nu_all - us);
+                if (nu <= 0) break;
+                for (int ds = 0;; ds += kMaxCand) {
+                    const int nd_all = gather_cands(D, yzd, pd, dy0, dy1, dz0, dz1, yh, zh, wy, wz, dxd, false, ds,
+                                                    dty, dtz, dk, dd);
+                    const int nd = min(kMaxCand, nd_all - ds);
+                    if (nd <= 0) break;
+#pragma unroll
+                    for (int i = 0; i < kMaxCand; ++i) {
+                        if (i < nu) {
+#pragma unroll
+                            for (int j = 0; j < kMaxCand; ++j) {
+                                if (j < nd) {
+                                    const float ay = uty[i] - dty[j];
+                                    const float az = utz[i] - dtz[j];
+                                    const float sy = ay * ay;
+                                    const float sz = az * az;
+                                    link_consider(best, sy + sz, uk[i], dk[j], uo[i], dd[j], kmax);
+                                }
+                            }
                         }
                     }
+                    if (ds + kMaxCand >= nd_all) break;
                 }
+                if (us + kMaxCand >= nu_all) break;
             }
-            B.up[base + h] = bu;
-            B.dn[base + h] = bd;
+            B.upk[base + k] = best.ku;
+            B.dnk[base + k] = best.kd;
         }
     }
 }
@@ -341,12 +405,12 @@ __global__ void __launch_bounds__(1024) k_clean(Batch B, DevParams P, int64_t g0
         const int64_t fu = (r + 1 < nr) ? B.off[g + 1] : 0;
         const int64_t fd = (r > 0) ? B.off[g - 1] : 0;
         int cnt = 0;
-        for (int h = threadIdx.x; h < n; h += blockDim.x) {
-            const int u = B.up[base + h], d = B.dn[base + h];
-            const int cu = (u >= 0 && B.dn[fu + u] == h) ? u : -1;
-            const int cd = (d >= 0 && B.up[fd + d] == h) ? d : -1;
-            B.cup[base + h] = cu;
-            B.cdn[base + h] = cd;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int u = B.upk[base + k], d = B.dnk[base + k];
+            const int cu = (u >= 0 && B.dnk[fu + u] == k) ? u : -1;
+            const int cd = (d >= 0 && B.upk[fd + d] == k) ? d : -1;
+            B.cupk[base + k] = cu;
+            B.cdnk[base + k] = cd;
             cnt += (cu >= 0 && cd < 0);
         }
         int total;
@@ -356,8 +420,9 @@ __global__ void __launch_bounds__(1024) k_clean(Batch B, DevParams P, int64_t g0
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 4, starts: compaction of the chain bottoms in (row, in-row index) order at the
-// row's scanned base; the position in this list is the start's rank.
+// Stage 4, starts.  A start's rank is its position among the chain bottoms in
+// (row, in-row index) order, from the row's scanned base.  The starts are also listed in
+// (row, sorted position) order, the order in which they are processed.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_starts(Batch B, DevParams P, int64_t g0, int64_t g1)
 {
@@ -365,17 +430,32 @@ __global__ void __launch_bounds__(1024) k_starts(Batch B, DevParams P, int64_t g
     for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
-        int64_t sb = B.row_sbase[g];
+        const int64_t sb = B.row_sbase[g];
+        int64_t run = sb;
         for (int h0 = 0; h0 < n; h0 += blockDim.x) {
             const int h = h0 + threadIdx.x;
-            const int f = (h < n) && B.cup[base + h] >= 0 && B.cdn[base + h] < 0;
+            const int k = (h < n) ? (int)B.iperm[base + h] : 0;
+            const int f = (h < n) && B.cupk[base + k] >= 0 && B.cdnk[base + k] < 0;
+            int total;
+            const int pos = block_excl_scan(f, &total, lds);
+            if (f) B.rank_at[base + k] = (int32_t)(run + pos);
+            run += total;
+        }
+        __threadfence_block();
+        __syncthreads();
+        run = sb;
+        for (int k0 = 0; k0 < n; k0 += blockDim.x) {
+            const int k = k0 + threadIdx.x;
+            const int f = (k < n) && B.cupk[base + k] >= 0 && B.cdnk[base + k] < 0;
             int total;
             const int pos = block_excl_scan(f, &total, lds);
             if (f) {
-                B.start_row[sb + pos] = (int32_t)g;
-                B.start_idx[sb + pos] = h;
+                const int64_t p = run + pos;
+                B.st_row[p] = (int32_t)g;
+                B.st_k[p] = k;
+                B.st_rank[p] = B.rank_at[base + k];
             }
-            sb += total;
+            run += total;
         }
     }
 }
@@ -688,7 +768,8 @@ __device__ bool trk_seed(Trk& t, const double* x, const double* y, const double*
     return true;
 }
 
-// Least-chi2 cluster of row g inside the follow window; -1 if none.
+// Least-chi2 cluster of row g inside the follow window: its sorted position, -1 if none.
+// Equal chi2: the smaller in-row index.
 __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const Trk& t, double& best_chi2)
 {
     const int64_t first = B.off[g];
@@ -702,23 +783,24 @@ __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const T
     if (wz > (double)P.win_z) wz = (double)P.win_z;
     const double yp = t.p[0], zp = t.p[1];
     if (!(fabs(yp) < 1.0e6) || !(fabs(zp) < 1.0e6)) return -1;
-    const double my = (fabs(yp) + wy + 1.0) * 1.0e-5, mz = (fabs(zp) + wz + 1.0) * 1.0e-5;
-    const int iy0 = bin_of((float)(yp - wy - my), v.ylo, v.by, v.ny);
-    const int iy1 = bin_of((float)(yp + wy + my), v.ylo, v.by, v.ny);
-    const int iz0 = bin_of((float)(zp - wz - mz), v.zlo, v.bz, v.nz);
-    const int iz1 = bin_of((float)(zp + wz + mz), v.zlo, v.bz, v.nz);
+    int iy0, iy1, iz0, iz1;
+    bin_span((float)yp, (float)wy, v.ylo, v.iby, v.ny, iy0, iy1);
+    bin_span((float)zp, (float)wz, v.zlo, v.ibz, v.nz, iz0, iz1);
     const double idet = 1.0 / (s00 * s11 - s01 * s01);
+    const float2* yz = B.yz + first;
     int best = -1;
     for (int iz = iz0; iz <= iz1; ++iz) {
         const uint32_t ka = v.bs[iz * v.ny + iy0], kb = v.bs[iz * v.ny + iy1 + 1];
         for (uint32_t k = ka; k < kb; ++k) {
-            const double dy = (double)B.ys[first + k] - yp;
-            const double dz = (double)B.zs[first + k] - zp;
+            const float2 c = yz[k];
+            const double dy = (double)c.x - yp;
+            const double dz = (double)c.y - zp;
             if (!(fabs(dy) <= wy) || !(fabs(dz) <= wz)) continue;
             const double chi2 = (dy * dy * s11 - 2.0 * dy * dz * s01 + dz * dz * s00) * idet;
-            const int c = (int)B.perm[first + k];
-            if (best < 0 || chi2 < best_chi2 || (chi2 == best_chi2 && c < best)) {
-                best = c;
+            bool take = best < 0 || chi2 < best_chi2;
+            if (!take && chi2 == best_chi2) take = B.perm[first + k] < B.perm[first + best];
+            if (take) {
+                best = (int)k;
                 best_chi2 = chi2;
             }
         }
@@ -726,129 +808,178 @@ __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const T
     return best;
 }
 
+// ------------------------------------------------------------------------------------
+// Length buckets: variable-length work is processed longest first, so that the lanes of
+// a wave carry work of similar length.  Processing order never changes a result.
+// ------------------------------------------------------------------------------------
+__global__ void k_bucket_scan(Batch B, int which, int n_buckets)
+{
+    // one block: offsets for descending length, total, then clear the histogram and fill
+    __shared__ int32_t tot;
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int L = n_buckets - 1; L >= 0; --L) {
+            B.bk->off[which][L] = run;
+            run += B.bk->hist[which][L];
+        }
+        tot = run;
+        if (which == 0) B.ctr->n_order = run; else B.ctr->n_fit = run;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) {
+        B.bk->hist[which][i] = 0;
+        B.bk->fill[which][i] = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Stage 5a, chains: walk the cleaned up-links from every start (one lane each), record
+// the chain in the tracklet's hit table and its length; chains of >= min_chain clusters
+// become tracklets and are listed longest first.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t* hit_slot(const Batch& B, int r, int64_t p)
+{
+    return B.tl_hits + (int64_t)r * B.cap_starts + p;
+}
+
+__global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
+{
+    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
+    const int nr = P.n_rows;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
+        const int64_t g = B.st_row[p];
+        const int r0 = (int)(g % nr);
+        const int64_t gs = g - r0;
+        int L = 0;
+        for (int r = r0, k = B.st_k[p]; r < nr && k >= 0; ++r) {
+            *hit_slot(B, r, p) = (uint16_t)k;
+            ++L;
+            k = B.cupk[B.off[gs + r] + k];
+        }
+        B.tl_len[p] = L;
+        B.tl_n[p] = 0;
+        if (L >= P.min_chain) atomicAdd(&B.bk->hist[0][L], 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_walk_list(Batch B, DevParams P)
+{
+    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
+        const int L = B.tl_len[p];
+        if (L < P.min_chain) continue;
+        B.order[B.bk->off[0][L] + atomicAdd(&B.bk->fill[0][L], 1)] = (int32_t)p;
+    }
+}
+
+// Follow from r_from toward r_to (exclusive) in steps of `step`; every visited row's
+// table entry is written (cluster or kNoHit).  Returns the clusters added; *last_hit is
+// the last row that received one (unchanged if none).
 __device__ int follow(const Batch& B, const DevParams& P, Trk& t, int64_t gs, int r_from, int r_to, int step,
-                      uint16_t* H)
+                      int64_t p, int* last_hit)
 {
     int misses = 0, added = 0;
     for (int r = r_from; r != r_to; r += step) {
         if (!trk_propagate(t, (double)P.rx[r], P)) break;
         double chi2;
-        const int c = search_row(B, P, gs + r, t, chi2);
-        if (c >= 0 && chi2 <= P.chi2_max) {
-            const int64_t gi = B.off[gs + r] + c;
-            trk_update(t, (double)B.y[gi], (double)B.z[gi], P);
-            H[r] = (uint16_t)c;
+        const int k = search_row(B, P, gs + r, t, chi2);
+        if (k >= 0 && chi2 <= P.chi2_max) {
+            const float2 c = B.yz[B.off[gs + r] + k];
+            trk_update(t, (double)c.x, (double)c.y, P);
+            *hit_slot(B, r, p) = (uint16_t)k;
+            *last_hit = r;
             misses = 0;
             ++added;
-        } else if (++misses > P.max_miss) {
-            break;
+        } else {
+            *hit_slot(B, r, p) = kNoHit;
+            if (++misses > P.max_miss) break;
         }
     }
     return added;
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 5, tracklets: one lane per chain bottom, pulled from a persistent work queue.
-// Chain along the cleaned up-links (>= min_chain clusters), three-point seed, Kalman
-// update over the chain, follow outward, reset C to C0 keeping p and refit inward over
-// all clusters so far, follow inward.  The clusters are recorded per row in a slot.
+// Stage 5b, tracklets: one lane per chain, pulled from a persistent work queue (longest
+// chains first).  Three-point seed, Kalman update over the chain, follow outward, reset
+// C to C0 keeping p and refit inward over all clusters so far, follow inward.  Clusters
+// are recorded per row (sorted positions); rows [rlo, rhi] are all written.
 // ------------------------------------------------------------------------------------
-__device__ void build_tracklet(const Batch& B, const DevParams& P, int64_t t)
+__device__ void build_tracklet(const Batch& B, const DevParams& P, int64_t p)
 {
     const int nr = P.n_rows;
-    const int64_t g = B.start_row[t];
-    const int i0 = B.start_idx[t];
+    const int64_t g = B.st_row[p];
     const int r0 = (int)(g % nr);
     const int64_t gs = g - r0;
-    int L = 0;
-    for (int r = r0, c = i0; r < nr && c >= 0; ++r) {
-        ++L;
-        c = B.cup[B.off[gs + r] + c];
-    }
-    if (L < P.min_chain) {
-        B.tl_n[t] = 0;
-        return;
-    }
-    const int slot = atomicAdd(&B.ctr->tl_count, 1);
-    if (slot >= B.cap_tl) {
-        atomicOr(&B.ctr->err, kErrTrackletCap);
-        B.tl_n[t] = 0;
-        return;
-    }
-    B.tl_slot[t] = slot;
-    uint16_t* H = B.tl_hits + (int64_t)slot * nr;
-    for (int r = 0; r < nr; ++r) H[r] = kNoHit;
-    // seed clusters: first, middle and last of the chain (distinct rows for L >= 3)
+    const int L = B.tl_len[p];
+    // seed clusters: first, middle and last of the chain
     const int rs[3] = {r0, r0 + (L - 1) / 2, r0 + L - 1};
     double sx[3], sy[3], sz[3];
-    for (int r = r0, c = i0; r < r0 + L; ++r) {
-        H[r] = (uint16_t)c;
-        const int64_t gi = B.off[gs + r] + c;
-        for (int q = 0; q < 3; ++q)
-            if (r == rs[q]) {
-                sx[q] = (double)P.rx[r];
-                sy[q] = (double)B.y[gi];
-                sz[q] = (double)B.z[gi];
-            }
-        c = B.cup[gi];
+    for (int q = 0; q < 3; ++q) {
+        const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
+        sx[q] = (double)P.rx[rs[q]];
+        sy[q] = (double)c.x;
+        sz[q] = (double)c.y;
     }
     Trk tr;
     int n = 0;
+    int rlo = r0, rhi = r0 + L - 1;
     bool ok = trk_seed(tr, sx, sy, sz, P);
     if (ok) {
         trk_reset_cov(tr, P);
         for (int r = r0; r < r0 + L; ++r) {
             if (r > r0 && !trk_propagate(tr, (double)P.rx[r], P)) { ok = false; break; }
-            const int64_t gi = B.off[gs + r] + H[r];
-            trk_update(tr, (double)B.y[gi], (double)B.z[gi], P);
+            const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
+            trk_update(tr, (double)c.x, (double)c.y, P);
         }
     }
     if (ok) {
-        n = L + follow(B, P, tr, gs, r0 + L, nr, +1, H);
+        n = L + follow(B, P, tr, gs, r0 + L, nr, +1, p, &rhi);
         trk_reset_cov(tr, P);
-        for (int r = nr - 1; r >= r0; --r) {
-            if (H[r] == kNoHit) continue;
+        for (int r = rhi; r >= r0; --r) {
+            const uint16_t k = *hit_slot(B, r, p);
+            if (k == kNoHit) continue;
             if (!trk_propagate(tr, (double)P.rx[r], P)) { ok = false; break; }
-            const int64_t gi = B.off[gs + r] + H[r];
-            trk_update(tr, (double)B.y[gi], (double)B.z[gi], P);
+            const float2 c = B.yz[B.off[gs + r] + k];
+            trk_update(tr, (double)c.x, (double)c.y, P);
         }
     }
-    if (ok) {
-        n += follow(B, P, tr, gs, r0 - 1, -1, -1, H);
-    } else {
-        for (int r = 0; r < nr; ++r) H[r] = kNoHit;
-        n = 0;
-    }
-    B.tl_n[t] = n;
+    if (ok) n += follow(B, P, tr, gs, r0 - 1, -1, -1, p, &rlo);
+    B.tl_n[p] = ok ? n : 0;
+    B.tl_rlo[p] = (int16_t)rlo;
+    B.tl_rhi[p] = (int16_t)rhi;
 }
 
 __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int chunk)
 {
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
+    const int64_t hi = B.ctr->n_order;
     const int lane = lane_id();
     const int per_wave = 64 * chunk;
     for (;;) {
         int take = 0;
         if (lane == 0) take = atomicAdd(&B.ctr->queue, per_wave);
         take = __shfl(take, 0, 64);
-        const int64_t t0 = lo + take;
-        if (t0 >= hi) break;
+        if (take >= hi) break;
         for (int k = 0; k < chunk; ++k) {
-            const int64_t t = t0 + (int64_t)k * 64 + lane;
-            if (t < hi) build_tracklet(B, P, t);
+            const int64_t i = (int64_t)take + (int64_t)k * 64 + lane;
+            if (i < hi) build_tracklet(B, P, B.order[i]);
         }
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 6, selection.  w = (n << 32) | (2^32 - 1 - rank); every cluster ends with the
-// largest w of the tracklets that contain it (64-bit atomic max, order independent).
-// Tracklets shorter than min_track_hits can neither be accepted nor outweigh a longer
-// one, so they do not take part.  The same launch rewinds the tracklet work queue.
+// Stage 6, selection.  A tracklet's weight orders tracklets by (clusters, then smaller
+// rank); every cluster ends with the largest weight of the tracklets that contain it
+// (atomic max, order independent).  Weights are only ever compared within a sector, so
+// the rank counts from the sector's first start: w = (n << 24) | (2^24 - 1 - rank_s)
+// (n <= 255, rank_s < 2^24 since a sector holds < 2^24 starts).  Tracklets shorter than
+// min_track_hits can neither be accepted nor outweigh a longer one and do not take part.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long weight_of(int n, int64_t t)
+__device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P, int n, int64_t rank, int64_t gs)
 {
-    return ((unsigned long long)(uint32_t)n << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)t);
+    const int64_t rs = rank - B.row_sbase[gs];
+    return ((uint32_t)n << 24) | (0xFFFFFFu - (uint32_t)rs);
 }
 
 __global__ void __launch_bounds__(256) k_claim(Batch B, DevParams P)
@@ -856,152 +987,227 @@ __global__ void __launch_bounds__(256) k_claim(Batch B, DevParams P)
     const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     const int nr = P.n_rows;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < hi; t += stride) {
-        const int n = B.tl_n[t];
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctr->queue = 0;   // the tracklet queue is done
+    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
+        const int n = B.tl_n[p];
         if (n < P.min_track_hits) continue;
-        const unsigned long long w = weight_of(n, t);
-        const int64_t g = B.start_row[t];
+        const int64_t g = B.st_row[p];
         const int64_t gs = g - g % nr;
-        const uint16_t* H = B.tl_hits + (int64_t)B.tl_slot[t] * nr;
-        for (int r = 0; r < nr; ++r) {
-            const uint16_t c = H[r];
-            if (c != kNoHit) atomicMax(&B.W[B.off[gs + r] + c], w);
+        const uint32_t w = weight_of(B, P, n, B.st_rank[p], gs);
+        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
+        for (int r = rlo; r <= rhi; ++r) {
+            const uint16_t k = *hit_slot(B, r, p);
+            if (k != kNoHit) atomicMax(&B.W[B.off[gs + r] + k], w);
         }
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 7, keep + final fit.  A tracklet keeps the clusters that carry its own weight and
-// is a track if it keeps >= min_track_hits.  Final fit on the kept clusters (inner to
-// outer): three-point seed, C = C0, update outward; C = C0 keeping p, update inward.
-// Result at the innermost kept cluster; a failed fit drops the track.
+// Stage 7a, keep: a tracklet keeps the clusters that carry its own weight and is a track
+// candidate if it keeps >= min_track_hits; candidates are listed, most clusters first.
 // ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_keepfit(Batch B, DevParams P)
+__global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
 {
     const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     const int nr = P.n_rows;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctr->queue = 0;   // tracklet queue is done
-    for (int64_t t = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < hi; t += stride) {
-        B.trk_flag[t] = 0;
-        B.hit_cnt[t] = 0;
-        const int n = B.tl_n[t];
+    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
+        const int64_t rank = B.st_rank[p];
+        B.trk_flag[rank] = 0;
+        B.hit_cnt[rank] = 0;
+        B.keep_n[p] = 0;
+        const int n = B.tl_n[p];
         if (n < P.min_track_hits) continue;
-        const unsigned long long w = weight_of(n, t);
-        const int64_t g = B.start_row[t];
+        const int64_t g = B.st_row[p];
         const int64_t gs = g - g % nr;
-        const int slot = B.tl_slot[t];
-        const uint16_t* H = B.tl_hits + (int64_t)slot * nr;
+        const uint32_t w = weight_of(B, P, n, rank, gs);
+        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
         uint64_t m[4] = {0, 0, 0, 0};
         int kept = 0;
-        for (int r = 0; r < nr; ++r) {
-            const uint16_t c = H[r];
-            if (c == kNoHit) continue;
-            if (B.W[B.off[gs + r] + c] == w) {
+        for (int r = rlo; r <= rhi; ++r) {
+            const uint16_t k = *hit_slot(B, r, p);
+            if (k == kNoHit) continue;
+            if (B.W[B.off[gs + r] + k] == w) {
                 m[r >> 6] |= 1ull << (r & 63);
                 ++kept;
             }
         }
         if (kept < P.min_track_hits) continue;
+        for (int i = 0; i < 4; ++i) B.keep_mask[p * 4 + i] = m[i];
+        B.keep_n[p] = kept;
+        atomicAdd(&B.bk->hist[1][kept], 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_keep_list(Batch B, DevParams P)
+{
+    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
+        const int kept = B.keep_n[p];
+        if (kept < P.min_track_hits) continue;
+        B.fit_list[B.bk->off[1][kept] + atomicAdd(&B.bk->fill[1][kept], 1)] = (int32_t)p;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Stage 7b, final fit on the kept clusters (inner to outer): three-point seed, C = C0,
+// update outward; C = C0 keeping p, update inward.  Result at the innermost kept
+// cluster; a failed fit drops the track.  Results stay in list order (slot i).
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ bool row_kept(const uint64_t* m, int r) { return (m[r >> 6] >> (r & 63)) & 1ull; }
+
+__global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
+{
+    const int64_t nfit = B.ctr->n_fit;
+    const int nr = P.n_rows;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nfit; i += stride) {
+        const int64_t p = B.fit_list[i];
+        const int64_t rank = B.st_rank[p];
+        const int kept = B.keep_n[p];
+        const int64_t g = B.st_row[p];
+        const int64_t gs = g - g % nr;
+        uint64_t m[4];
+        for (int q = 0; q < 4; ++q) m[q] = B.keep_mask[p * 4 + q];
+        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
         // seed rows: first, middle and last kept cluster
         const int want[3] = {0, (kept - 1) / 2, kept - 1};
         int rsel[3] = {0, 0, 0};
-        for (int r = 0, idx = 0; r < nr; ++r) {
-            if (!((m[r >> 6] >> (r & 63)) & 1ull)) continue;
+        for (int r = rlo, idx = 0; r <= rhi; ++r) {
+            if (!row_kept(m, r)) continue;
             for (int q = 0; q < 3; ++q)
                 if (want[q] == idx) rsel[q] = r;
             ++idx;
         }
         double sx[3], sy[3], sz[3];
         for (int q = 0; q < 3; ++q) {
-            const int64_t gi = B.off[gs + rsel[q]] + H[rsel[q]];
+            const float2 c = B.yz[B.off[gs + rsel[q]] + *hit_slot(B, rsel[q], p)];
             sx[q] = (double)P.rx[rsel[q]];
-            sy[q] = (double)B.y[gi];
-            sz[q] = (double)B.z[gi];
+            sy[q] = (double)c.x;
+            sz[q] = (double)c.y;
         }
         Trk tr;
         bool ok = trk_seed(tr, sx, sy, sz, P);
         if (ok) {
             trk_reset_cov(tr, P);
             for (int r = rsel[0]; r <= rsel[2]; ++r) {
-                if (!((m[r >> 6] >> (r & 63)) & 1ull)) continue;
+                if (!row_kept(m, r)) continue;
                 if (r > rsel[0] && !trk_propagate(tr, (double)P.rx[r], P)) { ok = false; break; }
-                const int64_t gi = B.off[gs + r] + H[r];
-                trk_update(tr, (double)B.y[gi], (double)B.z[gi], P);
+                const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
+                trk_update(tr, (double)c.x, (double)c.y, P);
             }
         }
         double chi2 = 0.0;
         if (ok) {
             trk_reset_cov(tr, P);
             for (int r = rsel[2]; r >= rsel[0]; --r) {
-                if (!((m[r >> 6] >> (r & 63)) & 1ull)) continue;
+                if (!row_kept(m, r)) continue;
                 if (r < rsel[2] && !trk_propagate(tr, (double)P.rx[r], P)) { ok = false; break; }
-                const int64_t gi = B.off[gs + r] + H[r];
-                const double my = (double)B.y[gi], mz = (double)B.z[gi];
+                const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
+                const double my = (double)c.x, mz = (double)c.y;
                 chi2 += trk_chi2(tr, my, mz, P);
                 trk_update(tr, my, mz, P);
             }
         }
         if (ok) {
-            for (int i = 0; i < 5; ++i) ok = ok && isfinite(tr.p[i]);
-            for (int i = 0; i < 15; ++i) ok = ok && isfinite(tr.c[i]);
+            for (int q = 0; q < 5; ++q) ok = ok && isfinite(tr.p[q]);
+            for (int q = 0; q < 15; ++q) ok = ok && isfinite(tr.c[q]);
         }
         if (!ok) continue;
-        double* fp = B.f_par + (int64_t)slot * 5;
-        double* fc = B.f_cov + (int64_t)slot * 15;
-        for (int i = 0; i < 5; ++i) fp[i] = tr.p[i];
-        for (int i = 0; i < 15; ++i) fc[i] = tr.c[i];
-        B.f_chi2[slot] = chi2;
-        B.f_xref[slot] = tr.x;
-        for (int i = 0; i < 4; ++i) B.f_mask[(int64_t)slot * 4 + i] = m[i];
-        B.trk_flag[t] = 1;
-        B.hit_cnt[t] = kept;
+        double* fp = B.f_par + i * 5;
+        double* fc = B.f_cov + i * 15;
+        for (int q = 0; q < 5; ++q) fp[q] = tr.p[q];
+        for (int q = 0; q < 15; ++q) fc[q] = tr.c[q];
+        B.f_chi2[i] = chi2;
+        B.f_xref[i] = tr.x;
+        B.trk_flag[rank] = 1;
+        B.hit_cnt[rank] = kept;
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 8, emit: tracks in rank order at their scanned positions, hits inner to outer,
-// cluster -> track map.  Writes beyond the caller's capacity are dropped and flagged.
+// Stage 8, emit: tracks at their scanned positions (rank order), hits inner to outer as
+// input cluster indices, cluster -> track map.  Writes beyond the caller's capacity are
+// dropped and flagged.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
 {
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
+    const int64_t nfit = B.ctr->n_fit;
     const int nr = P.n_rows;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < hi; t += stride) {
-        if (!B.trk_flag[t]) continue;
-        const int64_t T = B.trk_idx[t];
-        const int64_t hp = B.hit_pos[t];
-        const int nk = B.hit_cnt[t];
-        const int slot = B.tl_slot[t];
-        const int64_t g = B.start_row[t];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nfit; i += stride) {
+        const int64_t p = B.fit_list[i];
+        const int64_t rank = B.st_rank[p];
+        if (!B.trk_flag[rank]) continue;
+        const int64_t T = B.trk_idx[rank];
+        const int64_t hp = B.hit_pos[rank];
+        const int nk = B.hit_cnt[rank];
+        const int64_t g = B.st_row[p];
         const int64_t gs = g - g % nr;
         if (T >= B.cap_tracks || hp + nk > B.cap_hits) {
             atomicOr(&B.ctr->err, kErrOutCap);
             continue;
         }
-        for (int i = 0; i < 5; ++i) B.o_par[T * 5 + i] = B.f_par[(int64_t)slot * 5 + i];
-        for (int i = 0; i < 15; ++i) B.o_cov[T * 15 + i] = B.f_cov[(int64_t)slot * 15 + i];
-        B.o_xref[T] = B.f_xref[slot];
-        B.o_chi2[T] = B.f_chi2[slot];
+        for (int q = 0; q < 5; ++q) B.o_par[T * 5 + q] = B.f_par[i * 5 + q];
+        for (int q = 0; q < 15; ++q) B.o_cov[T * 15 + q] = B.f_cov[i * 15 + q];
+        B.o_xref[T] = B.f_xref[i];
+        B.o_chi2[T] = B.f_chi2[i];
         B.o_ndf[T] = 2 * nk - 5;
         B.o_nhits_trk[T] = nk;
         B.o_sector[T] = (int32_t)((g / nr) % P.n_sectors);
         B.o_tf[T] = (int32_t)(g / ((int64_t)nr * P.n_sectors));
         B.o_hit_off[T + 1] = hp + nk;
-        const uint64_t* m = B.f_mask + (int64_t)slot * 4;
-        const uint16_t* H = B.tl_hits + (int64_t)slot * nr;
         int64_t j = hp;
         for (int w = 0; w < 4; ++w) {
-            uint64_t bits = m[w];
+            uint64_t bits = B.keep_mask[p * 4 + w];
             while (bits) {
                 const int r = w * 64 + __ffsll((unsigned long long)bits) - 1;
                 bits &= bits - 1;
-                const int64_t gi = B.off[gs + r] + H[r];
+                const int64_t first = B.off[gs + r];
+                const int64_t gi = first + B.perm[first + *hit_slot(B, r, p)];
                 B.o_hit_ids[j++] = (int32_t)gi;
                 B.o_cluster_track[gi] = (int32_t)T;
             }
         }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Verification views: links in input (in-row index) order, starts and tracklet sizes in
+// rank order.  Not part of the tracking; run only on request.
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_debug_links(Batch B, DevParams P, int64_t g0, int64_t g1)
+{
+    const int nr = P.n_rows;
+    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+        const int r = (int)(g % nr);
+        const int64_t base = B.off[g];
+        const int n = (int)(B.off[g + 1] - base);
+        const int64_t fu = (r + 1 < nr) ? B.off[g + 1] : 0;
+        const int64_t fd = (r > 0) ? B.off[g - 1] : 0;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int64_t h = base + B.perm[base + k];
+            const int u = B.upk[base + k], d = B.dnk[base + k];
+            const int cu = B.cupk[base + k], cd = B.cdnk[base + k];
+            B.d_up[h] = u >= 0 ? (int)B.perm[fu + u] : -1;
+            B.d_dn[h] = d >= 0 ? (int)B.perm[fd + d] : -1;
+            B.d_cup[h] = cu >= 0 ? (int)B.perm[fu + cu] : -1;
+            B.d_cdn[h] = cd >= 0 ? (int)B.perm[fd + cd] : -1;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_debug_starts(Batch B, DevParams P)
+{
+    const int64_t hi = B.ctr->start_base;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
+        const int64_t rank = B.st_rank[p];
+        const int64_t g = B.st_row[p];
+        B.d_start_row[rank] = (int32_t)g;
+        B.d_start_idx[rank] = (int32_t)B.perm[B.off[g] + B.st_k[p]];
+        B.d_tl_n[rank] = B.tl_n[p];
     }
 }
 
@@ -1029,7 +1235,9 @@ void launch_grid(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, con
 
 void launch_links(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_links, dim3(grid_for(g1 - g0, 1, 1 << 16)), dim3(c.block), 0, s, b, p, g0, g1);
+    // k_links is compiled for at most 256 threads per block (register budget)
+    const int threads = c.block < 256 ? c.block : 256;
+    hipLaunchKernelGGL(k_links, dim3(grid_for(g1 - g0, 1, 1 << 16)), dim3(threads), 0, s, b, p, g0, g1);
 }
 
 void launch_clean(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s)
@@ -1056,6 +1264,13 @@ void launch_starts(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, c
     hipLaunchKernelGGL(k_starts, dim3(grid_for(g1 - g0, 1, 1 << 16)), dim3(c.block), 0, s, b, p, g0, g1);
 }
 
+void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_walk, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, s, b, 0, p.n_rows + 1);
+    hipLaunchKernelGGL(k_walk_list, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+}
+
 void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     const int wpb = c.tl_block / 64;
@@ -1068,9 +1283,16 @@ void launch_claim(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStr
     hipLaunchKernelGGL(k_claim, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
-void launch_keepfit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
+void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_keepfit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+    hipLaunchKernelGGL(k_keep, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, s, b, 1, p.n_rows + 1);
+    hipLaunchKernelGGL(k_keep_list, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+}
+
+void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
 void launch_track_scan(const Batch& b, hipStream_t s)
@@ -1093,6 +1315,13 @@ void launch_track_scan(const Batch& b, hipStream_t s)
 void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_emit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+}
+
+void launch_debug_views(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_debug_links, dim3(grid_for(b.n_rows_total, 1, 1 << 16)), dim3(256), 0, s, b, p,
+                       (int64_t)0, (int64_t)b.n_rows_total);
+    hipLaunchKernelGGL(k_debug_starts, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
 }  // namespace tpcsf
