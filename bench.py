@@ -106,6 +106,103 @@ def cpu_baseline(f, budget_s, max_sectors):
                        f"({done_cl} clusters, {done_t:.1f} s)")
 
 
+def serve(f_main, tuning, batched_rate, seconds, n_slots):
+    """Serving run over a pool of frames (this time frame and three frames of the uneven
+    pp / Pb-Pb mix).  The server's capacity is measured first with every slot kept busy;
+    then frames arrive by a Poisson process at 80% of that capacity and are admitted into
+    the library's server (n_slots slots, 64 GiB HBM budget).  Latency = arrival to tracks
+    downloaded to the host; an admission stall is an arrival that found no free slot."""
+    import torch
+    from paper_2009_07515_amd import synth, tpcsf
+    pool = [f_main]
+    for i in (0, 1, 2):
+        t0 = time.perf_counter()
+        pool.append(synth.config4_frame(i))
+        log(f"serving pool: frame {i} of the uneven mix, {pool[-1].n_clusters} clusters "
+            f"({time.perf_counter() - t0:.1f} s)")
+
+    def pinned(a):
+        t = torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+        return t.numpy()
+
+    pool_h = [(pinned(p.y), pinned(p.z), pinned(p.row_off)) for p in pool]
+    sizes = np.array([p.n_clusters for p in pool], dtype=np.float64)
+    srv = tpcsf.Server(synth.row_x(), tuning=tuning, n_slots=n_slots, hbm_budget=64 << 30)
+    # warm every slot with the largest pool frame so that slot growth is not timed
+    for _ in range(n_slots):
+        tks = [srv.submit(*pool_h[int(np.argmax(sizes))]) for _ in range(n_slots)]
+        for t in tks:
+            if t is not None:
+                srv.wait(t)
+                srv.release(t)
+    rng = np.random.Generator(np.random.PCG64(1005))
+
+    # capacity: closed loop, every slot kept busy with frames drawn from the pool
+    cap_s, done_cl, inflight = 3.0, 0, {}
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < cap_s or inflight:
+        if time.perf_counter() - t_start < cap_s:
+            while True:
+                w = int(rng.integers(0, len(pool)))
+                t = srv.submit(*pool_h[w])
+                if t is None:
+                    break
+                inflight[t] = w
+        for t in list(inflight):
+            if srv.poll(t):
+                done_cl += pool[inflight.pop(t)].n_clusters
+                srv.release(t)
+        time.sleep(0.0002)
+    capacity = done_cl / (time.perf_counter() - t_start)
+    log(f"serving capacity (closed loop, {n_slots} slots): {capacity / 1e9:.3f} G clusters/s")
+
+    # open loop: Poisson arrivals at 80% of that capacity
+    lam = 0.8 * capacity / sizes.mean()
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, int(seconds * lam * 1.5) + 16))
+    arrivals = arrivals[arrivals < seconds]
+    which = rng.integers(0, len(pool), arrivals.shape[0])
+    lat, done_clusters, stalled, stall_time = [], 0, 0, 0.0
+    queue, inflight = [], {}
+    i_next = 0
+    t_start = time.perf_counter()
+    while i_next < arrivals.shape[0] or queue or inflight:
+        now = time.perf_counter() - t_start
+        while i_next < arrivals.shape[0] and arrivals[i_next] <= now:
+            queue.append((arrivals[i_next], int(which[i_next])))
+            i_next += 1
+        while queue:
+            ta, w = queue[0]
+            t = srv.submit(*pool_h[w])
+            if t is None:
+                break
+            waited = (time.perf_counter() - t_start) - ta
+            if waited > 1e-3:           # had to wait for a slot: an admission stall
+                stalled += 1
+                stall_time += waited
+            inflight[t] = (ta, w)
+            queue.pop(0)
+        for t in list(inflight):
+            if srv.poll(t):
+                ta, w = inflight.pop(t)
+                lat.append((time.perf_counter() - t_start) - ta)
+                done_clusters += pool[w].n_clusters
+                srv.release(t)
+        time.sleep(0.0002)
+    wall = time.perf_counter() - t_start
+    lat = np.array(lat) * 1e3
+    res = {"seconds": wall, "frames": int(lat.shape[0]), "arrival_rate_hz": lam, "slots": n_slots,
+           "hbm_budget_gib": 64, "capacity_clusters_per_s": capacity,
+           "clusters_per_s_incl_pcie": done_clusters / wall,
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "max": float(lat.max())},
+           "admission_stalls": stalled, "admission_wait_s": stall_time,
+           "pool_clusters": [int(v) for v in sizes], "device_bytes": srv.bytes_used()}
+    log(f"serving: {res['frames']} frames in {wall:.1f} s, p50 {res['latency_ms']['p50']:.1f} ms, "
+        f"p99 {res['latency_ms']['p99']:.1f} ms, {stalled} stalled admissions")
+    srv.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +214,10 @@ def main():
     ap.add_argument("--cpu-sectors", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", type=str, default="", help="JSON dict of tuning overrides")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the serving run (Poisson arrivals at 80%% of capacity); 0 skips it")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for byte-counter calibration)")
     args = ap.parse_args()
@@ -145,6 +246,16 @@ def main():
     out = tpcsf.TrackBuffers(N)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+
+    # autotuner: bin sizes, bin cap and launch shapes on this input, result-invariance checked
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        best, tms, pts = trk.autotune(frame, reps=2, out=out)
+        tune = {"points": len(pts), "best": pts[best], "best_ms": tms[best], "default_ms": tms[0],
+                "seconds": time.perf_counter() - t0}
+        log(f"autotune: {len(pts)} points in {tune['seconds']:.1f} s, best {pts[best]} "
+            f"{tms[best]:.3f} ms (first point {tms[0]:.3f} ms)")
 
     # reference result of this input (also warms the graph)
     res0 = trk.track(frame, out=out, mode="batch")
@@ -245,6 +356,9 @@ def main():
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
                      "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
+    line["autotune"] = tune
+    if args.serve_seconds > 0:
+        line["serving"] = serve(f, trk.tuning.as_dict(), value, args.serve_seconds, args.serve_slots)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f, args.cpu_budget, args.cpu_sectors)
     print(json.dumps(line), flush=True)

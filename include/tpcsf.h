@@ -137,6 +137,12 @@ tpcsf_status tpcsf_set_tuning(tpcsf_ctx* ctx, const tpcsf_tuning* tuning);
 /* Scratch bytes a batch of n_clusters clusters in n_tf time frames needs. */
 size_t tpcsf_arena_bytes(const tpcsf_ctx* ctx, int64_t n_clusters, int32_t n_tf);
 
+/* Fix the scratch layout to a capacity of max_clusters clusters in max_tf time frames and
+ * allocate it now (TPCSF_E_NOMEM beyond the budget).  Smaller batches then reuse the same
+ * layout, so one captured graph serves every batch up to that capacity with the same
+ * buffers.  max_clusters = 0 releases the reservation (the arena is kept). */
+tpcsf_status tpcsf_reserve(tpcsf_ctx* ctx, int64_t max_clusters, int32_t max_tf);
+
 /* Plain form: every stage launched separately for every (time frame, sector). */
 tpcsf_status tpcsf_track_plain(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_tracks* out,
                                void* stream);
@@ -146,6 +152,16 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_t
  * captured once in a HIP graph and replayed while the batch shape and pointers repeat. */
 tpcsf_status tpcsf_track_batch(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_tracks* out,
                                void* stream);
+
+/* Autotuner: run the batched form at each of n_points tuning points (reps timed calls
+ * each, after one untimed call), check that every point gives exactly the first point's
+ * result (digest of all outputs), and keep the fastest point as the context's tuning.
+ * ms_out[i] (optional) receives the mean time per call of point i, *best its index.
+ * Returns TPCSF_E_INVALID, with the context's tuning unchanged, if a point is out of
+ * range or changes the result.  Synchronises the stream. */
+tpcsf_status tpcsf_autotune(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_tracks* out,
+                            const tpcsf_tuning* points, int32_t n_points, int32_t reps, float* ms_out,
+                            int32_t* best, void* stream);
 
 /* Wait for the stream and report errors the device found since the last sync:
  * TPCSF_E_INVALID (non-finite or |coordinate| > 1e5 cm), TPCSF_E_CAPACITY, or TPCSF_OK. */
@@ -185,6 +201,53 @@ tpcsf_status tpcsf_stage_times(tpcsf_ctx* ctx, float* ms, int32_t n);
 
 /* Message of the last error on this context (static storage of the context). */
 const char* tpcsf_last_error(const tpcsf_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching of time frames that arrive over time (the online setting
+ * of Sec. 3 and 7.1: every frame is processed whole and independently).
+ *
+ * A server owns n_slots slots.  A slot is a tracking context with its own stream and its
+ * own device and pinned host buffers, sized on first use and grown on demand; the device
+ * bytes of all slots stay within hbm_budget_bytes (0 = no bound).  tpcsf_server_submit()
+ * admits a frame into a free slot at once, or returns TPCSF_E_BUSY (an admission stall)
+ * when no free slot can hold it within the budget.  Upload, tracking and download run
+ * asynchronously on the slot's stream, so admitted frames overlap on the device.  Each
+ * frame's result is the same as tpcsf_track_batch() on that frame alone.  All server
+ * calls are thread-safe.
+ * ------------------------------------------------------------------------------------- */
+typedef struct tpcsf_server tpcsf_server;
+
+/* Host copy of one frame's tracks (caller-allocated host buffers, layout as tpcsf_tracks;
+ * cluster_track holds the frame's n_clusters entries). */
+typedef struct {
+    int64_t cap_tracks, cap_hits;
+    int64_t n_tracks, n_hits;           /* written */
+    double* params; double* cov; double* x_ref; double* chi2;
+    int32_t* ndf; int32_t* nhits; int32_t* sector;
+    int64_t* hit_off; int32_t* hit_ids; int32_t* cluster_track;
+} tpcsf_host_tracks;
+
+tpcsf_status tpcsf_server_create(const tpcsf_geometry* geo, const tpcsf_params* params,
+                                 const tpcsf_tuning* tuning, int32_t n_slots, size_t hbm_budget_bytes,
+                                 tpcsf_server** out);
+tpcsf_status tpcsf_server_destroy(tpcsf_server* server);
+
+/* Admit one time frame: y, z [host] [n_clusters], row_offsets [host] [n_sectors*n_rows+1].
+ * The host arrays must stay valid until the ticket completes; pinned (hipHostMalloc)
+ * memory makes the upload asynchronous.  *ticket identifies the frame. */
+tpcsf_status tpcsf_server_submit(tpcsf_server* server, const float* y, const float* z,
+                                 const int64_t* row_offsets, int64_t n_clusters, uint64_t* ticket);
+/* *done = 1 once the frame's tracks are on the host. */
+tpcsf_status tpcsf_server_poll(tpcsf_server* server, uint64_t ticket, int32_t* done);
+/* Wait up to timeout_us (< 0: forever); TPCSF_E_TIMEOUT if the frame is not done. */
+tpcsf_status tpcsf_server_wait(tpcsf_server* server, uint64_t ticket, int64_t timeout_us);
+/* Copy a completed frame's tracks into `out` and release its slot (TPCSF_E_BUSY if not
+ * done yet; TPCSF_E_CAPACITY, slot released, if out is too small).  out = NULL releases
+ * the slot without copying (the frame's status is still returned). */
+tpcsf_status tpcsf_server_result(tpcsf_server* server, uint64_t ticket, tpcsf_host_tracks* out);
+/* Device bytes the slots hold now. */
+size_t tpcsf_server_bytes_used(const tpcsf_server* server);
+const char* tpcsf_server_last_error(const tpcsf_server* server);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ constexpr double kCB = 0.00299792458;   // cm^-1 T^-1 GeV
 struct Layout {
     size_t total = 0;
     int64_t n = 0, R = 0, cap_starts = 0, cap_fit = 0, n_bins = 0;
-    size_t row_lo, row_bin, row_nb, row_nstart, row_sbase;
+    size_t row_lo, row_bin, row_nb, row_f, row_i, row_nstart, row_sbase;
     size_t bin_start, bin_fill, yz, perm, iperm, upk, dnk, cupk, cdnk, rank_at, W;
     size_t st_row, st_k, st_rank, tl_len, order, tl_n, tl_rlo, tl_rhi, tl_hits;
     size_t keep_n, keep_mask, fit_list, buckets;
@@ -53,6 +53,8 @@ struct tpcsf_ctx {
     tpcsf_params params{};
     tpcsf_tuning tuning{};
     size_t budget = 0;
+    int64_t reserve_n = 0;          // layout capacity (clusters), see tpcsf_reserve
+    int32_t reserve_tf = 0;
     float* d_rx = nullptr;
     Counters* d_ctr = nullptr;
     void* arena = nullptr;
@@ -87,6 +89,8 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
 {
+    if (n < c->reserve_n) n = c->reserve_n;
+    if (n_tf < c->reserve_tf) n_tf = c->reserve_tf;
     Layout L;
     L.n = n;
     L.R = (int64_t)n_tf * c->n_sectors * c->n_rows;
@@ -101,6 +105,8 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.row_lo = take(R * 8);
     L.row_bin = take(R * 8);
     L.row_nb = take(R * 8);
+    L.row_f = take(R * 16);
+    L.row_i = take(R * 16);
     L.row_nstart = take(R * 8);
     L.row_sbase = take(R * 8);
     L.bin_start = take((size_t)L.n_bins * 4);
@@ -232,7 +238,8 @@ tpcsf_status ensure_arena(tpcsf_ctx* c, const Layout& L)
         c->arena = nullptr;
         c->arena_size = 0;
     }
-    const size_t want = L.total + L.total / 8;
+    // reserved layouts are sized exactly; otherwise leave room for slightly larger batches
+    const size_t want = c->reserve_n ? L.total : L.total + L.total / 8;
     const size_t sz = (c->budget && want > c->budget) ? L.total : want;
     if ((e = hipMalloc(&c->arena, sz)) != hipSuccess) {
         c->arena = nullptr;
@@ -246,11 +253,14 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
 {
     char* a = (char*)c->arena;
     Batch B;
-    B.y = f->y; B.z = f->z; B.off = f->row_offsets; B.n = f->n_clusters;
-    B.n_rows_total = (int32_t)L.R;
+    B.y = f->y; B.z = f->z; B.off = f->row_offsets; B.n = L.n;
+    B.n_rows_total = (int32_t)((int64_t)f->n_tf * c->n_sectors * c->n_rows);
+    B.n_rows = c->n_rows;
     B.row_lo = (float2*)(a + L.row_lo);
     B.row_bin = (float2*)(a + L.row_bin);
     B.row_nb = (int2*)(a + L.row_nb);
+    B.row_f = (float4*)(a + L.row_f);
+    B.row_i = (int4*)(a + L.row_i);
     B.bin_start = (uint32_t*)(a + L.bin_start);
     B.bin_fill = (uint32_t*)(a + L.bin_fill);
     B.yz = (float2*)(a + L.yz);
@@ -486,7 +496,8 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
     const Batch B = make_batch(c, L, f, o);
     GraphKey k;
     std::memset(&k, 0, sizeof k);
-    k.y = f->y; k.z = f->z; k.off = f->row_offsets; k.n = f->n_clusters; k.R = L.R;
+    // the layout (not the cluster count) fixes every kernel argument
+    k.y = f->y; k.z = f->z; k.off = f->row_offsets; k.n = L.n; k.R = B.n_rows_total;
     k.arena = c->arena;
     k.out = *o;
     k.tuning = c->tuning;
@@ -568,6 +579,71 @@ tpcsf_status tpcsf_debug(tpcsf_ctx* c, tpcsf_debug_view* v)
     v->start_row = B.d_start_row;
     v->start_idx = B.d_start_idx;
     v->tl_nhits = B.d_tl_n;
+    return TPCSF_OK;
+}
+
+tpcsf_status tpcsf_reserve(tpcsf_ctx* c, int64_t max_clusters, int32_t max_tf)
+{
+    if (!c || max_clusters < 0 || max_clusters >= ((int64_t)1 << 31) - 1 || max_tf < 0) return TPCSF_E_INVALID;
+    c->reserve_n = max_clusters;
+    c->reserve_tf = max_tf;
+    return ensure_arena(c, make_layout(c, max_clusters, max_tf > 0 ? max_tf : 1));
+}
+
+tpcsf_status tpcsf_autotune(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks* o, const tpcsf_tuning* points,
+                            int32_t n_points, int32_t reps, float* ms_out, int32_t* best, void* stream)
+{
+    if (!c || !points || n_points < 1 || reps < 1) return TPCSF_E_INVALID;
+    for (int i = 0; i < n_points; ++i)
+        if (!tuning_ok(&points[i])) return fail(c, TPCSF_E_INVALID, "tuning point " + std::to_string(i) + " out of range");
+    const tpcsf_tuning saved = c->tuning;
+    const int32_t timing = c->timing;
+    c->timing = 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return hip_fail(c, e, "hipEventCreate");
+    unsigned long long ref = 0;
+    float best_ms = 0.0f;
+    int32_t best_i = -1;
+    tpcsf_status st = TPCSF_OK;
+    for (int i = 0; i < n_points && st == TPCSF_OK; ++i) {
+        c->tuning = points[i];
+        if ((st = tpcsf_track_batch(c, f, o, stream)) != TPCSF_OK) break;
+        launch_hash(c->last, f->n_clusters, launch_cfg(c), s);
+        if ((st = tpcsf_sync(c, stream)) != TPCSF_OK) break;
+        unsigned long long h = 0;
+        if ((e = hipMemcpy(&h, &c->d_ctr->hash, sizeof(h), hipMemcpyDeviceToHost)) != hipSuccess) {
+            st = hip_fail(c, e, "reading the output digest");
+            break;
+        }
+        if (i == 0) {
+            ref = h;
+        } else if (h != ref) {
+            st = fail(c, TPCSF_E_INVALID, "tuning point " + std::to_string(i) + " changed the result");
+            break;
+        }
+        (void)hipEventRecord(e0, s);
+        for (int k = 0; k < reps && st == TPCSF_OK; ++k) st = tpcsf_track_batch(c, f, o, stream);
+        (void)hipEventRecord(e1, s);
+        if (st != TPCSF_OK) break;
+        if ((st = tpcsf_sync(c, stream)) != TPCSF_OK) break;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (ms_out) ms_out[i] = ms;
+        if (best_i < 0 || ms < best_ms) { best_ms = ms; best_i = i; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = timing;
+    if (st != TPCSF_OK || best_i < 0) {
+        c->tuning = saved;
+        return st != TPCSF_OK ? st : TPCSF_E_INVALID;
+    }
+    c->tuning = points[best_i];
+    if (best) *best = best_i;
     return TPCSF_OK;
 }
 

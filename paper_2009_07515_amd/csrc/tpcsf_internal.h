@@ -39,6 +39,7 @@ struct Counters {
     int32_t n_fit;                  // tracks to fit (>= min_track_hits kept)
     int32_t queue;                  // tracklet work-queue head
     int32_t err;                    // error bits
+    unsigned long long hash;        // output digest (autotuner's result-invariance check)
 };
 
 // Length buckets used to order variable-length work (longest first): histogram, fill
@@ -64,10 +65,13 @@ struct Batch {
     const int64_t* off;             // [R+1]
     int64_t n;                      // clusters
     int32_t n_rows_total;           // R = n_tf * n_sectors * n_rows
+    int32_t n_rows;                 // rows per sector
     // grid
     float2* row_lo;                 // [R] y_lo, z_lo
     float2* row_bin;                // [R] b_y, b_z
     int2* row_nb;                   // [R] ny, nz
+    float4* row_f;                  // [R] y_lo, z_lo, 1/b_y, 1/b_z (search records)
+    int4* row_i;                    // [R] first cluster, count, ny, nz
     uint32_t* bin_start;            // [cap_mul*N + (cap_add+1)*R]
     uint32_t* bin_fill;             // same size
     float2* yz;                     // [N] sorted (y, z)
@@ -84,7 +88,7 @@ struct Batch {
     int32_t* st_k;                  // [cap_starts] sorted position
     int32_t* st_rank;               // [cap_starts] rank
     int64_t cap_starts;
-    // tracklets (p indexed); the hit table is row-major: H[r * cap_starts + p]
+    // tracklets (p indexed); hit table H[p * n_rows + r]
     int32_t* tl_len;                // chain length
     int32_t* order;                 // [cap_starts] tracklets to build, longest chain first
     int32_t* tl_n;                  // clusters, 0 = none
@@ -144,5 +148,6 @@ void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStrea
 void launch_track_scan(const Batch& b, hipStream_t s);
 void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_debug_views(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
+void launch_hash(const Batch& b, int64_t n_clusters, const LaunchCfg& c, hipStream_t s);
 
 }  // namespace tpcsf

@@ -182,6 +182,8 @@ __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0,
             B.row_lo[g] = make_float2(ylo, zlo);
             B.row_bin[g] = make_float2(by, bz);
             B.row_nb[g] = make_int2(ny, nz);
+            B.row_f[g] = make_float4(ylo, zlo, 1.0f / by, 1.0f / bz);
+            B.row_i[g] = make_int4((int)base, n, ny, nz);
         }
         const int nb = ny * nz;
         uint32_t* bs = B.bin_start + bin_base(P, base, g);
@@ -243,8 +245,9 @@ __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0,
 // ------------------------------------------------------------------------------------
 struct RowView {
     int64_t first;            // first cluster of the row
-    float ylo, zlo, by, bz;
-    float iby, ibz;           // reciprocals, for conservative window bins only
+    int n;                    // clusters in the row
+    float ylo, zlo;
+    float iby, ibz;           // reciprocal bin sizes, for conservative window bins only
     int ny, nz;
     const uint32_t* bs;       // bin_start of the row
 };
@@ -252,12 +255,11 @@ struct RowView {
 __device__ __forceinline__ RowView row_view(const Batch& B, const DevParams& P, int64_t g)
 {
     RowView v;
-    v.first = B.off[g];
-    const float2 lo = B.row_lo[g], bn = B.row_bin[g];
-    const int2 nb = B.row_nb[g];
-    v.ylo = lo.x; v.zlo = lo.y; v.by = bn.x; v.bz = bn.y; v.ny = nb.x; v.nz = nb.y;
-    v.iby = 1.0f / bn.x;
-    v.ibz = 1.0f / bn.y;
+    const float4 f = B.row_f[g];
+    const int4 i = B.row_i[g];
+    v.first = i.x;
+    v.n = i.y;
+    v.ylo = f.x; v.zlo = f.y; v.iby = f.z; v.ibz = f.w; v.ny = i.z; v.nz = i.w;
     v.bs = B.bin_start + bin_base(P, v.first, g);
     return v;
 }
@@ -301,19 +303,26 @@ __device__ __forceinline__ int gather_cands(const RowView& V, const float2* yz, 
     int cnt = 0;
     for (int iz = iz0; iz <= iz1; ++iz) {
         const uint32_t ka = V.bs[iz * V.ny + iy0], kb = V.bs[iz * V.ny + iy1 + 1];
-        for (uint32_t q = ka; q < kb; ++q) {
-            const float2 c = yz[q];
-            if (!(fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz)) continue;
-            const int slot = cnt - skip;
-            if (slot >= 0 && slot < kMaxCand) {
-                const float sy = above ? (c.x - yh) / dx : (yh - c.x) / dx;
-                const float sz = above ? (c.y - zh) / dx : (zh - c.y) / dx;
-                const int o = (int)perm[q];
+        for (uint32_t q0 = ka; q0 < kb; q0 += 4) {
+            float2 c4[4];
 #pragma unroll
-                for (int j = 0; j < kMaxCand; ++j)
-                    if (j == slot) { ty[j] = sy; tz[j] = sz; kk[j] = (int)q; oo[j] = o; }
+            for (int j = 0; j < 4; ++j) c4[j] = (q0 + j < kb) ? yz[q0 + j] : make_float2(INFINITY, INFINITY);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 c = c4[j];
+                const uint32_t q = q0 + j;
+                if (!(fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz)) continue;
+                const int slot = cnt - skip;
+                if (slot >= 0 && slot < kMaxCand) {
+                    const float sy = above ? (c.x - yh) / dx : (yh - c.x) / dx;
+                    const float sz = above ? (c.y - zh) / dx : (zh - c.y) / dx;
+                    const int o = (int)perm[q];
+#pragma unroll
+                    for (int m = 0; m < kMaxCand; ++m)
+                        if (m == slot) { ty[m] = sy; tz[m] = sz; kk[m] = (int)q; oo[m] = o; }
+                }
+                ++cnt;
             }
-            ++cnt;
         }
     }
     return cnt;
@@ -772,11 +781,9 @@ __device__ bool trk_seed(Trk& t, const double* x, const double* y, const double*
 // Equal chi2: the smaller in-row index.
 __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const Trk& t, double& best_chi2)
 {
-    const int64_t first = B.off[g];
-    const int n = (int)(B.off[g + 1] - first);
-    best_chi2 = 0.0;
-    if (n == 0) return -1;
     const RowView v = row_view(B, P, g);
+    best_chi2 = 0.0;
+    if (v.n == 0) return -1;
     const double s00 = t.c[0] + P.sy2, s01 = t.c[1], s11 = t.c[2] + P.sz2;
     double wy = P.nsig * sqrt(s00), wz = P.nsig * sqrt(s11);
     if (wy > (double)P.win_y) wy = (double)P.win_y;
@@ -787,21 +794,27 @@ __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const T
     bin_span((float)yp, (float)wy, v.ylo, v.iby, v.ny, iy0, iy1);
     bin_span((float)zp, (float)wz, v.zlo, v.ibz, v.nz, iz0, iz1);
     const double idet = 1.0 / (s00 * s11 - s01 * s01);
-    const float2* yz = B.yz + first;
+    const float2* yz = B.yz + v.first;
     int best = -1;
     for (int iz = iz0; iz <= iz1; ++iz) {
         const uint32_t ka = v.bs[iz * v.ny + iy0], kb = v.bs[iz * v.ny + iy1 + 1];
-        for (uint32_t k = ka; k < kb; ++k) {
-            const float2 c = yz[k];
-            const double dy = (double)c.x - yp;
-            const double dz = (double)c.y - zp;
-            if (!(fabs(dy) <= wy) || !(fabs(dz) <= wz)) continue;
-            const double chi2 = (dy * dy * s11 - 2.0 * dy * dz * s01 + dz * dz * s00) * idet;
-            bool take = best < 0 || chi2 < best_chi2;
-            if (!take && chi2 == best_chi2) take = B.perm[first + k] < B.perm[first + best];
-            if (take) {
-                best = (int)k;
-                best_chi2 = chi2;
+        for (uint32_t k0 = ka; k0 < kb; k0 += 4) {
+            float2 c4[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c4[j] = (k0 + j < kb) ? yz[k0 + j] : make_float2(INFINITY, INFINITY);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double dy = (double)c4[j].x - yp;
+                const double dz = (double)c4[j].y - zp;
+                if (!(fabs(dy) <= wy) || !(fabs(dz) <= wz)) continue;
+                const int k = (int)(k0 + j);
+                const double chi2 = (dy * dy * s11 - 2.0 * dy * dz * s01 + dz * dz * s00) * idet;
+                bool take = best < 0 || chi2 < best_chi2;
+                if (!take && chi2 == best_chi2) take = B.perm[v.first + k] < B.perm[v.first + best];
+                if (take) {
+                    best = k;
+                    best_chi2 = chi2;
+                }
             }
         }
     }
@@ -815,14 +828,12 @@ __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const T
 __global__ void k_bucket_scan(Batch B, int which, int n_buckets)
 {
     // one block: offsets for descending length, total, then clear the histogram and fill
-    __shared__ int32_t tot;
     if (threadIdx.x == 0) {
         int32_t run = 0;
         for (int L = n_buckets - 1; L >= 0; --L) {
             B.bk->off[which][L] = run;
             run += B.bk->hist[which][L];
         }
-        tot = run;
         if (which == 0) B.ctr->n_order = run; else B.ctr->n_fit = run;
     }
     __syncthreads();
@@ -835,11 +846,11 @@ __global__ void k_bucket_scan(Batch B, int which, int n_buckets)
 // ------------------------------------------------------------------------------------
 // Stage 5a, chains: walk the cleaned up-links from every start (one lane each), record
 // the chain in the tracklet's hit table and its length; chains of >= min_chain clusters
-// become tracklets and are listed longest first.
+// become tracklets.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ uint16_t* hit_slot(const Batch& B, int r, int64_t p)
 {
-    return B.tl_hits + (int64_t)r * B.cap_starts + p;
+    return B.tl_hits + p * (int64_t)B.n_rows + r;
 }
 
 __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
@@ -859,18 +870,6 @@ __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
         }
         B.tl_len[p] = L;
         B.tl_n[p] = 0;
-        if (L >= P.min_chain) atomicAdd(&B.bk->hist[0][L], 1);
-    }
-}
-
-__global__ void __launch_bounds__(256) k_walk_list(Batch B, DevParams P)
-{
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
-        const int L = B.tl_len[p];
-        if (L < P.min_chain) continue;
-        B.order[B.bk->off[0][L] + atomicAdd(&B.bk->fill[0][L], 1)] = (int32_t)p;
     }
 }
 
@@ -901,8 +900,9 @@ __device__ int follow(const Batch& B, const DevParams& P, Trk& t, int64_t gs, in
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 5b, tracklets: one lane per chain, pulled from a persistent work queue (longest
-// chains first).  Three-point seed, Kalman update over the chain, follow outward, reset
+// Stage 5b, tracklets: one lane per chain, pulled from a persistent work queue in
+// processing order (neighbouring chains of one sector share a wave).  Three-point seed,
+// Kalman update over the chain, follow outward, reset
 // C to C0 keeping p and refit inward over all clusters so far, follow inward.  Clusters
 // are recorded per row (sorted positions); rows [rlo, rhi] are all written.
 // ------------------------------------------------------------------------------------
@@ -953,17 +953,18 @@ __device__ void build_tracklet(const Batch& B, const DevParams& P, int64_t p)
 
 __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int chunk)
 {
-    const int64_t hi = B.ctr->n_order;
+    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     const int lane = lane_id();
     const int per_wave = 64 * chunk;
     for (;;) {
         int take = 0;
         if (lane == 0) take = atomicAdd(&B.ctr->queue, per_wave);
         take = __shfl(take, 0, 64);
-        if (take >= hi) break;
+        const int64_t t0 = lo + take;
+        if (t0 >= hi) break;
         for (int k = 0; k < chunk; ++k) {
-            const int64_t i = (int64_t)take + (int64_t)k * 64 + lane;
-            if (i < hi) build_tracklet(B, P, B.order[i]);
+            const int64_t p = t0 + (int64_t)k * 64 + lane;
+            if (p < hi && B.tl_len[p] >= P.min_chain) build_tracklet(B, P, p);
         }
     }
 }
@@ -1008,6 +1009,9 @@ __global__ void __launch_bounds__(256) k_claim(Batch B, DevParams P)
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
 {
+    __shared__ int32_t hist[kBuckets];
+    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
     const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     const int nr = P.n_rows;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1035,8 +1039,11 @@ __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
         if (kept < P.min_track_hits) continue;
         for (int i = 0; i < 4; ++i) B.keep_mask[p * 4 + i] = m[i];
         B.keep_n[p] = kept;
-        atomicAdd(&B.bk->hist[1][kept], 1);
+        atomicAdd(&hist[kept], 1);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
+        if (hist[i]) atomicAdd(&B.bk->hist[1][i], hist[i]);
 }
 
 __global__ void __launch_bounds__(256) k_keep_list(Batch B, DevParams P)
@@ -1158,17 +1165,14 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
         B.o_sector[T] = (int32_t)((g / nr) % P.n_sectors);
         B.o_tf[T] = (int32_t)(g / ((int64_t)nr * P.n_sectors));
         B.o_hit_off[T + 1] = hp + nk;
+        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
         int64_t j = hp;
-        for (int w = 0; w < 4; ++w) {
-            uint64_t bits = B.keep_mask[p * 4 + w];
-            while (bits) {
-                const int r = w * 64 + __ffsll((unsigned long long)bits) - 1;
-                bits &= bits - 1;
-                const int64_t first = B.off[gs + r];
-                const int64_t gi = first + B.perm[first + *hit_slot(B, r, p)];
-                B.o_hit_ids[j++] = (int32_t)gi;
-                B.o_cluster_track[gi] = (int32_t)T;
-            }
+        for (int r = rlo; r <= rhi; ++r) {
+            if (!((B.keep_mask[p * 4 + (r >> 6)] >> (r & 63)) & 1ull)) continue;
+            const int64_t first = B.off[gs + r];
+            const int64_t gi = first + B.perm[first + *hit_slot(B, r, p)];
+            B.o_hit_ids[j++] = (int32_t)gi;
+            B.o_cluster_track[gi] = (int32_t)T;
         }
     }
 }
@@ -1209,6 +1213,48 @@ __global__ void __launch_bounds__(256) k_debug_starts(Batch B, DevParams P)
         B.d_start_idx[rank] = (int32_t)B.perm[B.off[g] + B.st_k[p]];
         B.d_tl_n[rank] = B.tl_n[p];
     }
+}
+
+// ------------------------------------------------------------------------------------
+// Output digest: XOR over every output element of a mix of (array, index, bits).  The
+// XOR is independent of the order of the atomics, so equal outputs give equal digests.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x)
+{
+    x ^= x >> 30; x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27; x *= 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ unsigned long long elem_hash(unsigned long long tag, int64_t i, unsigned long long v)
+{
+    return mix64(v + mix64(((unsigned long long)i << 4) ^ tag));
+}
+
+__global__ void __launch_bounds__(256) k_hash(Batch B, int64_t n_clusters)
+{
+    const int64_t T = min(*B.o_ntracks, B.cap_tracks);
+    const int64_t H = min(*B.o_nhits, B.cap_hits);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long h = 0;
+    if (t0 == 0) h ^= elem_hash(1, 0, (unsigned long long)T) ^ elem_hash(2, 0, (unsigned long long)H);
+    for (int64_t i = t0; i < T; i += stride) {
+        for (int q = 0; q < 5; ++q) h ^= elem_hash(3, i * 5 + q, __double_as_longlong(B.o_par[i * 5 + q]));
+        for (int q = 0; q < 15; ++q) h ^= elem_hash(4, i * 15 + q, __double_as_longlong(B.o_cov[i * 15 + q]));
+        h ^= elem_hash(5, i, (unsigned long long)B.o_hit_off[i + 1]);
+        h ^= elem_hash(6, i, __double_as_longlong(B.o_chi2[i]));
+    }
+    for (int64_t i = t0; i < H; i += stride) h ^= elem_hash(7, i, (unsigned long long)(uint32_t)B.o_hit_ids[i]);
+    for (int64_t i = t0; i < n_clusters; i += stride)
+        h ^= elem_hash(8, i, (unsigned long long)(uint32_t)B.o_cluster_track[i]);
+    for (int d = 32; d >= 1; d >>= 1) h ^= __shfl_xor(h, d, 64);
+    if (lane_id() == 0 && h) atomicXor(&B.ctr->hash, h);
+}
+
+__global__ void k_hash_clear(Batch B)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) B.ctr->hash = 0ull;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1267,8 +1313,6 @@ void launch_starts(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, c
 void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_walk, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, s, b, 0, p.n_rows + 1);
-    hipLaunchKernelGGL(k_walk_list, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
 void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
@@ -1315,6 +1359,12 @@ void launch_track_scan(const Batch& b, hipStream_t s)
 void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_emit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+}
+
+void launch_hash(const Batch& b, int64_t n_clusters, const LaunchCfg& c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hash_clear, dim3(1), dim3(64), 0, s, b);
+    hipLaunchKernelGGL(k_hash, dim3(c.n_cu * 4), dim3(256), 0, s, b, n_clusters);
 }
 
 void launch_debug_views(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)

@@ -65,6 +65,13 @@ class TracksDesc(C.Structure):
                 ("cluster_track", C.c_void_p)]
 
 
+class HostTracks(C.Structure):
+    _fields_ = [("cap_tracks", C.c_int64), ("cap_hits", C.c_int64), ("n_tracks", C.c_int64), ("n_hits", C.c_int64),
+                ("params", C.c_void_p), ("cov", C.c_void_p), ("x_ref", C.c_void_p), ("chi2", C.c_void_p),
+                ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p), ("hit_off", C.c_void_p),
+                ("hit_ids", C.c_void_p), ("cluster_track", C.c_void_p)]
+
+
 class DebugView(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("row_lo", "row_bin", "row_nb", "bin_start", "perm", "up", "dn",
                                            "cup", "cdn", "n_starts", "start_row", "start_idx", "tl_nhits")]
@@ -115,6 +122,28 @@ def load():
     lib.tpcsf_stage_times.restype = C.c_int
     lib.tpcsf_last_error.argtypes = [vp]
     lib.tpcsf_last_error.restype = C.c_char_p
+    lib.tpcsf_reserve.argtypes = [vp, C.c_int64, C.c_int32]
+    lib.tpcsf_reserve.restype = C.c_int
+    lib.tpcsf_autotune.argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), C.POINTER(Tuning), C.c_int32,
+                                   C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int32), vp]
+    lib.tpcsf_autotune.restype = C.c_int
+    lib.tpcsf_server_create.argtypes = [C.POINTER(Geometry), C.POINTER(Params), C.POINTER(Tuning), C.c_int32,
+                                        C.c_size_t, C.POINTER(vp)]
+    lib.tpcsf_server_create.restype = C.c_int
+    lib.tpcsf_server_destroy.argtypes = [vp]
+    lib.tpcsf_server_destroy.restype = C.c_int
+    lib.tpcsf_server_submit.argtypes = [vp, vp, vp, vp, C.c_int64, C.POINTER(C.c_uint64)]
+    lib.tpcsf_server_submit.restype = C.c_int
+    lib.tpcsf_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32)]
+    lib.tpcsf_server_poll.restype = C.c_int
+    lib.tpcsf_server_wait.argtypes = [vp, C.c_uint64, C.c_int64]
+    lib.tpcsf_server_wait.restype = C.c_int
+    lib.tpcsf_server_result.argtypes = [vp, C.c_uint64, C.POINTER(HostTracks)]
+    lib.tpcsf_server_result.restype = C.c_int
+    lib.tpcsf_server_bytes_used.argtypes = [vp]
+    lib.tpcsf_server_bytes_used.restype = C.c_size_t
+    lib.tpcsf_server_last_error.argtypes = [vp]
+    lib.tpcsf_server_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -290,6 +319,28 @@ class Tracker:
         self.sync(stream)
         return out.result(frame.n_clusters)
 
+    def reserve(self, max_clusters, max_tf=1):
+        """Fix the scratch layout to this capacity (one graph then serves smaller batches)."""
+        self._check(self.lib.tpcsf_reserve(self.h, int(max_clusters), int(max_tf)))
+
+    def autotune(self, frame: DeviceFrame, points=None, reps=3, out=None, stream=None):
+        """Time the batched form at each tuning point, check that all give the same result,
+        and keep the fastest.  Returns (best index, ms per point, tuning points)."""
+        pts = [dict(self.tuning.as_dict(), **p) for p in (points or default_sweep())]
+        arr = (Tuning * len(pts))()
+        for i, p in enumerate(pts):
+            for k, v in p.items():
+                setattr(arr[i], k, v)
+        if out is None:
+            out = TrackBuffers(frame.n_clusters, min_track_hits=self.params.min_track_hits)
+        ms = (C.c_float * len(pts))()
+        best = C.c_int32(-1)
+        fd, od = frame.desc(), out.desc()
+        self._check(self.lib.tpcsf_autotune(self.h, C.byref(fd), C.byref(od), arr, len(pts), int(reps), ms,
+                                            C.byref(best), self._stream(stream)))
+        self.tuning = Tuning.from_buffer_copy(arr[best.value])
+        return best.value, [float(v) for v in ms], pts
+
     def set_stage_timing(self, on=True):
         self._check(self.lib.tpcsf_set_stage_timing(self.h, 1 if on else 0))
 
@@ -330,6 +381,117 @@ class Tracker:
         nb_total = int(t.cap_mul) * n + (int(t.cap_add) + 1) * R
         res["bin_start"] = dev(v.bin_start, nb_total, np.uint32)
         return res
+
+
+def default_sweep():
+    """Tuning points of the autotuner: grid bin sizes and bin cap crossed with launch
+    shapes (row-kernel block, tracklet block, work-queue chunk)."""
+    bins = [dict(bin_y=1.0, bin_z=2.0, cap_mul=2), dict(bin_y=2.0, bin_z=2.0, cap_mul=2),
+            dict(bin_y=2.0, bin_z=8.0, cap_mul=2), dict(bin_y=4.0, bin_z=4.0, cap_mul=2),
+            dict(bin_y=1.0, bin_z=1.0, cap_mul=4), dict(bin_y=2.0, bin_z=4.0, cap_mul=4),
+            dict(bin_y=3.0, bin_z=3.0, cap_mul=8)]
+    shapes = [dict(block=256, tl_block=256, chunk=1), dict(block=128, tl_block=128, chunk=1),
+              dict(block=256, tl_block=64, chunk=1), dict(block=512, tl_block=256, chunk=2)]
+    return [dict(b, **sh) for b in bins for sh in shapes]
+
+
+class Server:
+    """Continuous-batching server of the library (see tpcsf_server_* in the header)."""
+
+    def __init__(self, row_x, bz=0.5, n_sectors=36, params=None, tuning=None, n_slots=4, hbm_budget=0):
+        lib = load()
+        self.lib = lib
+        self.row_x = np.ascontiguousarray(row_x, dtype=np.float32)
+        self.n_sectors, self.n_rows = int(n_sectors), int(self.row_x.shape[0])
+        geo = Geometry(self.n_sectors, self.n_rows, self.row_x.ctypes.data_as(C.c_void_p), float(bz))
+        p = default_params()
+        for k, v in (params or {}).items():
+            if k == "c0":
+                p.c0 = (C.c_double * 5)(*v)
+            else:
+                setattr(p, k, v)
+        t = default_tuning()
+        for k, v in (tuning or {}).items():
+            setattr(t, k, v)
+        self.params = p
+        h = C.c_void_p()
+        st = lib.tpcsf_server_create(C.byref(geo), C.byref(p), C.byref(t), int(n_slots), int(hbm_budget), C.byref(h))
+        if st != OK:
+            raise TpcsfError(st, "tpcsf_server_create failed")
+        self.h = h
+        self._inputs = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tpcsf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise TpcsfError(st, self.lib.tpcsf_server_last_error(self.h).decode())
+
+    def submit(self, y, z, row_off):
+        """Admit a frame (numpy arrays; pinned memory makes the upload asynchronous).
+        Returns a ticket, or None if the server is busy (an admission stall)."""
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        z = np.ascontiguousarray(z, dtype=np.float32)
+        ro = np.ascontiguousarray(row_off, dtype=np.int64)
+        t = C.c_uint64()
+        st = self.lib.tpcsf_server_submit(self.h, y.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p),
+                                          ro.ctypes.data_as(C.c_void_p), int(y.shape[0]), C.byref(t))
+        if st == E_BUSY:
+            return None
+        self._check(st)
+        self._inputs[t.value] = (y, z, ro)      # keep the host arrays alive until done
+        return t.value
+
+    def poll(self, ticket):
+        d = C.c_int32()
+        self._check(self.lib.tpcsf_server_poll(self.h, ticket, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket, timeout_s=-1.0):
+        st = self.lib.tpcsf_server_wait(self.h, ticket, int(timeout_s * 1e6) if timeout_s >= 0 else -1)
+        if st == E_TIMEOUT:
+            return False
+        self._check(st)
+        return True
+
+    def release(self, ticket):
+        """Release a completed frame's slot without copying its tracks."""
+        st = self.lib.tpcsf_server_result(self.h, ticket, None)
+        del self._inputs[ticket]
+        self._check(st)
+
+    def result(self, ticket):
+        """Tracks of a completed frame as numpy arrays; releases its slot."""
+        y, _, _ = self._inputs[ticket]
+        n = int(y.shape[0])
+        T = n // max(1, self.params.min_track_hits) + 1
+        o = dict(params=np.zeros((T, 5)), cov=np.zeros((T, 15)), x_ref=np.zeros(T), chi2=np.zeros(T),
+                 ndf=np.zeros(T, np.int32), nhits=np.zeros(T, np.int32), sector=np.zeros(T, np.int32),
+                 hit_off=np.zeros(T + 1, np.int64), hit_ids=np.zeros(max(n, 1), np.int32),
+                 cluster_track=np.zeros(max(n, 1), np.int32))
+        ht = HostTracks(T, n, 0, 0, *[o[k].ctypes.data_as(C.c_void_p) for k in
+                                      ("params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector", "hit_off",
+                                       "hit_ids", "cluster_track")])
+        st = self.lib.tpcsf_server_result(self.h, ticket, C.byref(ht))
+        del self._inputs[ticket]
+        self._check(st)
+        Tn, Hn = ht.n_tracks, ht.n_hits
+        res = {k: v[:Tn] for k, v in o.items() if k not in ("hit_off", "hit_ids", "cluster_track")}
+        res.update(n_tracks=Tn, n_hits=Hn, hit_off=o["hit_off"][:Tn + 1], hit_ids=o["hit_ids"][:Hn],
+                   cluster_track=o["cluster_track"][:n])
+        return res
+
+    def bytes_used(self):
+        return int(self.lib.tpcsf_server_bytes_used(self.h))
 
 
 _hip = None

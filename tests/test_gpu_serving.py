@@ -1,0 +1,96 @@
+"""Batched-form extras on the GPU: the autotuner (result invariance across tuning
+points), reserved layouts (one graph for frames of different sizes) and the serving
+layer (each frame's result in a concurrent mix equals its result alone)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2009_07515_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("hit_off", "hit_ids", "params", "cov", "chi2", "sector", "cluster_track")
+
+
+def _np(res):
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+
+
+def _frames():
+    fs = [synth.config2_pbpb_event(seed=300 + i, n_primary=200 + 350 * i) for i in range(4)]
+    fs.append(synth.config1_single_sector(seed=77))
+    return fs
+
+
+def test_autotune_keeps_results_and_picks_a_point(small_pbpb_frame):
+    from paper_2009_07515_amd import tpcsf
+    trk = tpcsf.Tracker(synth.row_x())
+    fr = tpcsf.DeviceFrame.from_numpy(small_pbpb_frame.y, small_pbpb_frame.z, small_pbpb_frame.row_off)
+    ref = _np(trk.track(fr))
+    pts = [dict(bin_y=2.0, bin_z=2.0), dict(bin_y=1.0, bin_z=8.0, cap_mul=4, block=128),
+           dict(bin_y=5.0, bin_z=5.0, cap_mul=1, cap_add=16, tl_block=64, chunk=3)]
+    best, ms, used = trk.autotune(fr, points=pts, reps=2)
+    assert 0 <= best < len(pts) and all(m > 0 for m in ms)
+    assert trk.tuning.as_dict() == tpcsf.Tuning(**{k: used[best][k] for k, _ in tpcsf.Tuning._fields_}).as_dict()
+    got = _np(trk.track(fr))
+    for k in KEYS:
+        assert np.array_equal(ref[k], got[k]), k
+    with pytest.raises(tpcsf.TpcsfError) as e:
+        trk.autotune(fr, points=[dict(block=100)])
+    assert e.value.status == tpcsf.E_INVALID
+
+
+def test_reserved_layout_serves_frames_of_any_size():
+    from paper_2009_07515_amd import tpcsf
+    fs = _frames()
+    alone = [_np(tpcsf.Tracker(synth.row_x()).track(tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off)))
+             for f in fs]
+    trk = tpcsf.Tracker(synth.row_x())
+    trk.reserve(max(f.n_clusters for f in fs))
+    for f, ref in zip(fs, alone):
+        got = _np(trk.track(tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off)))
+        for k in KEYS:
+            assert np.array_equal(ref[k], got[k]), k
+
+
+@pytest.mark.parametrize("n_slots,budget", [(2, 0), (3, 6 << 30), (1, 0)])
+def test_server_results_alone_equal_results_in_the_mix(n_slots, budget):
+    from paper_2009_07515_amd import tpcsf
+    fs = _frames() * 2
+    trk = tpcsf.Tracker(synth.row_x())
+    alone = [_np(trk.track(tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off))) for f in fs[:5]]
+    srv = tpcsf.Server(synth.row_x(), n_slots=n_slots, hbm_budget=budget)
+    pending = list(range(len(fs)))
+    inflight, stalls, done = {}, 0, {}
+    t_end = time.time() + 100
+    while (pending or inflight) and time.time() < t_end:
+        while pending:
+            f = fs[pending[0]]
+            t = srv.submit(f.y, f.z, f.row_off)
+            if t is None:
+                stalls += 1
+                break
+            inflight[t] = pending.pop(0)
+        for t in list(inflight):
+            if srv.poll(t):
+                done[inflight.pop(t)] = srv.result(t)
+    assert not pending and not inflight
+    if n_slots < len(fs):
+        assert stalls > 0
+    for i, f in enumerate(fs):
+        ref = alone[i % 5]
+        got = done[i]
+        assert got["n_tracks"] == ref["n_tracks"]
+        for k in KEYS:
+            assert np.array_equal(np.asarray(ref[k]), np.asarray(got[k])), (i, k)
+    if budget:
+        assert srv.bytes_used() <= budget
+
+
+def test_server_budget_too_small_stalls():
+    from paper_2009_07515_amd import tpcsf
+    f = synth.config1_single_sector(seed=77)
+    srv = tpcsf.Server(synth.row_x(), n_slots=2, hbm_budget=1 << 16)
+    assert srv.submit(f.y, f.z, f.row_off) is None
+    assert srv.bytes_used() == 0
