@@ -79,6 +79,26 @@ def counts_from(trk, frame, res, nr):
                 F=int(res["n_tracks"]), Ha=int(res["n_hits"]), T=int(res["n_tracks"]), nr=nr)
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` (calibrated FETCH_SIZE + WRITE_SIZE) from the
+    committed rocprofv3 summary, or None if the kernels changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tpcsf_cfg3_counters.txt")
+    src = os.path.join(ROOT, "paper_2009_07515_amd", "csrc", "tpcsf_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    rec = {}
+    for ln in open(path):
+        f = ln.split()
+        if f and f[0] == "source_sha256" and f[1] != sha:
+            return None
+        if f and f[0] == "kernel":
+            rec[f[1]] = dict(zip(f[2::2], map(float, f[3::2])))
+    r = rec.get("k_" + kernel)
+    return None if r is None else r["fetch_bytes"] + r["write_bytes"]
+
+
 def cpu_baseline(f, budget_s, max_sectors):
     """The FP64 oracle on whole sectors of the same frame until ~budget_s of CPU time."""
     import oracle
@@ -350,8 +370,8 @@ def main():
         "stages_ms": stages,
         "counts": cnt,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": sb[dom]},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(dom),
+                     "algorithmic_bytes_per_launch": sb[dom], "launch_ms": stages[dom]},
         "path_hbm": {"bytes_per_cluster": path_bytes / N,
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
                      "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
