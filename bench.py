@@ -43,8 +43,8 @@ def stage_bytes(c):
                                                              "T", "nr"))
     return {
         "reset": 0,
-        # read y, z; write sorted (y, z), perm, inverse perm, bin table; clear W and cluster_track
-        "grid": 8 * N + 16 * N + 4 * B + 8 * N,
+        # read y, z; write sorted (y, z), perm, inverse perm, bin table; clear W
+        "grid": 8 * N + 16 * N + 4 * B + 4 * N,
         # read sorted (y, z), perm, bin tables; write up, dn
         "links": 12 * N + 4 * B + 8 * N,
         # read up, dn; write cleaned links; per-row start counts
@@ -52,20 +52,22 @@ def stage_bytes(c):
         "row_scan": 16 * R,
         # read cleaned links and the inverse perm; write (row, position, rank) of every start
         "starts": 12 * N + 12 * S,
-        # read starts and the chain links; write chain rows of the hit table, lengths, order
-        "walk": 8 * S + 4 * C + 2 * C + 8 * S + 4 * K,
-        # read order, start, chain coordinates (twice: fit and refit); write the hit table rows
-        # outside the chain and the tracklet record
-        "tracklets": 16 * K + 16 * Ht + 2 * nr * K,
-        # read tracklet records and tables; read-modify-write one 4-byte weight per cluster
-        "claim": 12 * K + 2 * nr * K + 8 * Hc,
+        # read starts and the chain links; write chain rows of the hit table, lengths
+        "walk": 8 * S + 4 * C + 2 * C + 8 * S,
+        # read start, chain coordinates (twice: fit and refit); write the hit table rows
+        # outside the chain and the tracklet record; claim: read-modify-write one 4-byte
+        # weight per cluster of the tracklets in the selection
+        "tracklets": 16 * K + 16 * Ht + 2 * nr * K + 8 * Hc,
         # read records, tables and weights; write kept masks and the candidate list
         "keep": 12 * K + 2 * nr * K + 4 * Hc + 40 * F,
         # read candidates, masks, kept coordinates (twice); write the fit results
         "fit": 44 * F + 16 * Ha + 2 * Ha + 176 * F,
         "track_scan": 24 * S,
-        # read fit results; write track records, hit lists and the cluster->track map
-        "emit": 176 * T + 48 * T + 8 * Ha + 6 * Ha,
+        # read fit results, hit table entries and perm; write track records and hit lists
+        "emit": 176 * T + 200 * T + 10 * Ha,
+        # read inverse perm and weights, per assigned cluster its track's flag, index and
+        # hit range (once per track); write the cluster->track map
+        "assign": 12 * N + 24 * T,
     }
 
 

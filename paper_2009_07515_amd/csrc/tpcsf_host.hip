@@ -21,17 +21,17 @@ struct Layout {
     size_t total = 0;
     int64_t n = 0, R = 0, cap_starts = 0, cap_fit = 0, n_bins = 0;
     size_t row_lo, row_bin, row_nb, row_f, row_i, row_nstart, row_sbase;
-    size_t bin_start, bin_fill, yz, perm, iperm, upk, dnk, cupk, cdnk, rank_at, W;
-    size_t st_row, st_k, st_rank, tl_len, order, tl_n, tl_rlo, tl_rhi, tl_hits;
-    size_t keep_n, keep_mask, fit_list, buckets;
+    size_t bin_start, yz, perm, iperm, upk, dnk, cupk, cdnk, rank_at, W;
+    size_t st_row, st_k, st_rank, tl_len, tl_n, tl_rlo, tl_rhi, tl_hits;
+    size_t keep_n, keep_mask, fit_list;
     size_t trk_flag, hit_cnt, trk_idx, hit_pos;
     size_t f_par, f_cov, f_chi2, f_xref, scan_part;
     size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n;
 };
 
 constexpr int kStages = 13;
-const char* const kStageNames[kStages] = {"reset", "grid",  "links", "clean", "row_scan",   "starts", "walk",
-                                          "tracklets", "claim", "keep", "fit", "track_scan", "emit"};
+const char* const kStageNames[kStages] = {"reset",     "grid", "links", "clean", "row_scan",   "starts", "walk",
+                                          "tracklets", "keep", "fit",   "track_scan", "emit", "assign"};
 
 struct GraphKey {
     const void* y = nullptr; const void* z = nullptr; const void* off = nullptr;
@@ -47,6 +47,7 @@ struct GraphKey {
 struct tpcsf_ctx {
     int device = 0;
     int n_cu = 256;
+    int grid_lds = 0;               // dynamic LDS bytes of the grid kernel
     int32_t n_sectors = 36, n_rows = 152;
     std::vector<float> row_x;
     double bz = 0.5;
@@ -110,7 +111,6 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.row_nstart = take(R * 8);
     L.row_sbase = take(R * 8);
     L.bin_start = take((size_t)L.n_bins * 4);
-    L.bin_fill = take((size_t)L.n_bins * 4);
     L.yz = take(N * 8);
     L.perm = take(N * 4);
     L.iperm = take(N * 4);
@@ -124,7 +124,6 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.st_k = take(S * 4);
     L.st_rank = take(S * 4);
     L.tl_len = take(S * 4);
-    L.order = take(S * 4);
     L.tl_n = take(S * 4);
     L.tl_rlo = take(S * 2);
     L.tl_rhi = take(S * 2);
@@ -132,7 +131,6 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.keep_n = take(S * 4);
     L.keep_mask = take(S * 4 * 8);
     L.fit_list = take(F * 4);
-    L.buckets = take(sizeof(Buckets));
     L.trk_flag = take(S * 4);
     L.hit_cnt = take(S * 4);
     L.trk_idx = take(S * 8);
@@ -177,6 +175,7 @@ LaunchCfg launch_cfg(const tpcsf_ctx* c)
     L.tl_block = c->tuning.tl_block;
     L.chunk = c->tuning.chunk;
     L.n_cu = c->n_cu;
+    L.grid_lds = c->grid_lds;
     return L;
 }
 
@@ -262,7 +261,6 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.row_f = (float4*)(a + L.row_f);
     B.row_i = (int4*)(a + L.row_i);
     B.bin_start = (uint32_t*)(a + L.bin_start);
-    B.bin_fill = (uint32_t*)(a + L.bin_fill);
     B.yz = (float2*)(a + L.yz);
     B.perm = (uint32_t*)(a + L.perm);
     B.iperm = (uint32_t*)(a + L.iperm);
@@ -276,7 +274,6 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.st_rank = (int32_t*)(a + L.st_rank);
     B.cap_starts = L.cap_starts;
     B.tl_len = (int32_t*)(a + L.tl_len);
-    B.order = (int32_t*)(a + L.order);
     B.tl_n = (int32_t*)(a + L.tl_n);
     B.tl_rlo = (int16_t*)(a + L.tl_rlo);
     B.tl_rhi = (int16_t*)(a + L.tl_rhi);
@@ -284,7 +281,6 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.keep_n = (int32_t*)(a + L.keep_n);
     B.keep_mask = (uint64_t*)(a + L.keep_mask);
     B.fit_list = (int32_t*)(a + L.fit_list);
-    B.bk = (Buckets*)(a + L.buckets);
     B.f_par = (double*)(a + L.f_par);
     B.f_cov = (double*)(a + L.f_cov);
     B.f_chi2 = (double*)(a + L.f_chi2);
@@ -330,11 +326,11 @@ void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t
     mark(); launch_starts(B, P, 0, R, LC, s);
     mark(); launch_walk(B, P, LC, s);
     mark(); launch_tracklets(B, P, LC, s);
-    mark(); launch_claim(B, P, LC, s);
     mark(); launch_keep(B, P, LC, s);
     mark(); launch_fit(B, P, LC, s);
     mark(); launch_track_scan(B, s);
     mark(); launch_emit(B, P, LC, s);
+    mark(); launch_assign(B, P, 0, R, LC, s);
     mark();
 }
 
@@ -398,6 +394,7 @@ tpcsf_status tpcsf_create(const tpcsf_geometry* geo, const tpcsf_params* params,
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, c->device)) != hipSuccess) { delete c; return TPCSF_E_HIP; }
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->grid_lds = grid_lds_setup((int)prop.sharedMemPerBlock);
     if ((e = hipMalloc(&c->d_rx, sizeof(float) * c->n_rows)) != hipSuccess) { delete c; return TPCSF_E_NOMEM; }
     if ((e = hipMalloc(&c->d_ctr, sizeof(Counters))) != hipSuccess) {
         (void)hipFree(c->d_rx);
@@ -471,11 +468,11 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
             launch_starts(B, P, g0, g1, LC, s);
             launch_walk(B, P, LC, s);
             launch_tracklets(B, P, LC, s);
-            launch_claim(B, P, LC, s);
             launch_keep(B, P, LC, s);
             launch_fit(B, P, LC, s);
             launch_track_scan(B, s);
             launch_emit(B, P, LC, s);
+            launch_assign(B, P, g0, g1, LC, s);
         }
     c->last = B;
     c->have_last = true;

@@ -35,20 +35,10 @@ struct Counters {
     int64_t rank_lo, rank_hi;       // rank range of the starts of the current launch set
     int64_t track_base;             // tracks emitted so far
     int64_t hit_base;               // hits emitted so far
-    int32_t n_order;                // tracklets to build (chains of >= min_chain)
     int32_t n_fit;                  // tracks to fit (>= min_track_hits kept)
     int32_t queue;                  // tracklet work-queue head
     int32_t err;                    // error bits
     unsigned long long hash;        // output digest (autotuner's result-invariance check)
-};
-
-// Length buckets used to order variable-length work (longest first): histogram, fill
-// counters and offsets, one set for chains and one for kept cluster counts.
-constexpr int kBuckets = kMaxRows + 1;
-struct Buckets {
-    int32_t hist[2][kBuckets];
-    int32_t fill[2][kBuckets];
-    int32_t off[2][kBuckets];
 };
 
 // Device pointers of one batch: inputs, arena and outputs.
@@ -73,7 +63,6 @@ struct Batch {
     float4* row_f;                  // [R] y_lo, z_lo, 1/b_y, 1/b_z (search records)
     int4* row_i;                    // [R] first cluster, count, ny, nz
     uint32_t* bin_start;            // [cap_mul*N + (cap_add+1)*R]
-    uint32_t* bin_fill;             // same size
     float2* yz;                     // [N] sorted (y, z)
     uint32_t* perm;                 // [N] sorted position -> in-row index
     uint32_t* iperm;                // [N] in-row index -> sorted position
@@ -90,12 +79,11 @@ struct Batch {
     int64_t cap_starts;
     // tracklets (p indexed); hit table H[p * n_rows + r]
     int32_t* tl_len;                // chain length
-    int32_t* order;                 // [cap_starts] tracklets to build, longest chain first
     int32_t* tl_n;                  // clusters, 0 = none
     int16_t* tl_rlo;                // first row holding a cluster
     int16_t* tl_rhi;                // last row holding a cluster
     uint16_t* tl_hits;              // sorted position per row, kNoHit if none
-    // keep and final fit: candidates listed densely, most kept clusters first
+    // keep and final fit: candidates listed densely
     int32_t* keep_n;                // [cap_starts] (p indexed) kept clusters, 0 = not a track
     uint64_t* keep_mask;            // [cap_starts][4] (p indexed) kept rows
     int32_t* fit_list;              // [cap_fit] p of every candidate
@@ -104,7 +92,6 @@ struct Batch {
     double* f_chi2;                 // [cap_fit]
     double* f_xref;                 // [cap_fit]
     int32_t cap_fit;
-    Buckets* bk;
     // rank indexed
     int32_t* trk_flag;              // 1 = accepted and fitted
     int32_t* hit_cnt;               // kept clusters of accepted tracks
@@ -131,9 +118,12 @@ struct LaunchCfg {
     int tl_block;   // tracklet kernels
     int chunk;      // starts per lane taken from the queue
     int n_cu;       // compute units
+    int grid_lds;   // dynamic LDS bytes of the grid kernel
 };
 
 // Stage launchers (all asynchronous on `stream`).  Row ranges are [g0, g1).
+// Allows the grid kernel the device's LDS per block; returns the dynamic LDS bytes to use.
+int grid_lds_setup(int max_lds_per_block);
 void launch_reset(const Batch& b, hipStream_t s);
 void launch_grid(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
 void launch_links(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
@@ -142,11 +132,11 @@ void launch_row_scan(const Batch& b, int64_t g0, int64_t g1, hipStream_t s);
 void launch_starts(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
 void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
-void launch_claim(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_track_scan(const Batch& b, hipStream_t s);
 void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
+void launch_assign(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
 void launch_debug_views(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_hash(const Batch& b, int64_t n_clusters, const LaunchCfg& c, hipStream_t s);
 

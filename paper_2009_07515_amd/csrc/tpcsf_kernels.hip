@@ -104,8 +104,6 @@ __device__ __forceinline__ int bin_of(float v, float lo, float b, int nb)
 // ------------------------------------------------------------------------------------
 __global__ void k_reset(Batch B)
 {
-    int32_t* bk = &B.bk->hist[0][0];
-    for (int i = threadIdx.x; i < 4 * kBuckets; i += blockDim.x) bk[i] = 0;   // hist and fill
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         Counters* c = B.ctr;
         c->start_base = 0;
@@ -113,7 +111,6 @@ __global__ void k_reset(Batch B)
         c->rank_hi = 0;
         c->track_base = 0;
         c->hit_base = 0;
-        c->n_order = 0;
         c->n_fit = 0;
         c->queue = 0;
         *B.o_ntracks = 0;
@@ -123,32 +120,70 @@ __global__ void k_reset(Batch B)
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 1, grid (binary32).  One wave per row.  Extents are exact minima/maxima;
+// Stage 1, grid (binary32).  One block per row.  Extents are exact minima/maxima;
 // ny = 1 + trunc((y_hi - y_lo)/b_y), nz alike; while ny*nz > cap_mul*n + cap_add the z bin
 // (once nz == 1 the y bin) doubles.  Clusters are ordered by bin iz*ny + iy, ties by
-// in-row index (stable counting sort: histogram, scan, then placement chunk by chunk in
-// index order, each chunk ranked inside the wave by a ballot match on the bin key).
-// Writes the sorted (y, z) pairs, perm (sorted -> in-row index) and its inverse.  The
-// same pass clears the selection weights and the cluster->track map of the row.
+// in-row index (a stable counting sort).
+//
+// The sort runs in LDS: bin counts by LDS atomics, an in-place block scan, placement by
+// LDS atomics (arbitrary order inside a bin), then every bin is put in index order by an
+// insertion sort (bins hold a few clusters).  All global writes are then row-contiguous:
+// sorted (y, z), perm (sorted -> in-row index), the bin table, and the inverse
+// permutation inside the row.  A row whose tables do not fit in LDS takes the same steps
+// on the global bin table, ordered chunk by chunk by one wave (a ballot match on the bin
+// key ranks equal keys inside a chunk).  The same pass clears the selection weights of
+// the row.
 // ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0, int64_t g1)
+constexpr int kGridThreads = 1024;
+constexpr int kGridStaticLds = 1024;    // bytes reserved for the kernel's static LDS
+constexpr int kGridMaxLdsBin = 64;      // largest bin ordered by the in-LDS insertion sort
+
+__device__ __forceinline__ uint32_t grid_key(float y, float z, float ylo, float zlo, float by, float bz, int ny,
+                                             int nz)
+{
+    return (uint32_t)(bin_of(z, zlo, bz, nz) * ny + bin_of(y, ylo, by, ny));
+}
+
+// In-place exclusive scan of a[0, m) in LDS by the whole block (sums < 2^31).
+__device__ void block_excl_scan_lds(uint32_t* a, int m, int* tmp /*[17]*/)
+{
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int seg = (m + nt - 1) / nt;
+    const int s0 = min(m, t * seg), s1 = min(m, s0 + seg);
+    uint32_t sum = 0;
+    for (int i = s0; i < s1; ++i) sum += a[i];
+    int total;
+    uint32_t run = (uint32_t)block_excl_scan((int)sum, &total, tmp);
+    for (int i = s0; i < s1; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kGridThreads) k_grid(Batch B, DevParams P, int64_t g0, int64_t g1, int lds_bytes)
 {
 #pragma clang fp contract(off)
-    const int lane = lane_id();
-    const int wpb = blockDim.x >> 6;
-    const int64_t nwaves = (int64_t)gridDim.x * wpb;
-    for (int64_t g = g0 + (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); g < g1; g += nwaves) {
+    extern __shared__ uint32_t sm[];
+    __shared__ float red[4][16];
+    __shared__ int badw[16];
+    __shared__ int tmp[17];
+    __shared__ uint32_t maxbin;
+    const int t = threadIdx.x, nt = blockDim.x, lane = lane_id(), w = t >> 6, nw = nt >> 6;
+    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
+        const float* yr = B.y + base;
+        const float* zr = B.z + base;
         float ylo = INFINITY, yhi = -INFINITY, zlo = INFINITY, zhi = -INFINITY;
         bool bad = false;
-        for (int i = lane; i < n; i += 64) {
-            const float y = B.y[base + i], z = B.z[base + i];
+        for (int i = t; i < n; i += nt) {
+            const float y = yr[i], z = zr[i];
             bad |= !(fabsf(y) <= 1.0e5f) || !(fabsf(z) <= 1.0e5f);
             ylo = fminf(ylo, y); yhi = fmaxf(yhi, y);
             zlo = fminf(zlo, z); zhi = fmaxf(zhi, z);
             B.W[base + i] = 0u;
-            B.o_cluster_track[base + i] = -1;
         }
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
@@ -157,8 +192,20 @@ __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0,
             zlo = fminf(zlo, __shfl_xor(zlo, d, 64));
             zhi = fmaxf(zhi, __shfl_xor(zhi, d, 64));
         }
-        if (__ballot(bad) != 0ull) {
-            if (lane == 0) atomicOr(&B.ctr->err, kErrInvalid);
+        const bool wbad = __ballot(bad) != 0ull;
+        if (lane == 0) {
+            red[0][w] = ylo; red[1][w] = yhi; red[2][w] = zlo; red[3][w] = zhi;
+            badw[w] = wbad ? 1 : 0;
+        }
+        __syncthreads();
+        bad = false;
+        for (int j = 0; j < nw; ++j) {
+            ylo = fminf(ylo, red[0][j]); yhi = fmaxf(yhi, red[1][j]);
+            zlo = fminf(zlo, red[2][j]); zhi = fmaxf(zhi, red[3][j]);
+            bad |= badw[j] != 0;
+        }
+        if (bad) {
+            if (t == 0) atomicOr(&B.ctr->err, kErrInvalid);
             ylo = yhi = zlo = zhi = 0.0f;   // keep every index in range; the call reports the error
         }
         if (n == 0) ylo = yhi = zlo = zhi = 0.0f;
@@ -178,7 +225,7 @@ __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0,
                 }
             }
         }
-        if (lane == 0) {
+        if (t == 0) {
             B.row_lo[g] = make_float2(ylo, zlo);
             B.row_bin[g] = make_float2(by, bz);
             B.row_nb[g] = make_int2(ny, nz);
@@ -187,46 +234,104 @@ __global__ void __launch_bounds__(1024) k_grid(Batch B, DevParams P, int64_t g0,
         }
         const int nb = ny * nz;
         uint32_t* bs = B.bin_start + bin_base(P, base, g);
-        uint32_t* bf = B.bin_fill + bin_base(P, base, g);
-        for (int b = lane; b <= nb; b += 64) {
-            st_rlx(bs + b, 0u);
-            st_rlx(bf + b, 0u);
+        // LDS: counts / cursors [nb + 1] (u32), then the placement [n] (u16)
+        bool in_lds = n <= 65535 && 4 * (int64_t)(nb + 1) + 2 * (int64_t)n <= (int64_t)lds_bytes;
+        uint32_t* cnt = sm;
+        uint16_t* pl = (uint16_t*)(sm + nb + 1);
+        if (in_lds) {
+            for (int b = t; b <= nb; b += nt) cnt[b] = 0u;
+            if (t == 0) maxbin = 0;
+            __syncthreads();
+            uint32_t mx = 0;
+            for (int i = t; i < n; i += nt)
+                mx = max(mx, atomicAdd(&cnt[grid_key(yr[i], zr[i], ylo, zlo, by, bz, ny, nz)], 1u) + 1u);
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
+            if (lane == 0) atomicMax(&maxbin, mx);
+            __syncthreads();
+            // the in-bin insertion sort is quadratic: a crowded bin takes the global path
+            in_lds = maxbin <= (uint32_t)kGridMaxLdsBin;
         }
-        wave_mem_fence();
-        for (int i = lane; i < n; i += 64) {
-            const int bin = bin_of(B.z[base + i], zlo, bz, nz) * ny + bin_of(B.y[base + i], ylo, by, ny);
-            atomicAdd(bs + bin + 1, 1u);
-        }
-        wave_mem_fence();
-        uint32_t carry = 0;
-        for (int b0 = 0; b0 < nb; b0 += 64) {
-            const int b = b0 + lane;
-            const uint32_t v = (b < nb) ? ld_rlx(bs + 1 + b) : 0u;
-            const uint32_t inc = wave_incl_scan(v) + carry;
-            if (b < nb) st_rlx(bs + 1 + b, inc);
-            carry = __shfl(inc, 63, 64);
-        }
-        wave_mem_fence();
-        const int nbits = 32 - __clz(nb > 1 ? nb - 1 : 1);
-        for (int i0 = 0; i0 < n; i0 += 64) {
-            const int i = i0 + lane;
-            const bool valid = i < n;
-            const float y = valid ? B.y[base + i] : 0.0f;
-            const float z = valid ? B.z[base + i] : 0.0f;
-            const uint32_t bin = valid ? (uint32_t)(bin_of(z, zlo, bz, nz) * ny + bin_of(y, ylo, by, ny)) : 0u;
-            const uint64_t eq = match_eq(bin, valid, nbits);
-            const int rank = __popcll(eq & lanemask_lt());
-            const int leader = valid ? (__ffsll((unsigned long long)eq) - 1) : 0;
-            uint32_t old = 0;
-            if (valid && lane == leader) old = atomicAdd(bf + bin, (uint32_t)__popcll(eq));
-            old = __shfl(old, leader, 64);
-            if (valid) {
-                const uint32_t pos = ld_rlx(bs + bin) + old + (uint32_t)rank;
-                B.yz[base + pos] = make_float2(y, z);
-                B.perm[base + pos] = (uint32_t)i;
-                B.iperm[base + i] = pos;
+        if (in_lds) {
+            block_excl_scan_lds(cnt, nb + 1, tmp);     // cnt[b] = first slot of bin b, cnt[nb] = n
+            for (int b = t; b <= nb; b += nt) bs[b] = cnt[b];
+            __syncthreads();
+            for (int i = t; i < n; i += nt) {
+                const uint32_t pos = atomicAdd(&cnt[grid_key(yr[i], zr[i], ylo, zlo, by, bz, ny, nz)], 1u);
+                pl[pos] = (uint16_t)i;
+            }
+            __syncthreads();
+            // cnt[b] is now the end of bin b; order each bin by in-row index
+            for (int b = t; b < nb; b += nt) {
+                const int s = b ? (int)cnt[b - 1] : 0, e = (int)cnt[b];
+                for (int a = s + 1; a < e; ++a) {
+                    const uint16_t v = pl[a];
+                    int c = a;
+                    while (c > s && pl[c - 1] > v) {
+                        pl[c] = pl[c - 1];
+                        --c;
+                    }
+                    pl[c] = v;
+                }
+            }
+            __syncthreads();
+            for (int k = t; k < n; k += nt) {
+                const uint32_t i = pl[k];
+                B.yz[base + k] = make_float2(yr[i], zr[i]);
+                B.perm[base + k] = i;
+                B.iperm[base + i] = (uint32_t)k;
+            }
+        } else {
+            __syncthreads();
+            for (int b = t; b <= nb; b += nt) st_rlx(bs + b, 0u);
+            __threadfence();
+            __syncthreads();
+            for (int i = t; i < n; i += nt) atomicAdd(bs + grid_key(yr[i], zr[i], ylo, zlo, by, bz, ny, nz), 1u);
+            __threadfence();
+            __syncthreads();
+            if (w == 0) {
+                uint32_t carry = 0;   // exclusive scan: bs[b] = first slot of bin b, bs[nb] = n
+                for (int b0 = 0; b0 <= nb; b0 += 64) {
+                    const int b = b0 + lane;
+                    const uint32_t v = (b <= nb) ? ld_rlx(bs + b) : 0u;
+                    const uint32_t inc = wave_incl_scan(v) + carry;
+                    if (b <= nb) st_rlx(bs + b, inc - v);
+                    carry = __shfl(inc, 63, 64);
+                }
+                wave_mem_fence();
+                const int nbits = 32 - __clz(nb > 1 ? nb - 1 : 1);
+                for (int i0 = 0; i0 < n; i0 += 64) {
+                    const int i = i0 + lane;
+                    const bool valid = i < n;
+                    const float y = valid ? yr[i] : 0.0f;
+                    const float z = valid ? zr[i] : 0.0f;
+                    const uint32_t bin = valid ? grid_key(y, z, ylo, zlo, by, bz, ny, nz) : 0u;
+                    const uint64_t eq = match_eq(bin, valid, nbits);
+                    const int rank = __popcll(eq & lanemask_lt());
+                    const int leader = valid ? (__ffsll((unsigned long long)eq) - 1) : 0;
+                    uint32_t old = 0;
+                    if (valid && lane == leader) old = atomicAdd(bs + bin, (uint32_t)__popcll(eq));
+                    old = __shfl(old, leader, 64);
+                    if (valid) {
+                        const uint32_t pos = old + (uint32_t)rank;
+                        B.yz[base + pos] = make_float2(y, z);
+                        B.perm[base + pos] = (uint32_t)i;
+                        B.iperm[base + i] = pos;
+                    }
+                }
+                wave_mem_fence();
+                // bs[b] is now the end of bin b: shift up by one bin to restore the starts,
+                // descending so that every value is read before it is overwritten
+                for (int hi = nb - 1; hi >= 1; hi -= 64) {
+                    const int b = hi - lane;
+                    const uint32_t v = (b >= 1) ? ld_rlx(bs + b - 1) : 0u;
+                    if (b >= 1) st_rlx(bs + b, v);
+                    wave_mem_fence();
+                }
+                if (lane == 0) st_rlx(bs, 0u);
             }
         }
+        __syncthreads();
     }
 }
 
@@ -822,28 +927,6 @@ __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const T
 }
 
 // ------------------------------------------------------------------------------------
-// Length buckets: variable-length work is processed longest first, so that the lanes of
-// a wave carry work of similar length.  Processing order never changes a result.
-// ------------------------------------------------------------------------------------
-__global__ void k_bucket_scan(Batch B, int which, int n_buckets)
-{
-    // one block: offsets for descending length, total, then clear the histogram and fill
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int L = n_buckets - 1; L >= 0; --L) {
-            B.bk->off[which][L] = run;
-            run += B.bk->hist[which][L];
-        }
-        if (which == 0) B.ctr->n_order = run; else B.ctr->n_fit = run;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) {
-        B.bk->hist[which][i] = 0;
-        B.bk->fill[which][i] = 0;
-    }
-}
-
-// ------------------------------------------------------------------------------------
 // Stage 5a, chains: walk the cleaned up-links from every start (one lane each), record
 // the chain in the tracklet's hit table and its length; chains of >= min_chain clusters
 // become tracklets.
@@ -858,6 +941,7 @@ __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
     const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     const int nr = P.n_rows;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctr->n_fit = 0;   // candidates of this launch set
     for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
         const int64_t g = B.st_row[p];
         const int r0 = (int)(g % nr);
@@ -897,6 +981,21 @@ __device__ int follow(const Batch& B, const DevParams& P, Trk& t, int64_t gs, in
         }
     }
     return added;
+}
+
+// ------------------------------------------------------------------------------------
+// Stage 6, selection.  A tracklet's weight orders tracklets by (clusters, then smaller
+// rank); every cluster ends with the largest weight of the tracklets that contain it
+// (atomic max, order independent).  The claim is made by the lane that built the
+// tracklet, right after building it.  Weights are only ever compared within a sector, so
+// the rank counts from the sector's first start: w = (n << 24) | (2^24 - 1 - rank_s)
+// (n <= 255, rank_s < 2^24 since a sector holds < 2^24 starts).  Tracklets shorter than
+// min_track_hits can neither be accepted nor outweigh a longer one and do not take part.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P, int n, int64_t rank, int64_t gs)
+{
+    const int64_t rs = rank - B.row_sbase[gs];
+    return ((uint32_t)n << 24) | (0xFFFFFFu - (uint32_t)rs);
 }
 
 // ------------------------------------------------------------------------------------
@@ -946,9 +1045,16 @@ __device__ void build_tracklet(const Batch& B, const DevParams& P, int64_t p)
         }
     }
     if (ok) n += follow(B, P, tr, gs, r0 - 1, -1, -1, p, &rlo);
-    B.tl_n[p] = ok ? n : 0;
+    if (!ok) n = 0;
+    B.tl_n[p] = n;
     B.tl_rlo[p] = (int16_t)rlo;
     B.tl_rhi[p] = (int16_t)rhi;
+    if (n < P.min_track_hits) return;
+    const uint32_t w = weight_of(B, P, n, B.st_rank[p], gs);
+    for (int r = rlo; r <= rhi; ++r) {
+        const uint16_t k = *hit_slot(B, r, p);
+        if (k != kNoHit) atomicMax(&B.W[B.off[gs + r] + k], w);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int chunk)
@@ -970,90 +1076,54 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int chu
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 6, selection.  A tracklet's weight orders tracklets by (clusters, then smaller
-// rank); every cluster ends with the largest weight of the tracklets that contain it
-// (atomic max, order independent).  Weights are only ever compared within a sector, so
-// the rank counts from the sector's first start: w = (n << 24) | (2^24 - 1 - rank_s)
-// (n <= 255, rank_s < 2^24 since a sector holds < 2^24 starts).  Tracklets shorter than
-// min_track_hits can neither be accepted nor outweigh a longer one and do not take part.
-// ------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P, int n, int64_t rank, int64_t gs)
-{
-    const int64_t rs = rank - B.row_sbase[gs];
-    return ((uint32_t)n << 24) | (0xFFFFFFu - (uint32_t)rs);
-}
-
-__global__ void __launch_bounds__(256) k_claim(Batch B, DevParams P)
-{
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
-    const int nr = P.n_rows;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctr->queue = 0;   // the tracklet queue is done
-    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
-        const int n = B.tl_n[p];
-        if (n < P.min_track_hits) continue;
-        const int64_t g = B.st_row[p];
-        const int64_t gs = g - g % nr;
-        const uint32_t w = weight_of(B, P, n, B.st_rank[p], gs);
-        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
-        for (int r = rlo; r <= rhi; ++r) {
-            const uint16_t k = *hit_slot(B, r, p);
-            if (k != kNoHit) atomicMax(&B.W[B.off[gs + r] + k], w);
-        }
-    }
-}
-
-// ------------------------------------------------------------------------------------
 // Stage 7a, keep: a tracklet keeps the clusters that carry its own weight and is a track
-// candidate if it keeps >= min_track_hits; candidates are listed, most clusters first.
+// candidate if it keeps >= min_track_hits.  Candidates are listed with one atomic per
+// wave, so the list stays in processing order within each wave's 64 tracklets.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
 {
-    __shared__ int32_t hist[kBuckets];
-    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) hist[i] = 0;
-    __syncthreads();
     const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     const int nr = P.n_rows;
+    const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
-        const int64_t rank = B.st_rank[p];
-        B.trk_flag[rank] = 0;
-        B.hit_cnt[rank] = 0;
-        B.keep_n[p] = 0;
-        const int n = B.tl_n[p];
-        if (n < P.min_track_hits) continue;
-        const int64_t g = B.st_row[p];
-        const int64_t gs = g - g % nr;
-        const uint32_t w = weight_of(B, P, n, rank, gs);
-        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
-        uint64_t m[4] = {0, 0, 0, 0};
-        int kept = 0;
-        for (int r = rlo; r <= rhi; ++r) {
-            const uint16_t k = *hit_slot(B, r, p);
-            if (k == kNoHit) continue;
-            if (B.W[B.off[gs + r] + k] == w) {
-                m[r >> 6] |= 1ull << (r & 63);
-                ++kept;
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctr->queue = 0;   // the tracklet queue is done
+    // wave-uniform loop: every lane of a wave takes part in each compaction
+    for (int64_t p0 = lo + (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); p0 < hi; p0 += stride) {
+        const int64_t p = p0 + lane;
+        bool cand = false;
+        if (p < hi) {
+            const int64_t rank = B.st_rank[p];
+            B.trk_flag[rank] = 0;
+            B.hit_cnt[rank] = 0;
+            const int n = B.tl_n[p];
+            if (n >= P.min_track_hits) {
+                const int64_t g = B.st_row[p];
+                const int64_t gs = g - g % nr;
+                const uint32_t w = weight_of(B, P, n, rank, gs);
+                const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
+                uint64_t m[4] = {0, 0, 0, 0};
+                int kept = 0;
+                for (int r = rlo; r <= rhi; ++r) {
+                    const uint16_t k = *hit_slot(B, r, p);
+                    if (k == kNoHit) continue;
+                    if (B.W[B.off[gs + r] + k] == w) {
+                        m[r >> 6] |= 1ull << (r & 63);
+                        ++kept;
+                    }
+                }
+                if (kept >= P.min_track_hits) {
+                    for (int i = 0; i < 4; ++i) B.keep_mask[p * 4 + i] = m[i];
+                    B.keep_n[p] = kept;
+                    cand = true;
+                }
             }
         }
-        if (kept < P.min_track_hits) continue;
-        for (int i = 0; i < 4; ++i) B.keep_mask[p * 4 + i] = m[i];
-        B.keep_n[p] = kept;
-        atomicAdd(&hist[kept], 1);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
-        if (hist[i]) atomicAdd(&B.bk->hist[1][i], hist[i]);
-}
-
-__global__ void __launch_bounds__(256) k_keep_list(Batch B, DevParams P)
-{
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
-        const int kept = B.keep_n[p];
-        if (kept < P.min_track_hits) continue;
-        B.fit_list[B.bk->off[1][kept] + atomicAdd(&B.bk->fill[1][kept], 1)] = (int32_t)p;
+        const uint64_t bal = __ballot(cand);
+        if (bal == 0ull) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&B.ctr->n_fit, __popcll(bal));
+        base = __shfl(base, 0, 64);
+        if (cand) B.fit_list[base + __popcll(bal & lanemask_lt())] = (int32_t)p;
     }
 }
 
@@ -1135,7 +1205,7 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 
 // ------------------------------------------------------------------------------------
 // Stage 8, emit: tracks at their scanned positions (rank order), hits inner to outer as
-// input cluster indices, cluster -> track map.  Writes beyond the caller's capacity are
+// input cluster indices.  Writes beyond the caller's capacity are
 // dropped and flagged.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
@@ -1170,9 +1240,35 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
         for (int r = rlo; r <= rhi; ++r) {
             if (!((B.keep_mask[p * 4 + (r >> 6)] >> (r & 63)) & 1ull)) continue;
             const int64_t first = B.off[gs + r];
-            const int64_t gi = first + B.perm[first + *hit_slot(B, r, p)];
-            B.o_hit_ids[j++] = (int32_t)gi;
-            B.o_cluster_track[gi] = (int32_t)T;
+            B.o_hit_ids[j++] = (int32_t)(first + B.perm[first + *hit_slot(B, r, p)]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Stage 9, cluster -> track map, per cluster in input order.  A cluster belongs to the
+// track whose weight it carries (the kept clusters of a track are exactly those), so the
+// weight names the tracklet by its rank within the sector; the map is -1 where that
+// tracklet was not accepted or its track was not written.
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_assign(Batch B, DevParams P, int64_t g0, int64_t g1)
+{
+    const int nr = P.n_rows;
+    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+        const int64_t base = B.off[g];
+        const int n = (int)(B.off[g + 1] - base);
+        const int64_t sbase = B.row_sbase[g - g % nr];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t w = B.W[base + B.iperm[base + i]];
+            int32_t T = -1;
+            if (w != 0u) {
+                const int64_t rank = sbase + (int64_t)(0xFFFFFFu - (w & 0xFFFFFFu));
+                if (B.trk_flag[rank]) {
+                    const int64_t t = B.trk_idx[rank];
+                    if (t < B.cap_tracks && B.hit_pos[rank] + B.hit_cnt[rank] <= B.cap_hits) T = (int32_t)t;
+                }
+            }
+            B.o_cluster_track[base + i] = T;
         }
     }
 }
@@ -1273,10 +1369,21 @@ void launch_reset(const Batch& b, hipStream_t s)
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, b);
 }
 
+int grid_lds_setup(int max_lds_per_block)
+{
+    int dyn = max_lds_per_block - kGridStaticLds;
+    if (dyn < 0) dyn = 0;
+    if (hipFuncSetAttribute((const void*)k_grid, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
+        (void)hipGetLastError();
+        dyn = 65536 - kGridStaticLds;
+    }
+    return dyn;
+}
+
 void launch_grid(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s)
 {
-    const int wpb = c.block / 64;
-    hipLaunchKernelGGL(k_grid, dim3(grid_for(g1 - g0, wpb, 1 << 16)), dim3(c.block), 0, s, b, p, g0, g1);
+    hipLaunchKernelGGL(k_grid, dim3(grid_for(g1 - g0, 1, 1 << 16)), dim3(kGridThreads), (size_t)c.grid_lds, s, b, p,
+                       g0, g1, c.grid_lds);
 }
 
 void launch_links(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s)
@@ -1322,16 +1429,9 @@ void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hi
     hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(c.tl_block), 0, s, b, p, c.chunk);
 }
 
-void launch_claim(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_claim, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
-}
-
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_keep, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, s, b, 1, p.n_rows + 1);
-    hipLaunchKernelGGL(k_keep_list, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
@@ -1359,6 +1459,11 @@ void launch_track_scan(const Batch& b, hipStream_t s)
 void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_emit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+}
+
+void launch_assign(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_assign, dim3(grid_for(g1 - g0, 1, 1 << 16)), dim3(256), 0, s, b, p, g0, g1);
 }
 
 void launch_hash(const Batch& b, int64_t n_clusters, const LaunchCfg& c, hipStream_t s)

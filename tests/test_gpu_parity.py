@@ -168,12 +168,23 @@ def test_edge_cases(row_x):
     assert res["n_tracks"] == 0 and res["n_hits"] == 0
     # single clusters, all in one row, and a frame of pure noise
     rng = np.random.Generator(np.random.PCG64(3))
+    # a row too large for the grid's on-chip tables, and rows with a crowded bin
+    # (hundreds of identical clusters, and a handful of duplicates) beside ordinary rows
+    big = np.eye(1, R, 200, dtype=np.int64)[0] * 40000
+    crowd = rng.integers(0, 6, R)
+    crowd[300:303] = 700
     for counts in (np.ones(R, np.int64), np.eye(1, R, 77, dtype=np.int64)[0] * 3000,
-                   rng.integers(0, 6, R)):
+                   rng.integers(0, 6, R), big, crowd):
         n = int(counts.sum())
         ro = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
         y = rng.uniform(-15, 15, n).astype(np.float32)
         z = rng.uniform(-250, 250, n).astype(np.float32)
+        if counts is big:
+            z *= 10.0        # 40000 bins: more than the on-chip tables hold
+        if counts is crowd:
+            for g, k in ((300, 500), (301, 60), (302, 66)):
+                y[ro[g]:ro[g] + k] = 1.25
+                z[ro[g]:ro[g] + k] = -7.5
         res = _np(trk.track(tpcsf.DeviceFrame.from_numpy(y, z, ro)))
         dbg = trk.debug(tpcsf.DeviceFrame.from_numpy(y, z, ro))
         ref = oracle.Oracle(row_x).track_frame(y, z, ro, debug=True)
