@@ -80,8 +80,9 @@ typedef struct {
  *   bin_y, bin_z: grid bin size (cm); a row of n clusters gets at most cap_mul*n+cap_add
  *   bins (the z bin, then the y bin, doubles until it fits).
  *   block: threads per block of the row kernels (64..1024, multiple of 64).
- *   tl_block: threads per block of the tracklet kernel (64..1024, multiple of 64).
- *   chunk: starts a wave takes from the work queue at a time (>= 1). */
+ *   tl_block: threads per block of the tracklet kernel (64..256, multiple of 64).
+ *   chunk: idle lanes at which a tracklet wave takes new work from the queue (1..64;
+ *   a wave with no busy lane always takes work). */
 typedef struct {
     float bin_y, bin_z;
     int32_t cap_mul, cap_add;

@@ -23,8 +23,8 @@ struct Layout {
     size_t row_lo, row_bin, row_nb, row_f, row_i, row_nstart, row_sbase;
     size_t bin_start, yz, perm, iperm, upk, dnk, cupk, cdnk, rank_at, W;
     size_t st_row, st_k, st_rank, tl_len, tl_n, tl_rlo, tl_rhi, tl_hits;
-    size_t keep_n, keep_mask, fit_list;
-    size_t trk_flag, hit_cnt, trk_idx, hit_pos;
+    size_t keep_n, fit_pos, keep_mask, fit_list;
+    size_t trk_flag, hit_cnt, trk_idx, hit_pos, trk_out;
     size_t f_par, f_cov, f_chi2, f_xref, scan_part;
     size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n;
 };
@@ -129,12 +129,14 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.tl_rhi = take(S * 2);
     L.tl_hits = take(S * (size_t)c->n_rows * 2);
     L.keep_n = take(S * 4);
+    L.fit_pos = take(S * 8);
     L.keep_mask = take(S * 4 * 8);
     L.fit_list = take(F * 4);
     L.trk_flag = take(S * 4);
     L.hit_cnt = take(S * 4);
     L.trk_idx = take(S * 8);
     L.hit_pos = take(S * 8);
+    L.trk_out = take(S * 4);
     L.f_par = take(F * 5 * 8);
     L.f_cov = take(F * 15 * 8);
     L.f_chi2 = take(F * 8);
@@ -184,7 +186,7 @@ bool tuning_ok(const tpcsf_tuning* t)
     return t && t->bin_y >= 1e-3f && t->bin_z >= 1e-3f && t->bin_y <= 1e5f && t->bin_z <= 1e5f &&
            t->cap_mul >= 1 && t->cap_mul <= 64 && t->cap_add >= 1 && t->cap_add <= 4096 &&
            t->block >= 64 && t->block <= 1024 && t->block % 64 == 0 && t->tl_block >= 64 &&
-           t->tl_block <= 1024 && t->tl_block % 64 == 0 && t->chunk >= 1 && t->chunk <= 64;
+           t->tl_block <= 256 && t->tl_block % 64 == 0 && t->chunk >= 1 && t->chunk <= 64;
 }
 
 bool params_ok(const tpcsf_params* p)
@@ -279,6 +281,7 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.tl_rhi = (int16_t*)(a + L.tl_rhi);
     B.tl_hits = (uint16_t*)(a + L.tl_hits);
     B.keep_n = (int32_t*)(a + L.keep_n);
+    B.fit_pos = (int64_t*)(a + L.fit_pos);
     B.keep_mask = (uint64_t*)(a + L.keep_mask);
     B.fit_list = (int32_t*)(a + L.fit_list);
     B.f_par = (double*)(a + L.f_par);
@@ -290,6 +293,7 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.hit_cnt = (int32_t*)(a + L.hit_cnt);
     B.trk_idx = (int64_t*)(a + L.trk_idx);
     B.hit_pos = (int64_t*)(a + L.hit_pos);
+    B.trk_out = (int32_t*)(a + L.trk_out);
     B.W = (uint32_t*)(a + L.W);
     B.scan_part = (int64_t*)(a + L.scan_part);
     B.ctr = c->d_ctr;
@@ -327,6 +331,7 @@ void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t
     mark(); launch_walk(B, P, LC, s);
     mark(); launch_tracklets(B, P, LC, s);
     mark(); launch_keep(B, P, LC, s);
+    launch_fit_scan(B, P, s);
     mark(); launch_fit(B, P, LC, s);
     mark(); launch_track_scan(B, s);
     mark(); launch_emit(B, P, LC, s);
@@ -469,6 +474,7 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
             launch_walk(B, P, LC, s);
             launch_tracklets(B, P, LC, s);
             launch_keep(B, P, LC, s);
+            launch_fit_scan(B, P, s);
             launch_fit(B, P, LC, s);
             launch_track_scan(B, s);
             launch_emit(B, P, LC, s);

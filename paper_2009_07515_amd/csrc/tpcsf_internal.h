@@ -35,8 +35,9 @@ struct Counters {
     int64_t rank_lo, rank_hi;       // rank range of the starts of the current launch set
     int64_t track_base;             // tracks emitted so far
     int64_t hit_base;               // hits emitted so far
-    int32_t n_fit;                  // tracks to fit (>= min_track_hits kept)
-    int32_t queue;                  // tracklet work-queue head
+    int64_t n_fit;                  // track candidates (>= min_track_hits kept)
+    int32_t queue[8];               // tracklet work queue: head of each XCD's segment
+    int32_t fit_queue[8];           // fit work queue: head of each XCD's segment
     int32_t err;                    // error bits
     unsigned long long hash;        // output digest (autotuner's result-invariance check)
 };
@@ -84,9 +85,10 @@ struct Batch {
     int16_t* tl_rhi;                // last row holding a cluster
     uint16_t* tl_hits;              // sorted position per row, kNoHit if none
     // keep and final fit: candidates listed densely
-    int32_t* keep_n;                // [cap_starts] (p indexed) kept clusters, 0 = not a track
+    int32_t* keep_n;                // [cap_starts] (p indexed) kept clusters, 0 = not a candidate
+    int64_t* fit_pos;               // [cap_starts] (p indexed) candidate slot (scan of keep_n)
     uint64_t* keep_mask;            // [cap_starts][4] (p indexed) kept rows
-    int32_t* fit_list;              // [cap_fit] p of every candidate
+    int32_t* fit_list;              // [cap_fit] p of every candidate, in p order
     double* f_par;                  // [cap_fit][5]
     double* f_cov;                  // [cap_fit][15]
     double* f_chi2;                 // [cap_fit]
@@ -97,6 +99,7 @@ struct Batch {
     int32_t* hit_cnt;               // kept clusters of accepted tracks
     int64_t* trk_idx;               // output track index
     int64_t* hit_pos;               // output hit offset
+    int32_t* trk_out;               // output track written for this rank, -1 if none
     // selection (sorted positions)
     uint32_t* W;                    // [N]
     // scan scratch
@@ -116,7 +119,7 @@ struct Batch {
 struct LaunchCfg {
     int block;      // row kernels
     int tl_block;   // tracklet kernels
-    int chunk;      // starts per lane taken from the queue
+    int chunk;      // idle lanes that make a tracklet wave take new work
     int n_cu;       // compute units
     int grid_lds;   // dynamic LDS bytes of the grid kernel
 };
@@ -133,6 +136,7 @@ void launch_starts(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, c
 void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
+void launch_fit_scan(const Batch& b, const DevParams& p, hipStream_t s);
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_track_scan(const Batch& b, hipStream_t s);
 void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);

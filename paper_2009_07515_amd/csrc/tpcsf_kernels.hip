@@ -100,6 +100,45 @@ __device__ __forceinline__ int bin_of(float v, float lo, float b, int nb)
 }
 
 // ------------------------------------------------------------------------------------
+// XCD-aware work placement.  The workgroups of a launch are dispatched round-robin over
+// the chip's 8 XCDs, each with its own L2.  Renumbering blocks so that the blocks of one
+// XCD get consecutive numbers, and splitting index ranges into one contiguous segment
+// per XCD, keeps neighbouring rows and the tracks of one sector in one L2.  Placement
+// never changes a result.
+// ------------------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_parts() { return (int)gridDim.x < kXcds ? (int)gridDim.x : kXcds; }
+
+// Block number with the blocks of each XCD consecutive (a bijection on [0, gridDim.x)).
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x, parts = xcd_parts();
+    const int x = b % parts, j = b / parts, q = nb / parts, rem = nb % parts;
+    return x * q + (x < rem ? x : rem) + j;
+}
+
+// Segment `x` of `parts` equal segments of [lo, hi).
+__device__ __forceinline__ void segment(int64_t lo, int64_t hi, int x, int parts, int64_t& s0, int64_t& s1)
+{
+    s0 = lo + (hi - lo) * x / parts;
+    s1 = lo + (hi - lo) * (x + 1) / parts;
+}
+
+// Per-thread loop bounds over [lo, hi): this block's XCD takes its segment, and the
+// XCD's blocks stride over it.  Iterate i = first; i < end; i += stride.
+__device__ __forceinline__ void xcd_span(int64_t lo, int64_t hi, int64_t& first, int64_t& end, int64_t& stride)
+{
+    const int parts = xcd_parts(), x = (int)blockIdx.x % parts, j = (int)blockIdx.x / parts;
+    const int nbx = ((int)gridDim.x - x + parts - 1) / parts;
+    int64_t s0, s1;
+    segment(lo, hi, x, parts, s0, s1);
+    first = s0 + (int64_t)j * blockDim.x + threadIdx.x;
+    end = s1;
+    stride = (int64_t)nbx * blockDim.x;
+}
+
+// ------------------------------------------------------------------------------------
 // k_reset: per-call counters.
 // ------------------------------------------------------------------------------------
 __global__ void k_reset(Batch B)
@@ -112,7 +151,10 @@ __global__ void k_reset(Batch B)
         c->track_base = 0;
         c->hit_base = 0;
         c->n_fit = 0;
-        c->queue = 0;
+        for (int x = 0; x < kXcds; ++x) {
+            c->queue[x] = 0;
+            c->fit_queue[x] = 0;
+        }
         *B.o_ntracks = 0;
         *B.o_nhits = 0;
         if (B.cap_tracks >= 0) B.o_hit_off[0] = 0;
@@ -171,7 +213,7 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(Batch B, DevParams P, int
     __shared__ int tmp[17];
     __shared__ uint32_t maxbin;
     const int t = threadIdx.x, nt = blockDim.x, lane = lane_id(), w = t >> 6, nw = nt >> 6;
-    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
         const float* yr = B.y + base;
@@ -344,9 +386,9 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(Batch B, DevParams P, int
 // least slope change D wins if D <= kink_max; ties go to the smaller u, then the
 // smaller d (in-row indices).  Results are stored as sorted positions.
 //
-// The qualifying candidates of each side are first gathered into registers (slopes
-// computed once per candidate), then all pairs are scored from registers.  A lane with
-// more than kMaxCand candidates on a side scores every pair straight from memory.
+// The qualifying up-row candidates are gathered into registers (slopes computed once per
+// candidate), kSlots at a time; the down row is then scanned and every qualifying
+// down-row candidate is scored against all of them.
 // ------------------------------------------------------------------------------------
 struct RowView {
     int64_t first;            // first cluster of the row
@@ -381,54 +423,60 @@ __device__ __forceinline__ void bin_span(float q, float w, float lo, float ib, i
     i1 = (f1 < (float)nb) ? (int)fmaxf(f1, 0.0f) : nb - 1;
 }
 
-constexpr int kMaxCand = 6;
+constexpr int kSlots = 4;
 
 struct LinkBest {
     float D;
-    int ku, kd;      // sorted positions
-    int uo, dd;      // in-row indices (tie-breaks)
+    int ku, kd;      // sorted positions, -1 = none
 };
 
-__device__ __forceinline__ void link_consider(LinkBest& b, float Dk, int ku, int kd, int uo, int dd, float kmax)
+// Pair (ku, kd) with slope change Dk against the best so far.  Equal D: the smaller u,
+// then the smaller d, by in-row index (looked up only on an exact tie).
+__device__ __forceinline__ void link_consider(LinkBest& b, float Dk, int ku, int kd, float kmax, const uint32_t* pu,
+                                              const uint32_t* pd)
 {
     if (!(Dk <= kmax)) return;
-    const bool better = b.ku < 0 || Dk < b.D || (Dk == b.D && (uo < b.uo || (uo == b.uo && dd < b.dd)));
-    if (better) { b.D = Dk; b.ku = ku; b.kd = kd; b.uo = uo; b.dd = dd; }
+    bool better = b.ku < 0 || Dk < b.D;
+    if (!better && Dk == b.D) {
+        const uint32_t u_new = pu[ku], u_old = pu[b.ku];
+        better = u_new < u_old || (u_new == u_old && pd[kd] < pd[b.kd]);
+    }
+    if (better) { b.D = Dk; b.ku = ku; b.kd = kd; }
 }
 
 // Qualifying candidates of one neighbour row for the cluster (yh, zh): skips the first
-// `skip`, keeps up to kMaxCand (slope, sorted position, in-row index), returns how many
-// qualify in all.  sgn = +1 for the row above (slope (c - h)/dx), -1 below ((h - c)/dx).
-__device__ __forceinline__ int gather_cands(const RowView& V, const float2* yz, const uint32_t* perm,
-                                            int iy0, int iy1, int iz0, int iz1, float yh, float zh,
-                                            float wy, float wz, float dx, bool above, int skip,
-                                            float* ty, float* tz, int* kk, int* oo)
+// `skip`, keeps up to kSlots (slopes, sorted position), returns how many qualify in all.
+// The bins of the window are visited z-bin by z-bin (each z-bin's y-span is one
+// contiguous range); bins and candidates form one flat loop, so lanes with different
+// bin and candidate counts do not diverge on nested loop bounds.
+__device__ __forceinline__ int gather_side(const RowView& V, const float2* yz, int iy0, int iy1, int iz0, int iz1,
+                                           float yh, float zh, float wy, float wz, float dx, bool above, int skip,
+                                           float (&ty)[kSlots], float (&tz)[kSlots], int (&kk)[kSlots])
 {
 #pragma clang fp contract(off)
     int cnt = 0;
-    for (int iz = iz0; iz <= iz1; ++iz) {
-        const uint32_t ka = V.bs[iz * V.ny + iy0], kb = V.bs[iz * V.ny + iy1 + 1];
-        for (uint32_t q0 = ka; q0 < kb; q0 += 4) {
-            float2 c4[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) c4[j] = (q0 + j < kb) ? yz[q0 + j] : make_float2(INFINITY, INFINITY);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float2 c = c4[j];
-                const uint32_t q = q0 + j;
-                if (!(fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz)) continue;
-                const int slot = cnt - skip;
-                if (slot >= 0 && slot < kMaxCand) {
-                    const float sy = above ? (c.x - yh) / dx : (yh - c.x) / dx;
-                    const float sz = above ? (c.y - zh) / dx : (zh - c.y) / dx;
-                    const int o = (int)perm[q];
-#pragma unroll
-                    for (int m = 0; m < kMaxCand; ++m)
-                        if (m == slot) { ty[m] = sy; tz[m] = sz; kk[m] = (int)q; oo[m] = o; }
-                }
-                ++cnt;
-            }
+    int iz = iz0;
+    uint32_t q = V.bs[iz * V.ny + iy0], qe = V.bs[iz * V.ny + iy1 + 1];
+    for (;;) {
+        while (q >= qe && iz < iz1) {
+            ++iz;
+            q = V.bs[iz * V.ny + iy0];
+            qe = V.bs[iz * V.ny + iy1 + 1];
         }
+        if (q >= qe) break;
+        const float2 c = yz[q];
+        if (fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz) {
+            const int slot = cnt - skip;
+            if (slot >= 0 && slot < kSlots) {
+                const float sy = above ? (c.x - yh) / dx : (yh - c.x) / dx;
+                const float sz = above ? (c.y - zh) / dx : (zh - c.y) / dx;
+#pragma unroll
+                for (int m = 0; m < kSlots; ++m)
+                    if (m == slot) { ty[m] = sy; tz[m] = sz; kk[m] = (int)q; }
+            }
+            ++cnt;
+        }
+        ++q;
     }
     return cnt;
 }
@@ -437,7 +485,7 @@ __global__ void __launch_bounds__(256) k_links(Batch B, DevParams P, int64_t g0,
 {
 #pragma clang fp contract(off)
     const int nr = P.n_rows;
-    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
         const int r = (int)(g % nr);
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
@@ -465,38 +513,46 @@ __global__ void __launch_bounds__(256) k_links(Batch B, DevParams P, int64_t g0,
             bin_span(zh, wz, U.zlo, U.ibz, U.nz, uz0, uz1);
             bin_span(yh, wy, D.ylo, D.iby, D.ny, dy0, dy1);
             bin_span(zh, wz, D.zlo, D.ibz, D.nz, dz0, dz1);
-            float uty[kMaxCand], utz[kMaxCand], dty[kMaxCand], dtz[kMaxCand];
-            int uk[kMaxCand], uo[kMaxCand], dk[kMaxCand], dd[kMaxCand];
-            LinkBest best = {0.0f, -1, -1, -1, -1};
-            // all (u, d) pairs, kMaxCand x kMaxCand at a time from registers
-            for (int us = 0;; us += kMaxCand) {
-                const int nu_all = gather_cands(U, yzu, pu, uy0, uy1, uz0, uz1, yh, zh, wy, wz, dxu, true, us,
-                                                uty, utz, uk, uo);
-                const int nu = min(kMaxCand, nu_all - us);
+            float uty[kSlots], utz[kSlots];
+            int uk[kSlots];
+            LinkBest best = {0.0f, -1, -1};
+            // the up-side candidates in registers, kSlots at a time; every down-side
+            // candidate is scored against them as the down row is scanned
+            for (int us = 0;; us += kSlots) {
+                const int nu_all = U.n ? gather_side(U, yzu, uy0, uy1, uz0, uz1, yh, zh, wy, wz, dxu, true, us, uty,
+                                                     utz, uk)
+                                       : 0;
+                const int nu = min(kSlots, nu_all - us);
                 if (nu <= 0) break;
-                for (int ds = 0;; ds += kMaxCand) {
-                    const int nd_all = gather_cands(D, yzd, pd, dy0, dy1, dz0, dz1, yh, zh, wy, wz, dxd, false, ds,
-                                                    dty, dtz, dk, dd);
-                    const int nd = min(kMaxCand, nd_all - ds);
-                    if (nd <= 0) break;
+                if (D.n) {
+                    int iz = dz0;
+                    uint32_t q = D.bs[iz * D.ny + dy0], qe = D.bs[iz * D.ny + dy1 + 1];
+                    for (;;) {
+                        while (q >= qe && iz < dz1) {
+                            ++iz;
+                            q = D.bs[iz * D.ny + dy0];
+                            qe = D.bs[iz * D.ny + dy1 + 1];
+                        }
+                        if (q >= qe) break;
+                        const float2 c = yzd[q];
+                        if (fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz) {
+                            const float ty = (yh - c.x) / dxd;
+                            const float tz = (zh - c.y) / dxd;
 #pragma unroll
-                    for (int i = 0; i < kMaxCand; ++i) {
-                        if (i < nu) {
-#pragma unroll
-                            for (int j = 0; j < kMaxCand; ++j) {
-                                if (j < nd) {
-                                    const float ay = uty[i] - dty[j];
-                                    const float az = utz[i] - dtz[j];
+                            for (int i = 0; i < kSlots; ++i) {
+                                if (i < nu) {
+                                    const float ay = uty[i] - ty;
+                                    const float az = utz[i] - tz;
                                     const float sy = ay * ay;
                                     const float sz = az * az;
-                                    link_consider(best, sy + sz, uk[i], dk[j], uo[i], dd[j], kmax);
+                                    link_consider(best, sy + sz, uk[i], (int)q, kmax, pu, pd);
                                 }
                             }
                         }
+                        ++q;
                     }
-                    if (ds + kMaxCand >= nd_all) break;
                 }
-                if (us + kMaxCand >= nu_all) break;
+                if (us + kSlots >= nu_all) break;
             }
             B.upk[base + k] = best.ku;
             B.dnk[base + k] = best.kd;
@@ -512,7 +568,7 @@ __global__ void __launch_bounds__(1024) k_clean(Batch B, DevParams P, int64_t g0
 {
     __shared__ int lds[17];
     const int nr = P.n_rows;
-    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
         const int r = (int)(g % nr);
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
@@ -541,7 +597,7 @@ __global__ void __launch_bounds__(1024) k_clean(Batch B, DevParams P, int64_t g0
 __global__ void __launch_bounds__(1024) k_starts(Batch B, DevParams P, int64_t g0, int64_t g1)
 {
     __shared__ int lds[17];
-    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
         const int64_t sb = B.row_sbase[g];
@@ -583,6 +639,7 @@ struct ScanJob {
     const int64_t* a64;       // channel A input (int64) or null
     const int32_t* a32;       // channel A input (int32) if a64 is null
     const int32_t* b32;       // channel B input (int32) or null
+    int32_t a_min;            // > 0: channel A counts a32[i] >= a_min as 1, else 0
     int64_t* outA;
     int64_t* outB;
     int64_t lo, hi;           // range if lo_ptr is null
@@ -614,7 +671,12 @@ __device__ __forceinline__ void scan_seg(int64_t lo, int64_t hi, int b, int64_t&
     if (s1 > hi) s1 = hi;
 }
 
-__device__ __forceinline__ int64_t scanA(const ScanJob& J, int64_t i) { return J.a64 ? J.a64[i] : (int64_t)J.a32[i]; }
+__device__ __forceinline__ int64_t scanA(const ScanJob& J, int64_t i)
+{
+    if (J.a64) return J.a64[i];
+    if (J.a_min > 0) return J.a32[i] >= J.a_min ? 1 : 0;
+    return (int64_t)J.a32[i];
+}
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(ScanJob J)
 {
@@ -938,11 +1000,12 @@ __device__ __forceinline__ uint16_t* hit_slot(const Batch& B, int r, int64_t p)
 
 __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
 {
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     const int nr = P.n_rows;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctr->n_fit = 0;   // candidates of this launch set
-    for (int64_t p = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi; p += stride) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)   // the fit queue of this launch set
+        for (int x = 0; x < kXcds; ++x) B.ctr->fit_queue[x] = 0;
+    int64_t first, end, stride;
+    xcd_span(B.ctr->rank_lo, B.ctr->rank_hi, first, end, stride);
+    for (int64_t p = first; p < end; p += stride) {
         const int64_t g = B.st_row[p];
         const int r0 = (int)(g % nr);
         const int64_t gs = g - r0;
@@ -955,32 +1018,6 @@ __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
         B.tl_len[p] = L;
         B.tl_n[p] = 0;
     }
-}
-
-// Follow from r_from toward r_to (exclusive) in steps of `step`; every visited row's
-// table entry is written (cluster or kNoHit).  Returns the clusters added; *last_hit is
-// the last row that received one (unchanged if none).
-__device__ int follow(const Batch& B, const DevParams& P, Trk& t, int64_t gs, int r_from, int r_to, int step,
-                      int64_t p, int* last_hit)
-{
-    int misses = 0, added = 0;
-    for (int r = r_from; r != r_to; r += step) {
-        if (!trk_propagate(t, (double)P.rx[r], P)) break;
-        double chi2;
-        const int k = search_row(B, P, gs + r, t, chi2);
-        if (k >= 0 && chi2 <= P.chi2_max) {
-            const float2 c = B.yz[B.off[gs + r] + k];
-            trk_update(t, (double)c.x, (double)c.y, P);
-            *hit_slot(B, r, p) = (uint16_t)k;
-            *last_hit = r;
-            misses = 0;
-            ++added;
-        } else {
-            *hit_slot(B, r, p) = kNoHit;
-            if (++misses > P.max_miss) break;
-        }
-    }
-    return added;
 }
 
 // ------------------------------------------------------------------------------------
@@ -999,207 +1036,425 @@ __device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 5b, tracklets: one lane per chain, pulled from a persistent work queue in
-// processing order (neighbouring chains of one sector share a wave).  Three-point seed,
-// Kalman update over the chain, follow outward, reset
-// C to C0 keeping p and refit inward over all clusters so far, follow inward.  Clusters
-// are recorded per row (sorted positions); rows [rlo, rhi] are all written.
+// Stage 5b, tracklets.  Per chain: three-point seed (first, middle and last cluster),
+// Kalman update over the chain, follow outward, reset C to C0 keeping p and refit inward
+// over all clusters so far, follow inward.  A follow step propagates to the next row and
+// takes the least-chi2 cluster inside the window if chi2 <= chi2_max; it stops after
+// more than max_miss consecutive misses or when the propagation fails.  Clusters are
+// recorded per row (sorted positions); rows [rlo, rhi] are all written.  A failed seed,
+// fit or refit leaves a tracklet of size 0.
+//
+// Execution is step-uniform: every lane holds one tracklet and each pass of the loop
+// moves every lane by one row, whatever phase it is in, so the binary64 propagation and
+// update run on all lanes together.  Lanes that finish take the next tracklet from the
+// list (one queue atomic per wave per 64 tracklets); a finished tracklet of >= min_track_hits clusters
+// claims its clusters with the whole wave (one row per lane).
 // ------------------------------------------------------------------------------------
-__device__ void build_tracklet(const Batch& B, const DevParams& P, int64_t p)
+// Hands work items of [lo, hi) to the idle lanes of a wave, in lane order.  The range is
+// split into one segment per XCD with a queue head each; a wave takes kGrab items of its
+// own XCD's segment at a time (one atomic per kGrab items) and moves on to the next
+// segment once its own is used up.  Returns -1 once every segment is used up.  `next`,
+// `end`, `seg` and `tried` are the wave's (uniform) queue state.
+constexpr int kGrab = 64;
+
+__device__ int64_t take_item(int32_t* heads, int64_t lo, int64_t hi, uint64_t idle, int64_t& next, int64_t& end,
+                             int& seg, int& tried)
+{
+    const int parts = xcd_parts();
+    const int want = __popcll(idle);
+    const int rank = __popcll(idle & lanemask_lt());
+    int64_t item = -1;
+    int given = 0;
+    while (given < want) {
+        if (next >= end) {
+            if (tried >= parts) break;
+            int64_t s0, s1;
+            segment(lo, hi, seg, parts, s0, s1);
+            int h = 0;
+            if (lane_id() == 0) h = atomicAdd(&heads[seg], kGrab);
+            h = __shfl(h, 0, 64);
+            if (s0 + h >= s1) {
+                seg = (seg + 1) % parts;
+                ++tried;
+                continue;
+            }
+            next = s0 + h;
+            end = (s0 + h + kGrab < s1) ? s0 + h + kGrab : s1;
+        }
+        const int64_t avail = end - next;
+        const int take = (int64_t)(want - given) < avail ? want - given : (int)avail;
+        if (rank >= given && rank < given + take) item = next + (rank - given);
+        next += take;
+        given += take;
+    }
+    return item;
+}
+
+enum : int { kIdle = 0, kFit = 1, kOut = 2, kRefit = 3, kIn = 4, kDone = 5, kExit = 6 };
+
+__global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int refill_min)
 {
     const int nr = P.n_rows;
-    const int64_t g = B.st_row[p];
-    const int r0 = (int)(g % nr);
-    const int64_t gs = g - r0;
-    const int L = B.tl_len[p];
-    // seed clusters: first, middle and last of the chain
-    const int rs[3] = {r0, r0 + (L - 1) / 2, r0 + L - 1};
-    double sx[3], sy[3], sz[3];
-    for (int q = 0; q < 3; ++q) {
-        const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
-        sx[q] = (double)P.rx[rs[q]];
-        sy[q] = (double)c.x;
-        sz[q] = (double)c.y;
-    }
+    const int lane = lane_id();
+    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
+    int phase = kIdle;
+    int64_t p = 0, gs = 0;
+    int r = 0, r0 = 0, rend = 0, rlo = 0, rhi = 0, n = 0, misses = 0;
+    int64_t q_next = 0, q_end = 0;
+    int q_seg = (int)blockIdx.x % xcd_parts(), q_tried = 0;
     Trk tr;
-    int n = 0;
-    int rlo = r0, rhi = r0 + L - 1;
-    bool ok = trk_seed(tr, sx, sy, sz, P);
-    if (ok) {
-        trk_reset_cov(tr, P);
-        for (int r = r0; r < r0 + L; ++r) {
-            if (r > r0 && !trk_propagate(tr, (double)P.rx[r], P)) { ok = false; break; }
-            const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
-            trk_update(tr, (double)c.x, (double)c.y, P);
+    for (;;) {
+        // refill idle lanes; chains shorter than min_chain are not tracklets (size 0)
+        const uint64_t idle = __ballot(phase == kIdle);
+        const uint64_t busy = __ballot(phase >= kFit && phase <= kIn);
+        if (idle != 0ull && (__popcll(idle) >= refill_min || busy == 0ull)) {
+            const int64_t j = take_item(B.ctr->queue, lo, hi, idle, q_next, q_end, q_seg, q_tried);
+            if (phase == kIdle) {
+                const int L = j >= 0 ? B.tl_len[j] : 0;
+                if (j < 0) {
+                    phase = kExit;
+                } else if (L >= P.min_chain) {
+                    p = j;
+                    const int64_t g = B.st_row[p];
+                    r0 = (int)(g % nr);
+                    gs = g - r0;
+                    rend = r0 + L;
+                    rlo = r0;
+                    rhi = r0 + L - 1;
+                    const int rs[3] = {r0, r0 + (L - 1) / 2, r0 + L - 1};
+                    double sx[3], sy[3], sz[3];
+                    for (int q = 0; q < 3; ++q) {
+                        const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
+                        sx[q] = (double)P.rx[rs[q]];
+                        sy[q] = (double)c.x;
+                        sz[q] = (double)c.y;
+                    }
+                    if (trk_seed(tr, sx, sy, sz, P)) {
+                        trk_reset_cov(tr, P);
+                        phase = kFit;
+                        r = r0;
+                        n = L;
+                    } else {
+                        phase = kDone;
+                        n = 0;
+                    }
+                }
+            }
         }
-    }
-    if (ok) {
-        n = L + follow(B, P, tr, gs, r0 + L, nr, +1, p, &rhi);
-        trk_reset_cov(tr, P);
-        for (int r = rhi; r >= r0; --r) {
-            const uint16_t k = *hit_slot(B, r, p);
-            if (k == kNoHit) continue;
-            if (!trk_propagate(tr, (double)P.rx[r], P)) { ok = false; break; }
+        if (__ballot(phase != kExit) == 0ull) break;
+
+        // one row per lane
+        const bool act = phase >= kFit && phase <= kIn;
+        bool moved = true;
+        if (act && !(phase == kFit && r == r0)) moved = trk_propagate(tr, (double)P.rx[r], P);
+        int k = -1;
+        if (act && moved) {
+            if (phase == kFit || phase == kRefit) {
+                k = *hit_slot(B, r, p);
+            } else {
+                double chi2;
+                k = search_row(B, P, gs + r, tr, chi2);
+                if (k >= 0 && !(chi2 <= P.chi2_max)) k = -1;
+            }
+        }
+        if (k >= 0) {
             const float2 c = B.yz[B.off[gs + r] + k];
             trk_update(tr, (double)c.x, (double)c.y, P);
         }
-    }
-    if (ok) n += follow(B, P, tr, gs, r0 - 1, -1, -1, p, &rlo);
-    if (!ok) n = 0;
-    B.tl_n[p] = n;
-    B.tl_rlo[p] = (int16_t)rlo;
-    B.tl_rhi[p] = (int16_t)rhi;
-    if (n < P.min_track_hits) return;
-    const uint32_t w = weight_of(B, P, n, B.st_rank[p], gs);
-    for (int r = rlo; r <= rhi; ++r) {
-        const uint16_t k = *hit_slot(B, r, p);
-        if (k != kNoHit) atomicMax(&B.W[B.off[gs + r] + k], w);
-    }
-}
-
-__global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int chunk)
-{
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
-    const int lane = lane_id();
-    const int per_wave = 64 * chunk;
-    for (;;) {
-        int take = 0;
-        if (lane == 0) take = atomicAdd(&B.ctr->queue, per_wave);
-        take = __shfl(take, 0, 64);
-        const int64_t t0 = lo + take;
-        if (t0 >= hi) break;
-        for (int k = 0; k < chunk; ++k) {
-            const int64_t p = t0 + (int64_t)k * 64 + lane;
-            if (p < hi && B.tl_len[p] >= P.min_chain) build_tracklet(B, P, p);
+        bool to_refit = false;
+        if (phase == kFit) {
+            if (!moved) {
+                phase = kDone;
+                n = 0;
+            } else if (++r == rend) {
+                phase = kOut;
+                misses = 0;
+                to_refit = r >= nr;
+            }
+        } else if (phase == kOut) {
+            if (!moved) {
+                to_refit = true;
+            } else {
+                if (k >= 0) {
+                    *hit_slot(B, r, p) = (uint16_t)k;
+                    rhi = r;
+                    misses = 0;
+                    ++n;
+                } else {
+                    *hit_slot(B, r, p) = kNoHit;
+                    to_refit = ++misses > P.max_miss;
+                }
+                if (!to_refit) to_refit = ++r >= nr;
+            }
+        } else if (phase == kRefit) {
+            if (!moved) {
+                phase = kDone;
+                n = 0;
+            } else {
+                int q = r - 1;
+                while (q >= r0 && *hit_slot(B, q, p) == kNoHit) --q;
+                if (q >= r0) {
+                    r = q;
+                } else {
+                    phase = kIn;
+                    misses = 0;
+                    r = r0 - 1;
+                    if (r < 0) phase = kDone;
+                }
+            }
+        } else if (phase == kIn) {
+            if (!moved) {
+                phase = kDone;
+            } else {
+                if (k >= 0) {
+                    *hit_slot(B, r, p) = (uint16_t)k;
+                    rlo = r;
+                    misses = 0;
+                    ++n;
+                } else {
+                    *hit_slot(B, r, p) = kNoHit;
+                    if (++misses > P.max_miss) phase = kDone;
+                }
+                if (phase == kIn && --r < 0) phase = kDone;
+            }
         }
+        if (to_refit) {
+            trk_reset_cov(tr, P);
+            phase = kRefit;
+            r = rhi;
+        }
+
+        // finished tracklets: record, then claim with the whole wave
+        uint64_t fin = __ballot(phase == kDone);
+        if (phase == kDone) {
+            B.tl_n[p] = n;
+            B.tl_rlo[p] = (int16_t)rlo;
+            B.tl_rhi[p] = (int16_t)rhi;
+        }
+        while (fin != 0ull) {
+            const int j = __ffsll((unsigned long long)fin) - 1;
+            fin &= fin - 1ull;
+            const int nj = __shfl(n, j, 64);
+            if (nj < P.min_track_hits) continue;
+            const int64_t pj = __shfl(p, j, 64);
+            const int64_t gsj = __shfl(gs, j, 64);
+            const int rloj = __shfl(rlo, j, 64), rhij = __shfl(rhi, j, 64);
+            const uint32_t w = weight_of(B, P, nj, B.st_rank[pj], gsj);
+            for (int rr = rloj + lane; rr <= rhij; rr += 64) {
+                const uint16_t kk = *hit_slot(B, rr, pj);
+                if (kk != kNoHit) atomicMax(&B.W[B.off[gsj + rr] + kk], w);
+            }
+        }
+        if (phase == kDone) phase = kIdle;
     }
 }
 
 // ------------------------------------------------------------------------------------
 // Stage 7a, keep: a tracklet keeps the clusters that carry its own weight and is a track
-// candidate if it keeps >= min_track_hits.  Candidates are listed with one atomic per
-// wave, so the list stays in processing order within each wave's 64 tracklets.
+// candidate if it keeps >= min_track_hits.  A device scan over the candidate flags then
+// gives every candidate its slot, in processing order.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
 {
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     const int nr = P.n_rows;
-    const int lane = lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctr->queue = 0;   // the tracklet queue is done
-    // wave-uniform loop: every lane of a wave takes part in each compaction
-    for (int64_t p0 = lo + (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); p0 < hi; p0 += stride) {
-        const int64_t p = p0 + lane;
-        bool cand = false;
-        if (p < hi) {
-            const int64_t rank = B.st_rank[p];
-            B.trk_flag[rank] = 0;
-            B.hit_cnt[rank] = 0;
-            const int n = B.tl_n[p];
-            if (n >= P.min_track_hits) {
-                const int64_t g = B.st_row[p];
-                const int64_t gs = g - g % nr;
-                const uint32_t w = weight_of(B, P, n, rank, gs);
-                const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
-                uint64_t m[4] = {0, 0, 0, 0};
-                int kept = 0;
-                for (int r = rlo; r <= rhi; ++r) {
-                    const uint16_t k = *hit_slot(B, r, p);
-                    if (k == kNoHit) continue;
-                    if (B.W[B.off[gs + r] + k] == w) {
-                        m[r >> 6] |= 1ull << (r & 63);
-                        ++kept;
-                    }
-                }
-                if (kept >= P.min_track_hits) {
-                    for (int i = 0; i < 4; ++i) B.keep_mask[p * 4 + i] = m[i];
-                    B.keep_n[p] = kept;
-                    cand = true;
+    if (blockIdx.x == 0 && threadIdx.x == 0)   // the tracklet queue is done
+        for (int x = 0; x < kXcds; ++x) B.ctr->queue[x] = 0;
+    int64_t first, end, stride;
+    xcd_span(B.ctr->rank_lo, B.ctr->rank_hi, first, end, stride);
+    for (int64_t p = first; p < end; p += stride) {
+        const int64_t rank = B.st_rank[p];
+        B.trk_flag[rank] = 0;
+        B.hit_cnt[rank] = 0;
+        B.trk_out[rank] = -1;
+        int kept = 0;
+        const int n = B.tl_n[p];
+        if (n >= P.min_track_hits) {
+            const int64_t g = B.st_row[p];
+            const int64_t gs = g - g % nr;
+            const uint32_t w = weight_of(B, P, n, rank, gs);
+            const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
+            uint64_t m[4] = {0, 0, 0, 0};
+            for (int r = rlo; r <= rhi; ++r) {
+                const uint16_t k = *hit_slot(B, r, p);
+                if (k == kNoHit) continue;
+                if (B.W[B.off[gs + r] + k] == w) {
+                    m[r >> 6] |= 1ull << (r & 63);
+                    ++kept;
                 }
             }
+            if (kept >= P.min_track_hits) {
+                for (int i = 0; i < 4; ++i) B.keep_mask[p * 4 + i] = m[i];
+            } else {
+                kept = 0;
+            }
         }
-        const uint64_t bal = __ballot(cand);
-        if (bal == 0ull) continue;
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&B.ctr->n_fit, __popcll(bal));
-        base = __shfl(base, 0, 64);
-        if (cand) B.fit_list[base + __popcll(bal & lanemask_lt())] = (int32_t)p;
+        B.keep_n[p] = kept;
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Stage 7b, final fit on the kept clusters (inner to outer): three-point seed, C = C0,
-// update outward; C = C0 keeping p, update inward.  Result at the innermost kept
-// cluster; a failed fit drops the track.  Results stay in list order (slot i).
+// Stage 7b, final fit on the kept clusters (inner to outer): three-point seed (first,
+// middle and last kept cluster), C = C0, update outward; C = C0 keeping p, update inward
+// from the last kept cluster, summing the chi2 of each cluster before its update.
+// Result at the innermost kept cluster; a failed fit drops the track.  Results are
+// stored at the candidate's list slot.
+//
+// Step-uniform like the tracklet stage: one candidate per lane, one kept row per pass of
+// the loop, finished lanes refill from the work queue over processing order.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ bool row_kept(const uint64_t* m, int r) { return (m[r >> 6] >> (r & 63)) & 1ull; }
+__device__ __forceinline__ uint64_t mask_word(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3, int w)
+{
+    return w == 0 ? m0 : (w == 1 ? m1 : (w == 2 ? m2 : m3));
+}
+
+// Smallest set row >= r (-1 if none) and largest set row <= r (-1 if none).
+__device__ __forceinline__ int row_at_or_above(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3, int r)
+{
+    for (int w = r >> 6; w < 4; ++w) {
+        uint64_t x = mask_word(m0, m1, m2, m3, w);
+        if (w == (r >> 6)) x &= ~0ull << (r & 63);
+        if (x) return (w << 6) + __ffsll((unsigned long long)x) - 1;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int row_at_or_below(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3, int r)
+{
+    for (int w = r >> 6; w >= 0; --w) {
+        uint64_t x = mask_word(m0, m1, m2, m3, w);
+        if (w == (r >> 6) && (r & 63) != 63) x &= (1ull << ((r & 63) + 1)) - 1ull;
+        if (x) return (w << 6) + 63 - __clzll((long long)x);
+    }
+    return -1;
+}
+
+// Position of the k-th (from 0) set bit of x; x has more than k set bits.
+__device__ __forceinline__ int nth_set_bit(uint64_t x, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        const int c = __popcll(x & ((1ull << sh) - 1ull));
+        if (k >= c) {
+            k -= c;
+            x >>= sh;
+            pos += sh;
+        }
+    }
+    return pos;
+}
+
+enum : int { kFitIdle = 0, kFwd = 1, kBwd = 2, kFitDone = 3, kFitExit = 4 };
 
 __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 {
-    const int64_t nfit = B.ctr->n_fit;
     const int nr = P.n_rows;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nfit; i += stride) {
-        const int64_t p = B.fit_list[i];
-        const int64_t rank = B.st_rank[p];
-        const int kept = B.keep_n[p];
-        const int64_t g = B.st_row[p];
-        const int64_t gs = g - g % nr;
-        uint64_t m[4];
-        for (int q = 0; q < 4; ++q) m[q] = B.keep_mask[p * 4 + q];
-        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
-        // seed rows: first, middle and last kept cluster
-        const int want[3] = {0, (kept - 1) / 2, kept - 1};
-        int rsel[3] = {0, 0, 0};
-        for (int r = rlo, idx = 0; r <= rhi; ++r) {
-            if (!row_kept(m, r)) continue;
-            for (int q = 0; q < 3; ++q)
-                if (want[q] == idx) rsel[q] = r;
-            ++idx;
-        }
-        double sx[3], sy[3], sz[3];
-        for (int q = 0; q < 3; ++q) {
-            const float2 c = B.yz[B.off[gs + rsel[q]] + *hit_slot(B, rsel[q], p)];
-            sx[q] = (double)P.rx[rsel[q]];
-            sy[q] = (double)c.x;
-            sz[q] = (double)c.y;
-        }
-        Trk tr;
-        bool ok = trk_seed(tr, sx, sy, sz, P);
-        if (ok) {
-            trk_reset_cov(tr, P);
-            for (int r = rsel[0]; r <= rsel[2]; ++r) {
-                if (!row_kept(m, r)) continue;
-                if (r > rsel[0] && !trk_propagate(tr, (double)P.rx[r], P)) { ok = false; break; }
-                const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
-                trk_update(tr, (double)c.x, (double)c.y, P);
+    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
+    int phase = kFitIdle;
+    int64_t i = 0, p = 0, gs = 0;
+    uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+    int r = 0, rfirst = 0, rlast = 0, kept = 0;
+    bool ok = false;
+    double chi2 = 0.0;
+    int64_t q_next = 0, q_end = 0;
+    int q_seg = (int)blockIdx.x % xcd_parts(), q_tried = 0;
+    Trk tr;
+    for (;;) {
+        const uint64_t idle = __ballot(phase == kFitIdle);
+        if (idle != 0ull) {
+            const int64_t j = take_item(B.ctr->fit_queue, lo, hi, idle, q_next, q_end, q_seg, q_tried);
+            if (phase == kFitIdle) {
+                kept = j >= 0 ? B.keep_n[j] : 0;
+                if (j < 0) {
+                    phase = kFitExit;
+                } else if (kept > 0) {
+                    p = j;
+                    i = B.fit_pos[p];
+                    B.fit_list[i] = (int32_t)p;
+                    const int64_t g = B.st_row[p];
+                    gs = g - g % nr;
+                    m0 = B.keep_mask[p * 4 + 0]; m1 = B.keep_mask[p * 4 + 1];
+                    m2 = B.keep_mask[p * 4 + 2]; m3 = B.keep_mask[p * 4 + 3];
+                    rfirst = row_at_or_above(m0, m1, m2, m3, 0);
+                    rlast = row_at_or_below(m0, m1, m2, m3, kMaxRows - 1);
+                    int want = (kept - 1) / 2, rmid = rfirst;
+                    for (int w = 0; w < 4; ++w) {
+                        const uint64_t x = mask_word(m0, m1, m2, m3, w);
+                        const int c = __popcll(x);
+                        if (want < c) { rmid = (w << 6) + nth_set_bit(x, want); break; }
+                        want -= c;
+                    }
+                    const int rs[3] = {rfirst, rmid, rlast};
+                    double sx[3], sy[3], sz[3];
+                    for (int q = 0; q < 3; ++q) {
+                        const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
+                        sx[q] = (double)P.rx[rs[q]];
+                        sy[q] = (double)c.x;
+                        sz[q] = (double)c.y;
+                    }
+                    chi2 = 0.0;
+                    if (trk_seed(tr, sx, sy, sz, P)) {
+                        trk_reset_cov(tr, P);
+                        phase = kFwd;
+                        r = rfirst;
+                    } else {
+                        phase = kFitDone;
+                        ok = false;
+                    }
+                }
             }
         }
-        double chi2 = 0.0;
-        if (ok) {
-            trk_reset_cov(tr, P);
-            for (int r = rsel[2]; r >= rsel[0]; --r) {
-                if (!row_kept(m, r)) continue;
-                if (r < rsel[2] && !trk_propagate(tr, (double)P.rx[r], P)) { ok = false; break; }
-                const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
-                const double my = (double)c.x, mz = (double)c.y;
-                chi2 += trk_chi2(tr, my, mz, P);
-                trk_update(tr, my, mz, P);
+        if (__ballot(phase != kFitExit) == 0ull) break;
+
+        const bool act = phase == kFwd || phase == kBwd;
+        bool moved = true;
+        if (act && !(phase == kFwd && r == rfirst) && !(phase == kBwd && r == rlast))
+            moved = trk_propagate(tr, (double)P.rx[r], P);
+        if (act && moved) {
+            const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
+            const double my = (double)c.x, mz = (double)c.y;
+            if (phase == kBwd) chi2 += trk_chi2(tr, my, mz, P);
+            trk_update(tr, my, mz, P);
+        }
+        if (phase == kFwd) {
+            if (!moved) {
+                phase = kFitDone;
+                ok = false;
+            } else if (r == rlast) {
+                trk_reset_cov(tr, P);
+                phase = kBwd;
+            } else {
+                r = row_at_or_above(m0, m1, m2, m3, r + 1);
+            }
+        } else if (phase == kBwd) {
+            if (!moved) {
+                phase = kFitDone;
+                ok = false;
+            } else if (r == rfirst) {
+                phase = kFitDone;
+                ok = true;
+            } else {
+                r = row_at_or_below(m0, m1, m2, m3, r - 1);
             }
         }
-        if (ok) {
-            for (int q = 0; q < 5; ++q) ok = ok && isfinite(tr.p[q]);
-            for (int q = 0; q < 15; ++q) ok = ok && isfinite(tr.c[q]);
+        if (phase == kFitDone) {
+            if (ok) {
+                for (int q = 0; q < 5; ++q) ok = ok && isfinite(tr.p[q]);
+                for (int q = 0; q < 15; ++q) ok = ok && isfinite(tr.c[q]);
+            }
+            if (ok) {
+                double* fp = B.f_par + i * 5;
+                double* fc = B.f_cov + i * 15;
+                for (int q = 0; q < 5; ++q) fp[q] = tr.p[q];
+                for (int q = 0; q < 15; ++q) fc[q] = tr.c[q];
+                B.f_chi2[i] = chi2;
+                B.f_xref[i] = tr.x;
+                const int64_t rank = B.st_rank[p];
+                B.trk_flag[rank] = 1;
+                B.hit_cnt[rank] = kept;
+            }
+            phase = kFitIdle;
         }
-        if (!ok) continue;
-        double* fp = B.f_par + i * 5;
-        double* fc = B.f_cov + i * 15;
-        for (int q = 0; q < 5; ++q) fp[q] = tr.p[q];
-        for (int q = 0; q < 15; ++q) fc[q] = tr.c[q];
-        B.f_chi2[i] = chi2;
-        B.f_xref[i] = tr.x;
-        B.trk_flag[rank] = 1;
-        B.hit_cnt[rank] = kept;
     }
 }
 
@@ -1210,10 +1465,10 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
 {
-    const int64_t nfit = B.ctr->n_fit;
     const int nr = P.n_rows;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nfit; i += stride) {
+    int64_t first, end, stride;
+    xcd_span(0, B.ctr->n_fit, first, end, stride);
+    for (int64_t i = first; i < end; i += stride) {
         const int64_t p = B.fit_list[i];
         const int64_t rank = B.st_rank[p];
         if (!B.trk_flag[rank]) continue;
@@ -1235,6 +1490,7 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
         B.o_sector[T] = (int32_t)((g / nr) % P.n_sectors);
         B.o_tf[T] = (int32_t)(g / ((int64_t)nr * P.n_sectors));
         B.o_hit_off[T + 1] = hp + nk;
+        B.trk_out[rank] = (int32_t)T;
         const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
         int64_t j = hp;
         for (int r = rlo; r <= rhi; ++r) {
@@ -1249,25 +1505,19 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
 // Stage 9, cluster -> track map, per cluster in input order.  A cluster belongs to the
 // track whose weight it carries (the kept clusters of a track are exactly those), so the
 // weight names the tracklet by its rank within the sector; the map is -1 where that
-// tracklet was not accepted or its track was not written.
+// tracklet was not accepted or its track was not written (emit records, per rank, the
+// track it wrote).
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_assign(Batch B, DevParams P, int64_t g0, int64_t g1)
 {
     const int nr = P.n_rows;
-    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
         const int64_t sbase = B.row_sbase[g - g % nr];
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const uint32_t w = B.W[base + B.iperm[base + i]];
-            int32_t T = -1;
-            if (w != 0u) {
-                const int64_t rank = sbase + (int64_t)(0xFFFFFFu - (w & 0xFFFFFFu));
-                if (B.trk_flag[rank]) {
-                    const int64_t t = B.trk_idx[rank];
-                    if (t < B.cap_tracks && B.hit_pos[rank] + B.hit_cnt[rank] <= B.cap_hits) T = (int32_t)t;
-                }
-            }
+            const int32_t T = w != 0u ? B.trk_out[sbase + (int64_t)(0xFFFFFFu - (w & 0xFFFFFFu))] : -1;
             B.o_cluster_track[base + i] = T;
         }
     }
@@ -1280,7 +1530,7 @@ __global__ void __launch_bounds__(256) k_assign(Batch B, DevParams P, int64_t g0
 __global__ void __launch_bounds__(256) k_debug_links(Batch B, DevParams P, int64_t g0, int64_t g1)
 {
     const int nr = P.n_rows;
-    for (int64_t g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
         const int r = (int)(g % nr);
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
@@ -1432,6 +1682,19 @@ void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hi
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_keep, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+}
+
+void launch_fit_scan(const Batch& b, const DevParams& p, hipStream_t s)
+{
+    ScanJob J = {};
+    J.a32 = b.keep_n;
+    J.a_min = 1;
+    J.outA = b.fit_pos;
+    J.lo_ptr = &b.ctr->rank_lo;
+    J.hi_ptr = &b.ctr->rank_hi;
+    J.totA = &b.ctr->n_fit;
+    J.part = b.scan_part;
+    run_scan(J, s);
 }
 
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
