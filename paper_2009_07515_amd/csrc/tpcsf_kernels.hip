@@ -423,6 +423,23 @@ __device__ __forceinline__ void bin_span(float q, float w, float lo, float ib, i
     i1 = (f1 < (float)nb) ? (int)fmaxf(f1, 0.0f) : nb - 1;
 }
 
+// First candidate range of a window: the y-span of z-bin iz0; when the y-span covers the
+// whole row, the ranges of all z-bins of the window are adjacent and form one range.
+// `iz` is the last z-bin the range covers.
+__device__ __forceinline__ void first_range(const RowView& V, int iy0, int iy1, int iz0, int iz1, int& iz,
+                                            uint32_t& q, uint32_t& qe)
+{
+    if (iy0 == 0 && iy1 == V.ny - 1) {
+        q = V.bs[iz0 * V.ny];
+        qe = V.bs[(iz1 + 1) * V.ny];
+        iz = iz1;
+    } else {
+        q = V.bs[iz0 * V.ny + iy0];
+        qe = V.bs[iz0 * V.ny + iy1 + 1];
+        iz = iz0;
+    }
+}
+
 constexpr int kSlots = 4;
 
 struct LinkBest {
@@ -455,8 +472,9 @@ __device__ __forceinline__ int gather_side(const RowView& V, const float2* yz, i
 {
 #pragma clang fp contract(off)
     int cnt = 0;
-    int iz = iz0;
-    uint32_t q = V.bs[iz * V.ny + iy0], qe = V.bs[iz * V.ny + iy1 + 1];
+    int iz;
+    uint32_t q, qe;
+    first_range(V, iy0, iy1, iz0, iz1, iz, q, qe);
     for (;;) {
         while (q >= qe && iz < iz1) {
             ++iz;
@@ -525,8 +543,9 @@ __global__ void __launch_bounds__(256) k_links(Batch B, DevParams P, int64_t g0,
                 const int nu = min(kSlots, nu_all - us);
                 if (nu <= 0) break;
                 if (D.n) {
-                    int iz = dz0;
-                    uint32_t q = D.bs[iz * D.ny + dy0], qe = D.bs[iz * D.ny + dy1 + 1];
+                    int iz;
+                    uint32_t q, qe;
+                    first_range(D, dy0, dy1, dz0, dz1, iz, q, qe);
                     for (;;) {
                         while (q >= qe && iz < dz1) {
                             ++iz;
@@ -944,11 +963,16 @@ __device__ bool trk_seed(Trk& t, const double* x, const double* y, const double*
     return true;
 }
 
-// Least-chi2 cluster of row g inside the follow window: its sorted position, -1 if none.
-// Equal chi2: the smaller in-row index.
-__device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const Trk& t, double& best_chi2)
+// Least-chi2 cluster of row g (row record rf, ri) inside the follow window: its sorted
+// position (-1 if none) and coordinates.  Equal chi2: the smaller in-row index.
+__device__ int search_row(const Batch& B, const DevParams& P, const float4 rf, const int4 ri, int64_t g, const Trk& t,
+                          double& best_chi2, float2& best_c)
 {
-    const RowView v = row_view(B, P, g);
+    RowView v;
+    v.first = ri.x;
+    v.n = ri.y;
+    v.ylo = rf.x; v.zlo = rf.y; v.iby = rf.z; v.ibz = rf.w; v.ny = ri.z; v.nz = ri.w;
+    v.bs = B.bin_start + bin_base(P, v.first, g);
     best_chi2 = 0.0;
     if (v.n == 0) return -1;
     const double s00 = t.c[0] + P.sy2, s01 = t.c[1], s11 = t.c[2] + P.sz2;
@@ -963,27 +987,35 @@ __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const T
     const double idet = 1.0 / (s00 * s11 - s01 * s01);
     const float2* yz = B.yz + v.first;
     int best = -1;
-    for (int iz = iz0; iz <= iz1; ++iz) {
-        const uint32_t ka = v.bs[iz * v.ny + iy0], kb = v.bs[iz * v.ny + iy1 + 1];
-        for (uint32_t k0 = ka; k0 < kb; k0 += 4) {
-            float2 c4[4];
+    int iz;
+    uint32_t q, qe;
+    first_range(v, iy0, iy1, iz0, iz1, iz, q, qe);
+    for (;;) {
+        while (q >= qe && iz < iz1) {
+            ++iz;
+            q = v.bs[iz * v.ny + iy0];
+            qe = v.bs[iz * v.ny + iy1 + 1];
+        }
+        if (q >= qe) break;
+        float2 c2[2];
+        c2[0] = yz[q];
+        c2[1] = (q + 1 < qe) ? yz[q + 1] : make_float2(INFINITY, INFINITY);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) c4[j] = (k0 + j < kb) ? yz[k0 + j] : make_float2(INFINITY, INFINITY);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const double dy = (double)c4[j].x - yp;
-                const double dz = (double)c4[j].y - zp;
-                if (!(fabs(dy) <= wy) || !(fabs(dz) <= wz)) continue;
-                const int k = (int)(k0 + j);
-                const double chi2 = (dy * dy * s11 - 2.0 * dy * dz * s01 + dz * dz * s00) * idet;
-                bool take = best < 0 || chi2 < best_chi2;
-                if (!take && chi2 == best_chi2) take = B.perm[v.first + k] < B.perm[v.first + best];
-                if (take) {
-                    best = k;
-                    best_chi2 = chi2;
-                }
+        for (int j = 0; j < 2; ++j) {
+            const double dy = (double)c2[j].x - yp;
+            const double dz = (double)c2[j].y - zp;
+            if (!(fabs(dy) <= wy) || !(fabs(dz) <= wz)) continue;
+            const int k = (int)(q + j);
+            const double chi2 = (dy * dy * s11 - 2.0 * dy * dz * s01 + dz * dz * s00) * idet;
+            bool take = best < 0 || chi2 < best_chi2;
+            if (!take && chi2 == best_chi2) take = B.perm[v.first + k] < B.perm[v.first + best];
+            if (take) {
+                best = k;
+                best_chi2 = chi2;
+                best_c = c2[j];
             }
         }
+        q += 2;
     }
     return best;
 }
@@ -993,9 +1025,11 @@ __device__ int search_row(const Batch& B, const DevParams& P, int64_t g, const T
 // the chain in the tracklet's hit table and its length; chains of >= min_chain clusters
 // become tracklets.
 // ------------------------------------------------------------------------------------
+// Hit table, row-major: entry (r, p) at r * cap_starts + p, so that neighbouring
+// tracklets' entries for one row are adjacent.
 __device__ __forceinline__ uint16_t* hit_slot(const Batch& B, int r, int64_t p)
 {
-    return B.tl_hits + p * (int64_t)B.n_rows + r;
+    return B.tl_hits + (int64_t)r * B.cap_starts + p;
 }
 
 __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
@@ -1042,13 +1076,15 @@ __device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P
 // takes the least-chi2 cluster inside the window if chi2 <= chi2_max; it stops after
 // more than max_miss consecutive misses or when the propagation fails.  Clusters are
 // recorded per row (sorted positions); rows [rlo, rhi] are all written.  A failed seed,
-// fit or refit leaves a tracklet of size 0.
+// fit or refit leaves a tracklet of size 0.  A tracklet of >= min_track_hits clusters
+// then claims them (stage 6).
 //
-// Execution is step-uniform: every lane holds one tracklet and each pass of the loop
-// moves every lane by one row, whatever phase it is in, so the binary64 propagation and
-// update run on all lanes together.  Lanes that finish take the next tracklet from the
-// list (one queue atomic per wave per 64 tracklets); a finished tracklet of >= min_track_hits clusters
-// claims its clusters with the whole wave (one row per lane).
+// Execution is row-synchronous: a wave takes 64 consecutive tracklets in processing
+// order (one start row, neighbouring bins, so the tracks lie close together) and sweeps
+// the rows with all of them: upward for the chain fit and the outward follow, downward
+// for the refit and the inward follow, then once more for the claim.  At every pass all
+// lanes work on the same row, so row records, hit table entries (row-major) and search
+// windows are shared between the lanes of the wave.
 // ------------------------------------------------------------------------------------
 // Hands work items of [lo, hi) to the idle lanes of a wave, in lane order.  The range is
 // split into one segment per XCD with a queue head each; a wave takes kGrab items of its
@@ -1090,162 +1126,168 @@ __device__ int64_t take_item(int32_t* heads, int64_t lo, int64_t hi, uint64_t id
     return item;
 }
 
-enum : int { kIdle = 0, kFit = 1, kOut = 2, kRefit = 3, kIn = 4, kDone = 5, kExit = 6 };
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
 
-__global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int refill_min)
+enum : int { kWait = 0, kFit = 1, kOut = 2, kUpDone = 3, kRefit = 4, kIn = 5, kDone = 6 };
+
+__global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
-    const int lane = lane_id();
     const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
-    int phase = kIdle;
-    int64_t p = 0, gs = 0;
-    int r = 0, r0 = 0, rend = 0, rlo = 0, rhi = 0, n = 0, misses = 0;
     int64_t q_next = 0, q_end = 0;
     int q_seg = (int)blockIdx.x % xcd_parts(), q_tried = 0;
-    Trk tr;
     for (;;) {
-        // refill idle lanes; chains shorter than min_chain are not tracklets (size 0)
-        const uint64_t idle = __ballot(phase == kIdle);
-        const uint64_t busy = __ballot(phase >= kFit && phase <= kIn);
-        if (idle != 0ull && (__popcll(idle) >= refill_min || busy == 0ull)) {
-            const int64_t j = take_item(B.ctr->queue, lo, hi, idle, q_next, q_end, q_seg, q_tried);
-            if (phase == kIdle) {
-                const int L = j >= 0 ? B.tl_len[j] : 0;
-                if (j < 0) {
-                    phase = kExit;
-                } else if (L >= P.min_chain) {
-                    p = j;
-                    const int64_t g = B.st_row[p];
-                    r0 = (int)(g % nr);
-                    gs = g - r0;
-                    rend = r0 + L;
-                    rlo = r0;
-                    rhi = r0 + L - 1;
-                    const int rs[3] = {r0, r0 + (L - 1) / 2, r0 + L - 1};
-                    double sx[3], sy[3], sz[3];
-                    for (int q = 0; q < 3; ++q) {
-                        const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
-                        sx[q] = (double)P.rx[rs[q]];
-                        sy[q] = (double)c.x;
-                        sz[q] = (double)c.y;
-                    }
-                    if (trk_seed(tr, sx, sy, sz, P)) {
-                        trk_reset_cov(tr, P);
-                        phase = kFit;
-                        r = r0;
-                        n = L;
-                    } else {
-                        phase = kDone;
-                        n = 0;
-                    }
+        const int64_t p = take_item(B.ctr->queue, lo, hi, ~0ull, q_next, q_end, q_seg, q_tried);
+        if (__ballot(p >= 0) == 0ull) break;
+        const int L = p >= 0 ? B.tl_len[p] : 0;
+        const bool live = L >= P.min_chain;
+        int r0 = 0, rend = 0, rlo = 0, rhi = 0, n = 0, misses = 0, phase = kDone;
+        int64_t gs = 0;
+        Trk tr;
+        if (live) {
+            const int64_t g = B.st_row[p];
+            r0 = (int)(g % nr);
+            gs = g - r0;
+            rend = r0 + L;
+            rlo = r0;
+            rhi = r0 + L - 1;
+            const int rs[3] = {r0, r0 + (L - 1) / 2, r0 + L - 1};
+            double sx[3], sy[3], sz[3];
+            for (int q = 0; q < 3; ++q) {
+                const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
+                sx[q] = (double)P.rx[rs[q]];
+                sy[q] = (double)c.x;
+                sz[q] = (double)c.y;
+            }
+            if (trk_seed(tr, sx, sy, sz, P)) {
+                trk_reset_cov(tr, P);
+                phase = kWait;
+                n = L;
+            }
+        }
+
+        // upward: chain fit from r0, then follow outward
+        for (int r = wave_min_i(phase == kWait ? r0 : nr); r < nr && __ballot(phase <= kOut) != 0ull; ++r) {
+            if (phase == kWait && r == r0) phase = kFit;
+            const bool act = phase == kFit || phase == kOut;
+            bool moved = true;
+            if (act && !(phase == kFit && r == r0)) moved = trk_propagate(tr, (double)P.rx[r], P);
+            int k = -1;
+            float2 c = make_float2(0.0f, 0.0f);
+            if (act && moved) {
+                if (phase == kFit) {
+                    k = *hit_slot(B, r, p);
+                    c = B.yz[B.off[gs + r] + k];
+                } else {
+                    double chi2;
+                    k = search_row(B, P, B.row_f[gs + r], B.row_i[gs + r], gs + r, tr, chi2, c);
+                    if (k >= 0 && !(chi2 <= P.chi2_max)) k = -1;
                 }
             }
-        }
-        if (__ballot(phase != kExit) == 0ull) break;
-
-        // one row per lane
-        const bool act = phase >= kFit && phase <= kIn;
-        bool moved = true;
-        if (act && !(phase == kFit && r == r0)) moved = trk_propagate(tr, (double)P.rx[r], P);
-        int k = -1;
-        if (act && moved) {
-            if (phase == kFit || phase == kRefit) {
-                k = *hit_slot(B, r, p);
-            } else {
-                double chi2;
-                k = search_row(B, P, gs + r, tr, chi2);
-                if (k >= 0 && !(chi2 <= P.chi2_max)) k = -1;
-            }
-        }
-        if (k >= 0) {
-            const float2 c = B.yz[B.off[gs + r] + k];
-            trk_update(tr, (double)c.x, (double)c.y, P);
-        }
-        bool to_refit = false;
-        if (phase == kFit) {
-            if (!moved) {
-                phase = kDone;
-                n = 0;
-            } else if (++r == rend) {
-                phase = kOut;
-                misses = 0;
-                to_refit = r >= nr;
-            }
-        } else if (phase == kOut) {
-            if (!moved) {
-                to_refit = true;
-            } else {
-                if (k >= 0) {
+            if (k >= 0) trk_update(tr, (double)c.x, (double)c.y, P);
+            if (phase == kFit) {
+                if (!moved) {
+                    phase = kDone;
+                    n = 0;
+                } else if (r == rend - 1) {
+                    phase = kOut;
+                    misses = 0;
+                }
+            } else if (phase == kOut) {
+                if (!moved) {
+                    phase = kUpDone;
+                } else if (k >= 0) {
                     *hit_slot(B, r, p) = (uint16_t)k;
                     rhi = r;
                     misses = 0;
                     ++n;
                 } else {
                     *hit_slot(B, r, p) = kNoHit;
-                    to_refit = ++misses > P.max_miss;
+                    if (++misses > P.max_miss) phase = kUpDone;
                 }
-                if (!to_refit) to_refit = ++r >= nr;
-            }
-        } else if (phase == kRefit) {
-            if (!moved) {
-                phase = kDone;
-                n = 0;
-            } else {
-                int q = r - 1;
-                while (q >= r0 && *hit_slot(B, q, p) == kNoHit) --q;
-                if (q >= r0) {
-                    r = q;
-                } else {
-                    phase = kIn;
-                    misses = 0;
-                    r = r0 - 1;
-                    if (r < 0) phase = kDone;
-                }
-            }
-        } else if (phase == kIn) {
-            if (!moved) {
-                phase = kDone;
-            } else {
-                if (k >= 0) {
-                    *hit_slot(B, r, p) = (uint16_t)k;
-                    rlo = r;
-                    misses = 0;
-                    ++n;
-                } else {
-                    *hit_slot(B, r, p) = kNoHit;
-                    if (++misses > P.max_miss) phase = kDone;
-                }
-                if (phase == kIn && --r < 0) phase = kDone;
             }
         }
-        if (to_refit) {
+        if (phase == kOut || phase == kUpDone) {
             trk_reset_cov(tr, P);
             phase = kRefit;
-            r = rhi;
         }
 
-        // finished tracklets: record, then claim with the whole wave
-        uint64_t fin = __ballot(phase == kDone);
-        if (phase == kDone) {
+        // downward: refit over the rows with a cluster from rhi to r0, then follow inward
+        for (int r = wave_max_i(phase == kRefit ? rhi : -1); r >= 0 && __ballot(phase == kRefit || phase == kIn) != 0ull;
+             --r) {
+            bool act = false;
+            int k = -1;
+            if (phase == kRefit && r <= rhi) {
+                k = *hit_slot(B, r, p);
+                act = k != kNoHit;
+            } else if (phase == kIn) {
+                act = true;
+            }
+            bool moved = true;
+            if (act) moved = trk_propagate(tr, (double)P.rx[r], P);
+            float2 c = make_float2(0.0f, 0.0f);
+            if (act && moved) {
+                if (phase == kRefit) {
+                    c = B.yz[B.off[gs + r] + k];
+                } else {
+                    double chi2;
+                    k = search_row(B, P, B.row_f[gs + r], B.row_i[gs + r], gs + r, tr, chi2, c);
+                    if (k >= 0 && !(chi2 <= P.chi2_max)) k = -1;
+                }
+                if (k >= 0) trk_update(tr, (double)c.x, (double)c.y, P);
+            }
+            if (phase == kRefit && r <= rhi) {
+                if (act && !moved) {
+                    phase = kDone;
+                    n = 0;
+                } else if (r == r0) {
+                    phase = r0 > 0 ? kIn : kDone;
+                    misses = 0;
+                }
+            } else if (phase == kIn) {
+                if (!moved) {
+                    phase = kDone;
+                } else {
+                    if (k >= 0) {
+                        *hit_slot(B, r, p) = (uint16_t)k;
+                        rlo = r;
+                        misses = 0;
+                        ++n;
+                    } else {
+                        *hit_slot(B, r, p) = kNoHit;
+                        if (++misses > P.max_miss) phase = kDone;
+                    }
+                    if (r == 0) phase = kDone;
+                }
+            }
+        }
+
+        if (live) {
             B.tl_n[p] = n;
             B.tl_rlo[p] = (int16_t)rlo;
             B.tl_rhi[p] = (int16_t)rhi;
         }
-        while (fin != 0ull) {
-            const int j = __ffsll((unsigned long long)fin) - 1;
-            fin &= fin - 1ull;
-            const int nj = __shfl(n, j, 64);
-            if (nj < P.min_track_hits) continue;
-            const int64_t pj = __shfl(p, j, 64);
-            const int64_t gsj = __shfl(gs, j, 64);
-            const int rloj = __shfl(rlo, j, 64), rhij = __shfl(rhi, j, 64);
-            const uint32_t w = weight_of(B, P, nj, B.st_rank[pj], gsj);
-            for (int rr = rloj + lane; rr <= rhij; rr += 64) {
-                const uint16_t kk = *hit_slot(B, rr, pj);
-                if (kk != kNoHit) atomicMax(&B.W[B.off[gsj + rr] + kk], w);
+        // claim, row by row
+        const bool claim = live && n >= P.min_track_hits;
+        const uint32_t w = claim ? weight_of(B, P, n, B.st_rank[p], gs) : 0u;
+        const int c1 = wave_max_i(claim ? rhi : -1);
+        for (int r = wave_min_i(claim ? rlo : nr); r <= c1; ++r) {
+            if (claim && r >= rlo && r <= rhi) {
+                const uint16_t kk = *hit_slot(B, r, p);
+                if (kk != kNoHit) atomicMax(&B.W[B.off[gs + r] + kk], w);
             }
         }
-        if (phase == kDone) phase = kIdle;
     }
 }
 
@@ -1346,7 +1388,7 @@ __device__ __forceinline__ int nth_set_bit(uint64_t x, int k)
 
 enum : int { kFitIdle = 0, kFwd = 1, kBwd = 2, kFitDone = 3, kFitExit = 4 };
 
-__global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
+__global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P, int refill_min)
 {
     const int nr = P.n_rows;
     const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
@@ -1354,6 +1396,8 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
     int64_t i = 0, p = 0, gs = 0;
     uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
     int r = 0, rfirst = 0, rlast = 0, kept = 0;
+    int pk = 0;             // next cluster: sorted position in its row
+    int64_t poff = 0;       // and the row's first cluster
     bool ok = false;
     double chi2 = 0.0;
     int64_t q_next = 0, q_end = 0;
@@ -1361,7 +1405,8 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
     Trk tr;
     for (;;) {
         const uint64_t idle = __ballot(phase == kFitIdle);
-        if (idle != 0ull) {
+        const uint64_t busy = __ballot(phase == kFwd || phase == kBwd);
+        if (idle != 0ull && (__popcll(idle) >= refill_min || busy == 0ull)) {
             const int64_t j = take_item(B.ctr->fit_queue, lo, hi, idle, q_next, q_end, q_seg, q_tried);
             if (phase == kFitIdle) {
                 kept = j >= 0 ? B.keep_n[j] : 0;
@@ -1397,6 +1442,8 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
                         trk_reset_cov(tr, P);
                         phase = kFwd;
                         r = rfirst;
+                        pk = *hit_slot(B, r, p);
+                        poff = B.off[gs + r];
                     } else {
                         phase = kFitDone;
                         ok = false;
@@ -1407,11 +1454,12 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
         if (__ballot(phase != kFitExit) == 0ull) break;
 
         const bool act = phase == kFwd || phase == kBwd;
+        float2 c = make_float2(0.0f, 0.0f);
+        if (act) c = B.yz[poff + pk];   // located at the end of the previous pass
         bool moved = true;
         if (act && !(phase == kFwd && r == rfirst) && !(phase == kBwd && r == rlast))
             moved = trk_propagate(tr, (double)P.rx[r], P);
         if (act && moved) {
-            const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
             const double my = (double)c.x, mz = (double)c.y;
             if (phase == kBwd) chi2 += trk_chi2(tr, my, mz, P);
             trk_update(tr, my, mz, P);
@@ -1436,6 +1484,10 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
             } else {
                 r = row_at_or_below(m0, m1, m2, m3, r - 1);
             }
+        }
+        if (phase == kFwd || phase == kBwd) {   // locate the next step's cluster
+            pk = *hit_slot(B, r, p);
+            poff = B.off[gs + r];
         }
         if (phase == kFitDone) {
             if (ok) {
@@ -1676,7 +1728,7 @@ void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hi
 {
     const int wpb = c.tl_block / 64;
     const int blocks = c.n_cu * (16 / wpb > 0 ? 16 / wpb : 1);
-    hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(c.tl_block), 0, s, b, p, c.chunk);
+    hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(c.tl_block), 0, s, b, p);
 }
 
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
@@ -1699,7 +1751,7 @@ void launch_fit_scan(const Batch& b, const DevParams& p, hipStream_t s)
 
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+    hipLaunchKernelGGL(k_fit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p, c.chunk);
 }
 
 void launch_track_scan(const Batch& b, hipStream_t s)

@@ -387,9 +387,11 @@ def default_sweep():
     """Tuning points of the autotuner: grid bin sizes and bin cap crossed with launch
     shapes (row-kernel block, tracklet block, work-queue chunk)."""
     bins = [dict(bin_y=1.0, bin_z=2.0, cap_mul=2), dict(bin_y=2.0, bin_z=2.0, cap_mul=2),
-            dict(bin_y=2.0, bin_z=8.0, cap_mul=2), dict(bin_y=4.0, bin_z=4.0, cap_mul=2),
-            dict(bin_y=1.0, bin_z=1.0, cap_mul=4), dict(bin_y=2.0, bin_z=4.0, cap_mul=4),
-            dict(bin_y=3.0, bin_z=3.0, cap_mul=8)]
+            dict(bin_y=4.0, bin_z=4.0, cap_mul=2), dict(bin_y=2.0, bin_z=4.0, cap_mul=4),
+            dict(bin_y=3.0, bin_z=3.0, cap_mul=8), dict(bin_y=16.0, bin_z=1.0, cap_mul=4),
+            # one y-bin per row: a window's z-bins form one contiguous range
+            dict(bin_y=1000.0, bin_z=0.5, cap_mul=2), dict(bin_y=1000.0, bin_z=1.0, cap_mul=2),
+            dict(bin_y=1000.0, bin_z=2.0, cap_mul=2)]
     shapes = [dict(block=256, tl_block=256, chunk=1), dict(block=128, tl_block=128, chunk=1),
               dict(block=256, tl_block=64, chunk=1), dict(block=512, tl_block=256, chunk=2)]
     return [dict(b, **sh) for b in bins for sh in shapes]
