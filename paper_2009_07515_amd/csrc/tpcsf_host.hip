@@ -22,7 +22,7 @@ struct Layout {
     int64_t n = 0, R = 0, cap_starts = 0, cap_fit = 0, n_bins = 0;
     size_t row_lo, row_bin, row_nb, row_f, row_i, row_nstart, row_sbase;
     size_t bin_start, yz, perm, iperm, upk, dnk, cupk, cdnk, rank_at, W;
-    size_t st_row, st_k, st_rank, tl_len, tl_n, tl_rlo, tl_rhi, tl_hits;
+    size_t st_row, st_k, st_rank, tl_len, order, tl_n, tl_rlo, tl_rhi, tl_hits;
     size_t keep_n, fit_pos, keep_mask, fit_list;
     size_t trk_flag, hit_cnt, trk_idx, hit_pos, trk_out;
     size_t f_par, f_cov, f_chi2, f_xref, scan_part;
@@ -124,6 +124,7 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.st_k = take(S * 4);
     L.st_rank = take(S * 4);
     L.tl_len = take(S * 4);
+    L.order = take(S * 4);
     L.tl_n = take(S * 4);
     L.tl_rlo = take(S * 2);
     L.tl_rhi = take(S * 2);
@@ -276,6 +277,7 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.st_rank = (int32_t*)(a + L.st_rank);
     B.cap_starts = L.cap_starts;
     B.tl_len = (int32_t*)(a + L.tl_len);
+    B.order = (int32_t*)(a + L.order);
     B.tl_n = (int32_t*)(a + L.tl_n);
     B.tl_rlo = (int16_t*)(a + L.tl_rlo);
     B.tl_rhi = (int16_t*)(a + L.tl_rhi);
@@ -329,9 +331,10 @@ void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t
     mark(); launch_row_scan(B, 0, R, s);
     mark(); launch_starts(B, P, 0, R, LC, s);
     mark(); launch_walk(B, P, LC, s);
+    launch_order(B, P, LC, s);
     mark(); launch_tracklets(B, P, LC, s);
     mark(); launch_keep(B, P, LC, s);
-    launch_fit_scan(B, P, s);
+    launch_fit_scan(B, P, LC, s);
     mark(); launch_fit(B, P, LC, s);
     mark(); launch_track_scan(B, s);
     mark(); launch_emit(B, P, LC, s);
@@ -472,9 +475,10 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
             launch_row_scan(B, g0, g1, s);
             launch_starts(B, P, g0, g1, LC, s);
             launch_walk(B, P, LC, s);
+            launch_order(B, P, LC, s);
             launch_tracklets(B, P, LC, s);
             launch_keep(B, P, LC, s);
-            launch_fit_scan(B, P, s);
+            launch_fit_scan(B, P, LC, s);
             launch_fit(B, P, LC, s);
             launch_track_scan(B, s);
             launch_emit(B, P, LC, s);

@@ -35,6 +35,7 @@ struct Counters {
     int64_t rank_lo, rank_hi;       // rank range of the starts of the current launch set
     int64_t track_base;             // tracks emitted so far
     int64_t hit_base;               // hits emitted so far
+    int64_t n_order;                // tracklets to build (chains of >= min_chain)
     int64_t n_fit;                  // track candidates (>= min_track_hits kept)
     int32_t queue[8];               // tracklet work queue: head of each XCD's segment
     int32_t fit_queue[8];           // fit work queue: head of each XCD's segment
@@ -80,6 +81,7 @@ struct Batch {
     int64_t cap_starts;
     // tracklets (p indexed); hit table H[p * n_rows + r]
     int32_t* tl_len;                // chain length
+    int32_t* order;                 // [cap_starts] p of every tracklet to build, in p order
     int32_t* tl_n;                  // clusters, 0 = none
     int16_t* tl_rlo;                // first row holding a cluster
     int16_t* tl_rhi;                // last row holding a cluster
@@ -134,9 +136,10 @@ void launch_clean(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, co
 void launch_row_scan(const Batch& b, int64_t g0, int64_t g1, hipStream_t s);
 void launch_starts(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
 void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
+void launch_order(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
-void launch_fit_scan(const Batch& b, const DevParams& p, hipStream_t s);
+void launch_fit_scan(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_track_scan(const Batch& b, hipStream_t s);
 void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);

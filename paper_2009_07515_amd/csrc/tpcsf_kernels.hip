@@ -151,6 +151,7 @@ __global__ void k_reset(Batch B)
         c->track_base = 0;
         c->hit_base = 0;
         c->n_fit = 0;
+        c->n_order = 0;
         for (int x = 0; x < kXcds; ++x) {
             c->queue[x] = 0;
             c->fit_queue[x] = 0;
@@ -1054,6 +1055,16 @@ __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
     }
 }
 
+// The tracklets to build, listed in processing order: slot from a device scan of the
+// chain lengths (fit_pos serves as the scan's output here; the fit stage rewrites it).
+__global__ void __launch_bounds__(256) k_order(Batch B, DevParams P)
+{
+    int64_t first, end, stride;
+    xcd_span(B.ctr->rank_lo, B.ctr->rank_hi, first, end, stride);
+    for (int64_t p = first; p < end; p += stride)
+        if (B.tl_len[p] >= P.min_chain) B.order[B.fit_pos[p]] = (int32_t)p;
+}
+
 // ------------------------------------------------------------------------------------
 // Stage 6, selection.  A tracklet's weight orders tracklets by (clusters, then smaller
 // rank); every cluster ends with the largest weight of the tracklets that contain it
@@ -1079,9 +1090,9 @@ __device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P
 // fit or refit leaves a tracklet of size 0.  A tracklet of >= min_track_hits clusters
 // then claims them (stage 6).
 //
-// Execution is row-synchronous: a wave takes 64 consecutive tracklets in processing
-// order (one start row, neighbouring bins, so the tracks lie close together) and sweeps
-// the rows with all of them: upward for the chain fit and the outward follow, downward
+// Execution is row-synchronous: a wave takes 64 consecutive tracklets of the list, which
+// is in processing order (one start row, neighbouring bins: the tracks lie close
+// together), and sweeps the rows with all of them: upward for the chain fit and the outward follow, downward
 // for the refit and the inward follow, then once more for the claim.  At every pass all
 // lanes work on the same row, so row records, hit table entries (row-major) and search
 // windows are shared between the lanes of the wave.
@@ -1144,12 +1155,12 @@ enum : int { kWait = 0, kFit = 1, kOut = 2, kUpDone = 3, kRefit = 4, kIn = 5, kD
 __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
     int64_t q_next = 0, q_end = 0;
     int q_seg = (int)blockIdx.x % xcd_parts(), q_tried = 0;
     for (;;) {
-        const int64_t p = take_item(B.ctr->queue, lo, hi, ~0ull, q_next, q_end, q_seg, q_tried);
-        if (__ballot(p >= 0) == 0ull) break;
+        const int64_t j = take_item(B.ctr->queue, 0, B.ctr->n_order, ~0ull, q_next, q_end, q_seg, q_tried);
+        if (__ballot(j >= 0) == 0ull) break;
+        const int64_t p = j >= 0 ? (int64_t)B.order[j] : -1;
         const int L = p >= 0 ? B.tl_len[p] : 0;
         const bool live = L >= P.min_chain;
         int r0 = 0, rend = 0, rlo = 0, rhi = 0, n = 0, misses = 0, phase = kDone;
@@ -1341,8 +1352,8 @@ __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
 // Result at the innermost kept cluster; a failed fit drops the track.  Results are
 // stored at the candidate's list slot.
 //
-// Step-uniform like the tracklet stage: one candidate per lane, one kept row per pass of
-// the loop, finished lanes refill from the work queue over processing order.
+// Row-synchronous like the tracklet stage: a wave takes 64 consecutive candidates and
+// sweeps their kept rows outward, then inward, all lanes on the same row at each pass.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t mask_word(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3, int w)
 {
@@ -1386,126 +1397,100 @@ __device__ __forceinline__ int nth_set_bit(uint64_t x, int k)
     return pos;
 }
 
-enum : int { kFitIdle = 0, kFwd = 1, kBwd = 2, kFitDone = 3, kFitExit = 4 };
+// Candidates listed by slot (processing order), from the scan of the kept counts.
+__global__ void __launch_bounds__(256) k_fit_list(Batch B, DevParams P)
+{
+    int64_t first, end, stride;
+    xcd_span(B.ctr->rank_lo, B.ctr->rank_hi, first, end, stride);
+    for (int64_t p = first; p < end; p += stride)
+        if (B.keep_n[p] > 0) B.fit_list[B.fit_pos[p]] = (int32_t)p;
+}
 
-__global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P, int refill_min)
+__device__ __forceinline__ bool row_set(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3, int r)
+{
+    return (mask_word(m0, m1, m2, m3, r >> 6) >> (r & 63)) & 1ull;
+}
+
+__global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
-    const int64_t lo = B.ctr->rank_lo, hi = B.ctr->rank_hi;
-    int phase = kFitIdle;
-    int64_t i = 0, p = 0, gs = 0;
-    uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-    int r = 0, rfirst = 0, rlast = 0, kept = 0;
-    int pk = 0;             // next cluster: sorted position in its row
-    int64_t poff = 0;       // and the row's first cluster
-    bool ok = false;
-    double chi2 = 0.0;
     int64_t q_next = 0, q_end = 0;
     int q_seg = (int)blockIdx.x % xcd_parts(), q_tried = 0;
-    Trk tr;
     for (;;) {
-        const uint64_t idle = __ballot(phase == kFitIdle);
-        const uint64_t busy = __ballot(phase == kFwd || phase == kBwd);
-        if (idle != 0ull && (__popcll(idle) >= refill_min || busy == 0ull)) {
-            const int64_t j = take_item(B.ctr->fit_queue, lo, hi, idle, q_next, q_end, q_seg, q_tried);
-            if (phase == kFitIdle) {
-                kept = j >= 0 ? B.keep_n[j] : 0;
-                if (j < 0) {
-                    phase = kFitExit;
-                } else if (kept > 0) {
-                    p = j;
-                    i = B.fit_pos[p];
-                    B.fit_list[i] = (int32_t)p;
-                    const int64_t g = B.st_row[p];
-                    gs = g - g % nr;
-                    m0 = B.keep_mask[p * 4 + 0]; m1 = B.keep_mask[p * 4 + 1];
-                    m2 = B.keep_mask[p * 4 + 2]; m3 = B.keep_mask[p * 4 + 3];
-                    rfirst = row_at_or_above(m0, m1, m2, m3, 0);
-                    rlast = row_at_or_below(m0, m1, m2, m3, kMaxRows - 1);
-                    int want = (kept - 1) / 2, rmid = rfirst;
-                    for (int w = 0; w < 4; ++w) {
-                        const uint64_t x = mask_word(m0, m1, m2, m3, w);
-                        const int c = __popcll(x);
-                        if (want < c) { rmid = (w << 6) + nth_set_bit(x, want); break; }
-                        want -= c;
-                    }
-                    const int rs[3] = {rfirst, rmid, rlast};
-                    double sx[3], sy[3], sz[3];
-                    for (int q = 0; q < 3; ++q) {
-                        const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
-                        sx[q] = (double)P.rx[rs[q]];
-                        sy[q] = (double)c.x;
-                        sz[q] = (double)c.y;
-                    }
-                    chi2 = 0.0;
-                    if (trk_seed(tr, sx, sy, sz, P)) {
-                        trk_reset_cov(tr, P);
-                        phase = kFwd;
-                        r = rfirst;
-                        pk = *hit_slot(B, r, p);
-                        poff = B.off[gs + r];
-                    } else {
-                        phase = kFitDone;
-                        ok = false;
-                    }
-                }
+        const int64_t i = take_item(B.ctr->fit_queue, 0, B.ctr->n_fit, ~0ull, q_next, q_end, q_seg, q_tried);
+        if (__ballot(i >= 0) == 0ull) break;
+        const bool live = i >= 0;
+        int64_t p = 0, gs = 0;
+        uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+        int rfirst = nr, rlast = -1, kept = 0;
+        bool ok = false;
+        Trk tr;
+        if (live) {
+            p = B.fit_list[i];
+            kept = B.keep_n[p];
+            const int64_t g = B.st_row[p];
+            gs = g - g % nr;
+            m0 = B.keep_mask[p * 4 + 0]; m1 = B.keep_mask[p * 4 + 1];
+            m2 = B.keep_mask[p * 4 + 2]; m3 = B.keep_mask[p * 4 + 3];
+            rfirst = row_at_or_above(m0, m1, m2, m3, 0);
+            rlast = row_at_or_below(m0, m1, m2, m3, kMaxRows - 1);
+            int want = (kept - 1) / 2, rmid = rfirst;
+            for (int w = 0; w < 4; ++w) {
+                const uint64_t x = mask_word(m0, m1, m2, m3, w);
+                const int c = __popcll(x);
+                if (want < c) { rmid = (w << 6) + nth_set_bit(x, want); break; }
+                want -= c;
             }
+            const int rs[3] = {rfirst, rmid, rlast};
+            double sx[3], sy[3], sz[3];
+            for (int q = 0; q < 3; ++q) {
+                const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
+                sx[q] = (double)P.rx[rs[q]];
+                sy[q] = (double)c.x;
+                sz[q] = (double)c.y;
+            }
+            ok = trk_seed(tr, sx, sy, sz, P);
+            if (ok) trk_reset_cov(tr, P);
         }
-        if (__ballot(phase != kFitExit) == 0ull) break;
-
-        const bool act = phase == kFwd || phase == kBwd;
-        float2 c = make_float2(0.0f, 0.0f);
-        if (act) c = B.yz[poff + pk];   // located at the end of the previous pass
-        bool moved = true;
-        if (act && !(phase == kFwd && r == rfirst) && !(phase == kBwd && r == rlast))
-            moved = trk_propagate(tr, (double)P.rx[r], P);
-        if (act && moved) {
+        // outward over the kept rows
+        const int ra = wave_min_i(ok ? rfirst : nr), rb = wave_max_i(ok ? rlast : -1);
+        for (int r = ra; r <= rb; ++r) {
+            if (!(ok && row_set(m0, m1, m2, m3, r))) continue;
+            if (r > rfirst && !trk_propagate(tr, (double)P.rx[r], P)) {
+                ok = false;
+                continue;
+            }
+            const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
+            trk_update(tr, (double)c.x, (double)c.y, P);
+        }
+        if (ok) trk_reset_cov(tr, P);
+        // inward from the last kept row, summing chi2 before each update
+        double chi2 = 0.0;
+        for (int r = rb; r >= ra; --r) {
+            if (!(ok && row_set(m0, m1, m2, m3, r))) continue;
+            if (r < rlast && !trk_propagate(tr, (double)P.rx[r], P)) {
+                ok = false;
+                continue;
+            }
+            const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
             const double my = (double)c.x, mz = (double)c.y;
-            if (phase == kBwd) chi2 += trk_chi2(tr, my, mz, P);
+            chi2 += trk_chi2(tr, my, mz, P);
             trk_update(tr, my, mz, P);
         }
-        if (phase == kFwd) {
-            if (!moved) {
-                phase = kFitDone;
-                ok = false;
-            } else if (r == rlast) {
-                trk_reset_cov(tr, P);
-                phase = kBwd;
-            } else {
-                r = row_at_or_above(m0, m1, m2, m3, r + 1);
-            }
-        } else if (phase == kBwd) {
-            if (!moved) {
-                phase = kFitDone;
-                ok = false;
-            } else if (r == rfirst) {
-                phase = kFitDone;
-                ok = true;
-            } else {
-                r = row_at_or_below(m0, m1, m2, m3, r - 1);
-            }
+        if (ok) {
+            for (int q = 0; q < 5; ++q) ok = ok && isfinite(tr.p[q]);
+            for (int q = 0; q < 15; ++q) ok = ok && isfinite(tr.c[q]);
         }
-        if (phase == kFwd || phase == kBwd) {   // locate the next step's cluster
-            pk = *hit_slot(B, r, p);
-            poff = B.off[gs + r];
-        }
-        if (phase == kFitDone) {
-            if (ok) {
-                for (int q = 0; q < 5; ++q) ok = ok && isfinite(tr.p[q]);
-                for (int q = 0; q < 15; ++q) ok = ok && isfinite(tr.c[q]);
-            }
-            if (ok) {
-                double* fp = B.f_par + i * 5;
-                double* fc = B.f_cov + i * 15;
-                for (int q = 0; q < 5; ++q) fp[q] = tr.p[q];
-                for (int q = 0; q < 15; ++q) fc[q] = tr.c[q];
-                B.f_chi2[i] = chi2;
-                B.f_xref[i] = tr.x;
-                const int64_t rank = B.st_rank[p];
-                B.trk_flag[rank] = 1;
-                B.hit_cnt[rank] = kept;
-            }
-            phase = kFitIdle;
+        if (ok) {
+            double* fp = B.f_par + i * 5;
+            double* fc = B.f_cov + i * 15;
+            for (int q = 0; q < 5; ++q) fp[q] = tr.p[q];
+            for (int q = 0; q < 15; ++q) fc[q] = tr.c[q];
+            B.f_chi2[i] = chi2;
+            B.f_xref[i] = tr.x;
+            const int64_t rank = B.st_rank[p];
+            B.trk_flag[rank] = 1;
+            B.hit_cnt[rank] = kept;
         }
     }
 }
@@ -1724,6 +1709,20 @@ void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStre
     hipLaunchKernelGGL(k_walk, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
+void launch_order(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
+{
+    ScanJob J = {};
+    J.a32 = b.tl_len;
+    J.a_min = p.min_chain > 0 ? p.min_chain : 1;
+    J.outA = b.fit_pos;
+    J.lo_ptr = &b.ctr->rank_lo;
+    J.hi_ptr = &b.ctr->rank_hi;
+    J.totA = &b.ctr->n_order;
+    J.part = b.scan_part;
+    run_scan(J, s);
+    hipLaunchKernelGGL(k_order, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+}
+
 void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     const int wpb = c.tl_block / 64;
@@ -1736,7 +1735,7 @@ void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStre
     hipLaunchKernelGGL(k_keep, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
-void launch_fit_scan(const Batch& b, const DevParams& p, hipStream_t s)
+void launch_fit_scan(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     ScanJob J = {};
     J.a32 = b.keep_n;
@@ -1747,11 +1746,12 @@ void launch_fit_scan(const Batch& b, const DevParams& p, hipStream_t s)
     J.totA = &b.ctr->n_fit;
     J.part = b.scan_part;
     run_scan(J, s);
+    hipLaunchKernelGGL(k_fit_list, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p, c.chunk);
+    hipLaunchKernelGGL(k_fit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
 void launch_track_scan(const Batch& b, hipStream_t s)
