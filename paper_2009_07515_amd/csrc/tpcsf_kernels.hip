@@ -1310,38 +1310,55 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
 __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
+    const int lane = lane_id();
     if (blockIdx.x == 0 && threadIdx.x == 0)   // the tracklet queue is done
         for (int x = 0; x < kXcds; ++x) B.ctr->queue[x] = 0;
     int64_t first, end, stride;
     xcd_span(B.ctr->rank_lo, B.ctr->rank_hi, first, end, stride);
-    for (int64_t p = first; p < end; p += stride) {
-        const int64_t rank = B.st_rank[p];
-        B.trk_flag[rank] = 0;
-        B.hit_cnt[rank] = 0;
-        B.trk_out[rank] = -1;
-        int kept = 0;
-        const int n = B.tl_n[p];
-        if (n >= P.min_track_hits) {
-            const int64_t g = B.st_row[p];
-            const int64_t gs = g - g % nr;
-            const uint32_t w = weight_of(B, P, n, rank, gs);
-            const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
-            uint64_t m[4] = {0, 0, 0, 0};
-            for (int r = rlo; r <= rhi; ++r) {
-                const uint16_t k = *hit_slot(B, r, p);
-                if (k == kNoHit) continue;
-                if (B.W[B.off[gs + r] + k] == w) {
-                    m[r >> 6] |= 1ull << (r & 63);
-                    ++kept;
-                }
-            }
-            if (kept >= P.min_track_hits) {
-                for (int i = 0; i < 4; ++i) B.keep_mask[p * 4 + i] = m[i];
-            } else {
-                kept = 0;
+    // wave-uniform loop over 64 consecutive tracklets, their rows swept together
+    for (int64_t p0 = first - lane; p0 < end; p0 += stride) {
+        const int64_t p = p0 + lane;
+        const bool in = p < end;
+        int n = 0, rlo = nr, rhi = -1;
+        int64_t gs = 0;
+        uint32_t w = 0u;
+        if (in) {
+            const int64_t rank = B.st_rank[p];
+            B.trk_flag[rank] = 0;
+            B.hit_cnt[rank] = 0;
+            B.trk_out[rank] = -1;
+            n = B.tl_n[p];
+            if (n >= P.min_track_hits) {
+                const int64_t g = B.st_row[p];
+                gs = g - g % nr;
+                w = weight_of(B, P, n, rank, gs);
+                rlo = B.tl_rlo[p];
+                rhi = B.tl_rhi[p];
             }
         }
-        B.keep_n[p] = kept;
+        const bool sel = in && n >= P.min_track_hits;
+        uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+        int kept = 0;
+        const int rb = wave_max_i(sel ? rhi : -1);
+        for (int r = wave_min_i(sel ? rlo : nr); r <= rb; ++r) {
+            if (!(sel && r >= rlo && r <= rhi)) continue;
+            const uint16_t k = *hit_slot(B, r, p);
+            if (k == kNoHit || B.W[B.off[gs + r] + k] != w) continue;
+            const uint64_t bit = 1ull << (r & 63);
+            const int wd = r >> 6;
+            m0 |= wd == 0 ? bit : 0ull;
+            m1 |= wd == 1 ? bit : 0ull;
+            m2 |= wd == 2 ? bit : 0ull;
+            m3 |= wd == 3 ? bit : 0ull;
+            ++kept;
+        }
+        if (sel && kept >= P.min_track_hits) {
+            B.keep_mask[p * 4 + 0] = m0; B.keep_mask[p * 4 + 1] = m1;
+            B.keep_mask[p * 4 + 2] = m2; B.keep_mask[p * 4 + 3] = m3;
+        } else {
+            kept = 0;
+        }
+        if (in) B.keep_n[p] = kept;
     }
 }
 
@@ -1503,37 +1520,55 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
+    const int lane = lane_id();
     int64_t first, end, stride;
     xcd_span(0, B.ctr->n_fit, first, end, stride);
-    for (int64_t i = first; i < end; i += stride) {
-        const int64_t p = B.fit_list[i];
-        const int64_t rank = B.st_rank[p];
-        if (!B.trk_flag[rank]) continue;
-        const int64_t T = B.trk_idx[rank];
-        const int64_t hp = B.hit_pos[rank];
-        const int nk = B.hit_cnt[rank];
-        const int64_t g = B.st_row[p];
-        const int64_t gs = g - g % nr;
-        if (T >= B.cap_tracks || hp + nk > B.cap_hits) {
-            atomicOr(&B.ctr->err, kErrOutCap);
-            continue;
+    // wave-uniform loop over 64 consecutive candidates; their hit lists are written row
+    // by row with all lanes on the same row
+    for (int64_t i0 = first - lane; i0 < end; i0 += stride) {
+        const int64_t i = i0 + lane;
+        bool on = i < end;
+        int64_t p = 0, gs = 0, j = 0;
+        uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+        int rlo = nr, rhi = -1;
+        if (on) {
+            p = B.fit_list[i];
+            const int64_t rank = B.st_rank[p];
+            on = B.trk_flag[rank] != 0;
+            if (on) {
+                const int64_t T = B.trk_idx[rank];
+                const int64_t hp = B.hit_pos[rank];
+                const int nk = B.hit_cnt[rank];
+                const int64_t g = B.st_row[p];
+                gs = g - g % nr;
+                if (T >= B.cap_tracks || hp + nk > B.cap_hits) {
+                    atomicOr(&B.ctr->err, kErrOutCap);
+                    on = false;
+                } else {
+                    for (int q = 0; q < 5; ++q) B.o_par[T * 5 + q] = B.f_par[i * 5 + q];
+                    for (int q = 0; q < 15; ++q) B.o_cov[T * 15 + q] = B.f_cov[i * 15 + q];
+                    B.o_xref[T] = B.f_xref[i];
+                    B.o_chi2[T] = B.f_chi2[i];
+                    B.o_ndf[T] = 2 * nk - 5;
+                    B.o_nhits_trk[T] = nk;
+                    B.o_sector[T] = (int32_t)((g / nr) % P.n_sectors);
+                    B.o_tf[T] = (int32_t)(g / ((int64_t)nr * P.n_sectors));
+                    B.o_hit_off[T + 1] = hp + nk;
+                    B.trk_out[rank] = (int32_t)T;
+                    m0 = B.keep_mask[p * 4 + 0]; m1 = B.keep_mask[p * 4 + 1];
+                    m2 = B.keep_mask[p * 4 + 2]; m3 = B.keep_mask[p * 4 + 3];
+                    rlo = B.tl_rlo[p];
+                    rhi = B.tl_rhi[p];
+                    j = hp;
+                }
+            }
         }
-        for (int q = 0; q < 5; ++q) B.o_par[T * 5 + q] = B.f_par[i * 5 + q];
-        for (int q = 0; q < 15; ++q) B.o_cov[T * 15 + q] = B.f_cov[i * 15 + q];
-        B.o_xref[T] = B.f_xref[i];
-        B.o_chi2[T] = B.f_chi2[i];
-        B.o_ndf[T] = 2 * nk - 5;
-        B.o_nhits_trk[T] = nk;
-        B.o_sector[T] = (int32_t)((g / nr) % P.n_sectors);
-        B.o_tf[T] = (int32_t)(g / ((int64_t)nr * P.n_sectors));
-        B.o_hit_off[T + 1] = hp + nk;
-        B.trk_out[rank] = (int32_t)T;
-        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
-        int64_t j = hp;
-        for (int r = rlo; r <= rhi; ++r) {
-            if (!((B.keep_mask[p * 4 + (r >> 6)] >> (r & 63)) & 1ull)) continue;
-            const int64_t first = B.off[gs + r];
-            B.o_hit_ids[j++] = (int32_t)(first + B.perm[first + *hit_slot(B, r, p)]);
+        const int rb = wave_max_i(rhi);
+        for (int r = wave_min_i(rlo); r <= rb; ++r) {
+            if (on && row_set(m0, m1, m2, m3, r)) {
+                const int64_t f = B.off[gs + r];
+                B.o_hit_ids[j++] = (int32_t)(f + B.perm[f + *hit_slot(B, r, p)]);
+            }
         }
     }
 }
