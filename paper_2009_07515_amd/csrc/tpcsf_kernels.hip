@@ -1150,6 +1150,8 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
+constexpr int kRowBatch = 8;   // rows per pass of the claim, keep and emit sweeps
+
 enum : int { kWait = 0, kFit = 1, kOut = 2, kUpDone = 3, kRefit = 4, kIn = 5, kDone = 6 };
 
 __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
@@ -1289,15 +1291,24 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
             B.tl_rlo[p] = (int16_t)rlo;
             B.tl_rhi[p] = (int16_t)rhi;
         }
-        // claim, row by row
+        // claim, kRowBatch rows per pass: the loads of all of them are issued before
+        // their atomics
         const bool claim = live && n >= P.min_track_hits;
         const uint32_t w = claim ? weight_of(B, P, n, B.st_rank[p], gs) : 0u;
         const int c1 = wave_max_i(claim ? rhi : -1);
-        for (int r = wave_min_i(claim ? rlo : nr); r <= c1; ++r) {
-            if (claim && r >= rlo && r <= rhi) {
-                const uint16_t kk = *hit_slot(B, r, p);
-                if (kk != kNoHit) atomicMax(&B.W[B.off[gs + r] + kk], w);
+        for (int r = wave_min_i(claim ? rlo : nr); r <= c1; r += kRowBatch) {
+            uint16_t kk[kRowBatch];
+            int64_t ff[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int rr = r + u;
+                const bool on = claim && rr >= rlo && rr <= rhi;
+                kk[u] = on ? *hit_slot(B, rr, p) : kNoHit;
+                ff[u] = on ? B.off[gs + rr] : 0;
             }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u)
+                if (kk[u] != kNoHit) atomicMax(&B.W[ff[u] + kk[u]], w);
         }
     }
 }
@@ -1340,17 +1351,31 @@ __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
         uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
         int kept = 0;
         const int rb = wave_max_i(sel ? rhi : -1);
-        for (int r = wave_min_i(sel ? rlo : nr); r <= rb; ++r) {
-            if (!(sel && r >= rlo && r <= rhi)) continue;
-            const uint16_t k = *hit_slot(B, r, p);
-            if (k == kNoHit || B.W[B.off[gs + r] + k] != w) continue;
-            const uint64_t bit = 1ull << (r & 63);
-            const int wd = r >> 6;
-            m0 |= wd == 0 ? bit : 0ull;
-            m1 |= wd == 1 ? bit : 0ull;
-            m2 |= wd == 2 ? bit : 0ull;
-            m3 |= wd == 3 ? bit : 0ull;
-            ++kept;
+        for (int r = wave_min_i(sel ? rlo : nr); r <= rb; r += kRowBatch) {
+            uint16_t kk[kRowBatch];
+            int64_t ff[kRowBatch];
+            uint32_t ww[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int rr = r + u;
+                const bool on = sel && rr >= rlo && rr <= rhi;
+                kk[u] = on ? *hit_slot(B, rr, p) : kNoHit;
+                ff[u] = on ? B.off[gs + rr] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) ww[u] = kk[u] != kNoHit ? B.W[ff[u] + kk[u]] : 0u;
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                if (kk[u] == kNoHit || ww[u] != w) continue;
+                const int rr = r + u;
+                const uint64_t bit = 1ull << (rr & 63);
+                const int wd = rr >> 6;
+                m0 |= wd == 0 ? bit : 0ull;
+                m1 |= wd == 1 ? bit : 0ull;
+                m2 |= wd == 2 ? bit : 0ull;
+                m3 |= wd == 3 ? bit : 0ull;
+                ++kept;
+            }
         }
         if (sel && kept >= P.min_track_hits) {
             B.keep_mask[p * 4 + 0] = m0; B.keep_mask[p * 4 + 1] = m1;
@@ -1564,11 +1589,21 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
             }
         }
         const int rb = wave_max_i(rhi);
-        for (int r = wave_min_i(rlo); r <= rb; ++r) {
-            if (on && row_set(m0, m1, m2, m3, r)) {
-                const int64_t f = B.off[gs + r];
-                B.o_hit_ids[j++] = (int32_t)(f + B.perm[f + *hit_slot(B, r, p)]);
+        for (int r = wave_min_i(rlo); r <= rb; r += kRowBatch) {
+            uint32_t kk[kRowBatch];
+            int64_t ff[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int rr = r + u;
+                const bool set = on && rr <= rhi && row_set(m0, m1, m2, m3, rr);
+                kk[u] = set ? *hit_slot(B, rr, p) : 0xFFFFFFFFu;
+                ff[u] = set ? B.off[gs + rr] : 0;
             }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) kk[u] = kk[u] != 0xFFFFFFFFu ? B.perm[ff[u] + kk[u]] : 0xFFFFFFFFu;
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u)
+                if (kk[u] != 0xFFFFFFFFu) B.o_hit_ids[j++] = (int32_t)(ff[u] + kk[u]);
         }
     }
 }
