@@ -840,10 +840,12 @@ __device__ bool trk_propagate(Trk& t, double x1, const DevParams& P)
     const double kap = P.a * t.p[4];
     const double s1 = s0 + kap * dx;
     if (!(fabs(s0) < P.sinphi_max) || !(fabs(s1) < P.sinphi_max)) return false;
-    const double c0 = sqrt((1.0 - s0) * (1.0 + s0));
-    const double c1 = sqrt((1.0 - s1) * (1.0 + s1));
-    const double cs = c0 + c1;
-    const double tb = (s0 + s1) / cs;
+    // cos(phi) at both ends and their reciprocals from one reciprocal square root each
+    const double u0 = (1.0 - s0) * (1.0 + s0), u1 = (1.0 - s1) * (1.0 + s1);
+    const double ic0 = rsqrt(u0), ic1 = rsqrt(u1);
+    const double c0 = u0 * ic0, c1 = u1 * ic1;
+    const double ics = 1.0 / (c0 + c1);
+    const double tb = (s0 + s1) * ics;
     const double sec2 = 1.0 + tb * tb;
     const double sec = sqrt(sec2);
     const double chord = dx * sec;
@@ -852,11 +854,10 @@ __device__ bool trk_propagate(Trk& t, double x1, const DevParams& P)
     double A, Ap;
     arc_factor(h, A, Ap);
     const double ds = chord * A;
-    const double ic0 = 1.0 / c0, ic1 = 1.0 / c1;
     const double q = 0.5 * tb * dx * ic1;
     const double j02 = 0.5 * dx * sec2 * (ic0 + ic1);
     const double j04 = P.a * (0.5 * dx * dx * sec2 * ic1);
-    const double j12 = tl * (dx * (s0 + s1) * ic0 * ic1 / cs);
+    const double j12 = tl * (dx * (s0 + s1) * ic0 * ic1 * ics);
     const double j13 = ds;
     const double j14 = tl * P.a * (chord * (q * A + Ap * (0.5 * chord) * (1.0 + kap * q)));
     const double j24 = P.a * dx;
