@@ -612,15 +612,55 @@ __global__ void __launch_bounds__(1024) k_clean(Batch B, DevParams P, int64_t g0
 // ------------------------------------------------------------------------------------
 // Stage 4, starts.  A start's rank is its position among the chain bottoms in
 // (row, in-row index) order, from the row's scanned base.  The starts are also listed in
-// (row, sorted position) order, the order in which they are processed.
+// (row, sorted position) order, the order in which they are processed.  The start flags
+// and the row-local ranks are kept in LDS by sorted position, so the links are read once,
+// coalesced (rows beyond kStartsLdsRow clusters take the same steps in global memory).
 // ------------------------------------------------------------------------------------
+constexpr int kStartsLdsRow = 16384;   // rows up to this size rank their starts in LDS
+
 __global__ void __launch_bounds__(1024) k_starts(Batch B, DevParams P, int64_t g0, int64_t g1)
 {
     __shared__ int lds[17];
+    __shared__ uint8_t flag[kStartsLdsRow];     // start flag by sorted position
+    __shared__ uint16_t rnk[kStartsLdsRow];     // row-local rank by sorted position
     for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
         const int64_t sb = B.row_sbase[g];
+        const bool in_lds = n <= kStartsLdsRow;
+        if (in_lds) {
+            // flags in sorted order (coalesced), ranks in input order through iperm
+            for (int k = threadIdx.x; k < n; k += blockDim.x)
+                flag[k] = B.cupk[base + k] >= 0 && B.cdnk[base + k] < 0;
+            __syncthreads();
+            int run = 0;
+            for (int h0 = 0; h0 < n; h0 += blockDim.x) {
+                const int h = h0 + threadIdx.x;
+                const int k = (h < n) ? (int)B.iperm[base + h] : 0;
+                const int f = (h < n) && flag[k];
+                int total;
+                const int pos = block_excl_scan(f, &total, lds);
+                if (f) rnk[k] = (uint16_t)(run + pos);
+                run += total;
+            }
+            __syncthreads();
+            int64_t out = sb;
+            for (int k0 = 0; k0 < n; k0 += blockDim.x) {
+                const int k = k0 + threadIdx.x;
+                const int f = (k < n) && flag[k];
+                int total;
+                const int pos = block_excl_scan(f, &total, lds);
+                if (f) {
+                    const int64_t p = out + pos;
+                    B.st_row[p] = (int32_t)g;
+                    B.st_k[p] = k;
+                    B.st_rank[p] = (int32_t)(sb + rnk[k]);
+                }
+                out += total;
+            }
+            __syncthreads();
+            continue;
+        }
         int64_t run = sb;
         for (int h0 = 0; h0 < n; h0 += blockDim.x) {
             const int h = h0 + threadIdx.x;
