@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TPC clusters tracked/sec on 1 MI355X (batched vs plain) + p99 time-frame latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6      # MI355X binary64 vector peak (TFLOP/s)
 
 
 def log(msg):
@@ -76,9 +77,29 @@ def counts_from(trk, frame, res, nr):
     nb = d["row_nb"].astype(np.int64)
     tl = d["tl_nhits"].astype(np.int64)
     linked = int(((d["cup"] >= 0) | (d["cdn"] >= 0)).sum())
+    w = [int(v) for v in d["work"]]
     return dict(N=frame.n_clusters, R=int(nb.shape[0]), B=int((nb[:, 0] * nb[:, 1] + 1).sum()), C=linked,
                 S=int(d["n_starts"]), K=int((tl > 0).sum()), Ht=int(tl.sum()), Hc=int(tl[tl >= 20].sum()),
-                F=int(res["n_tracks"]), Ha=int(res["n_hits"]), T=int(res["n_tracks"]), nr=nr)
+                F=int(res["n_tracks"]), Ha=int(res["n_hits"]), T=int(res["n_tracks"]), nr=nr,
+                work=dict(tl_propagations=w[0], tl_updates=w[1], tl_window_clusters=w[2],
+                          fit_propagations=w[3], fit_updates=w[4], fit_chi2=w[5]))
+
+
+# binary64 floating-point operations of one step, counted from the formulas (an FMA is
+# two, a division or square root one): helix propagation with its Jacobian and the
+# covariance transport J C J^T; Kalman update with the 2x2 gain; chi2 of a cluster
+# inside a follow window; chi2 of a cluster in the final fit
+FLOPS_PROPAGATE, FLOPS_UPDATE, FLOPS_WINDOW, FLOPS_CHI2 = 182, 121, 12, 17
+
+
+def stage_flops(c):
+    """Algorithmic binary64 operations of the Kalman stages, from the step counts of the
+    call (the same counts the oracle takes for this input)."""
+    w = c["work"]
+    return {"tracklets": FLOPS_PROPAGATE * w["tl_propagations"] + FLOPS_UPDATE * w["tl_updates"]
+            + FLOPS_WINDOW * w["tl_window_clusters"],
+            "fit": FLOPS_PROPAGATE * w["fit_propagations"] + FLOPS_UPDATE * w["fit_updates"]
+            + FLOPS_CHI2 * w["fit_chi2"]}
 
 
 def profiled_traffic(kernel):
@@ -345,9 +366,24 @@ def main():
     res = out.result(N)
     cnt = counts_from(trk, frame, res, 152)
     sb = stage_bytes(cnt)
+    sf = stage_flops(cnt)
     dom = max((k for k in stages if k != "reset"), key=lambda k: stages[k])
-    achieved = sb[dom] / (stages[dom] * 1e-3) / 1e9
+    hbm_gbs = sb[dom] / (stages[dom] * 1e-3) / 1e9
     path_bytes = sum(sb.values())
+    if dom in sf:
+        # a Kalman stage: bound by binary64 vector arithmetic
+        achieved = sf[dom] / (stages[dom] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                    "frac": achieved / FP64_PEAK_TFS, "traffic": profiled_traffic(dom),
+                    "algorithmic_flops_per_launch": sf[dom], "launch_ms": stages[dom],
+                    "hbm": {"algorithmic_bytes_per_launch": sb[dom], "achieved_GBs": hbm_gbs,
+                            "frac": hbm_gbs / HBM_PEAK_GBS}}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(dom),
+                    "algorithmic_bytes_per_launch": sb[dom], "launch_ms": stages[dom]}
+    kalman = {k: {"TFLOPs": sf[k] / (stages[k] * 1e-3) / 1e12, "frac_fp64_peak": sf[k] / (stages[k] * 1e-3) / 1e12
+                  / FP64_PEAK_TFS} for k in sf}
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
 
     line = {
@@ -371,9 +407,8 @@ def main():
                        "max": float(lat.max())},
         "stages_ms": stages,
         "counts": cnt,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(dom),
-                     "algorithmic_bytes_per_launch": sb[dom], "launch_ms": stages[dom]},
+        "roofline": roofline,
+        "kalman_stages": kalman,
         "path_hbm": {"bytes_per_cluster": path_bytes / N,
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
                      "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

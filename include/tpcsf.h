@@ -180,13 +180,18 @@ tpcsf_status tpcsf_sync(tpcsf_ctx* ctx, void* stream);
  *   up, dn, cup, cdn             raw and cleaned links, in-row index or -1 (int32)
  *   n_starts                     number of chain bottoms (device scalar, int64)
  *   start_row, start_idx         global row and in-row index of each start, rank order
- *   tl_nhits                     clusters of the tracklet of each start (0 = none) (int32) */
+ *   tl_nhits                     clusters of the tracklet of each start (0 = none) (int32)
+ *   work[6]                      algorithmic work of the call (int64): tracklet Kalman
+ *                                propagations (attempts), updates, clusters inside the
+ *                                follow windows; final-fit propagations, updates, chi2
+ *                                evaluations */
 typedef struct {
     const float* row_lo; const float* row_bin; const int32_t* row_nb;
     const uint32_t* bin_start; const uint32_t* perm;
     const int32_t* up; const int32_t* dn; const int32_t* cup; const int32_t* cdn;
     const int64_t* n_starts; const int32_t* start_row; const int32_t* start_idx;
     const int32_t* tl_nhits;
+    const int64_t* work;
 } tpcsf_debug_view;
 tpcsf_status tpcsf_debug(tpcsf_ctx* ctx, tpcsf_debug_view* view);
 

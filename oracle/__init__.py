@@ -57,7 +57,7 @@ class _Debug(C.Structure):
         ("start", C.c_void_p),
         ("cap_tracklets", C.c_int64), ("n_tracklets", C.c_int64),
         ("tl_start", C.c_void_p), ("tl_nhits", C.c_void_p), ("tl_hits", C.c_void_p),
-        ("W", C.c_void_p),
+        ("W", C.c_void_p), ("work", C.c_int64 * 6),
     ]
 
 
@@ -171,6 +171,7 @@ class Oracle:
                 d["tl_hits"] = d["tl_hits"][:K]
             for k in ("perm", "up", "dn", "cup", "cdn", "start", "W"):
                 d[k] = d[k][:n]
+            d["work"] = np.array(list(dbg.work), np.int64)
             res["debug"] = d
         return res
 

@@ -424,8 +424,14 @@ double orc_update(const orc_cfg* cfg, double my, double mz, double* p, double* C
 /* Step 7: final fit of n ordered clusters.  Seed from first/middle/last, C = C0, update
  * at the first cluster and outward over the rest; then C = C0 keeping p, update at the
  * last cluster and inward to the first.  Result at the innermost cluster. */
+/* Counts one step of kind k (see orc_debug.work); no effect on any result. */
+static void count(int64_t* work, int k)
+{
+    if (work) ++work[k];
+}
+
 static int kfit(const orc_cfg* cfg, int32_t n, const orc_real* x, const orc_real* y,
-                const orc_real* z, kstate* st, orc_real* chi2, orc_real* p_outer)
+                const orc_real* z, kstate* st, orc_real* chi2, orc_real* p_outer, int64_t* work)
 {
     if (n < 3) return -1;
     orc_real sx[3] = {x[0], x[(n - 1) / 2], x[n - 1]};
@@ -434,17 +440,25 @@ static int kfit(const orc_cfg* cfg, int32_t n, const orc_real* x, const orc_real
     if (kseed(cfg, sx, sy, sz, st->p) != 0) return -1;
     st->x = x[0];
     kreset(cfg, st);
+    count(work, 4);
     kupdate(cfg, st, y[0], z[0]);
     for (int32_t i = 1; i < n; ++i) {
+        count(work, 3);
         if (kprop(cfg, st, x[i], NULL) != 0) return -1;
+        count(work, 4);
         kupdate(cfg, st, y[i], z[i]);
     }
     if (p_outer)
         for (int i = 0; i < 5; ++i) p_outer[i] = st->p[i];
     kreset(cfg, st);
+    count(work, 4);
+    count(work, 5);
     orc_real c2 = kupdate(cfg, st, y[n - 1], z[n - 1]);
     for (int32_t i = n - 2; i >= 0; --i) {
+        count(work, 3);
         if (kprop(cfg, st, x[i], NULL) != 0) return -1;
+        count(work, 4);
+        count(work, 5);
         c2 += kupdate(cfg, st, y[i], z[i]);
     }
     *chi2 = c2;
@@ -464,7 +478,7 @@ int orc_fit_hits(const orc_cfg* cfg, int32_t n, const double* x, const double* y
     for (int32_t i = 0; i < n; ++i) { xr[i] = (orc_real)x[i]; yr[i] = (orc_real)y[i]; zr[i] = (orc_real)z[i]; }
     kstate st;
     orc_real c2 = 0, po[5];
-    int rc = kfit(cfg, n, xr, yr, zr, &st, &c2, po);
+    int rc = kfit(cfg, n, xr, yr, zr, &st, &c2, po, NULL);
     free(xr);
     if (rc != 0) return -1;
     for (int i = 0; i < 5; ++i) p[i] = st.p[i];
@@ -488,7 +502,9 @@ typedef struct {
     const int64_t* row_off;          /* [n_rows+1] of this sector (absolute)          */
     const int32_t* sidx;             /* per-row y-sorted in-row indices (sector-relative) */
     int64_t base;
+    int64_t* work;                   /* step counters (orc_debug.work) or NULL        */
 } sector_view;
+
 
 static int32_t search_row(const sector_view* sv, int r, const kstate* st, orc_real* chi2_out)
 {
@@ -515,6 +531,7 @@ static int32_t search_row(const sector_view* sv, int r, const kstate* st, orc_re
         orc_real yc = (orc_real)sv->y[o + c], zc = (orc_real)sv->z[o + c];
         if (yc - yp > wy) break;
         if (R_FABS(zc - zp) > wz) continue;
+        count(sv->work, 2);
         orc_real c2 = kchi2(cfg, st, yc, zc);
         if (best < 0 || c2 < bchi || (c2 == bchi && c < best)) { best = c; bchi = c2; }
     }
@@ -527,10 +544,12 @@ static int follow(const sector_view* sv, kstate* st, int r_from, int r_to, int s
     const orc_cfg* cfg = sv->cfg;
     int misses = 0;
     for (int r = r_from; r != r_to; r += step) {
+        count(sv->work, 0);
         if (kprop(cfg, st, (orc_real)cfg->row_x[r], NULL) != 0) break;
         orc_real c2;
         int32_t c = search_row(sv, r, st, &c2);
         if (c >= 0 && c2 <= (orc_real)cfg->chi2_max) {
+            count(sv->work, 1);
             kupdate(cfg, st, (orc_real)sv->y[sv->row_off[r] + c], (orc_real)sv->z[sv->row_off[r] + c]);
             hits[r] = c;
             misses = 0;
@@ -575,7 +594,11 @@ static int32_t build_tracklet(const sector_view* sv, const int32_t* cup, int r0,
     kreset(cfg, &st);
     for (int r = r0; r < r0 + L; ++r) {
         int64_t g = sv->row_off[r] + hits[r];
-        if (r > r0 && kprop(cfg, &st, (orc_real)cfg->row_x[r], NULL) != 0) goto fail;
+        if (r > r0) {
+            count(sv->work, 0);
+            if (kprop(cfg, &st, (orc_real)cfg->row_x[r], NULL) != 0) goto fail;
+        }
+        count(sv->work, 1);
         kupdate(cfg, &st, (orc_real)sv->y[g], (orc_real)sv->z[g]);
     }
     /* follow outward */
@@ -586,7 +609,9 @@ static int32_t build_tracklet(const sector_view* sv, const int32_t* cup, int r0,
     for (int r = nr - 1; r >= r0; --r) {
         if (hits[r] < 0) continue;
         int64_t g = sv->row_off[r] + hits[r];
+        count(sv->work, 0);
         if (kprop(cfg, &st, (orc_real)cfg->row_x[r], NULL) != 0) goto fail;
+        count(sv->work, 1);
         kupdate(cfg, &st, (orc_real)sv->y[g], (orc_real)sv->z[g]);
     }
     /* follow inward */
@@ -623,6 +648,8 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
         if (row_off[g + 1] < row_off[g]) return -1;
     int rc = 0;
     int64_t n_tracks = 0, n_hits = 0, n_tl = 0, bin_used = 0;
+    if (dbg)
+        for (int k = 0; k < 6; ++k) dbg->work[k] = 0;
     if (out->cluster_track)
         for (int64_t i = 0; i < n; ++i) out->cluster_track[i] = -1;
     if (out->hit_off && out->cap_tracks >= 0) out->hit_off[0] = 0;
@@ -669,7 +696,7 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
         }
         for (int r = 0; r < nr; ++r)
             sort_row_by_y(y + ro[r], ro[r + 1] - ro[r], sidx + (ro[r] - base));
-        sector_view sv = {cfg, y, z, ro, sidx, base};
+        sector_view sv = {cfg, y, z, ro, sidx, base, dbg ? dbg->work : NULL};
 
         /* Step 4/5: start hits in (row, in-row index) order, one tracklet each */
         int64_t n_start = 0;
@@ -748,7 +775,7 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
             if (m < cfg->min_track_hits) continue;
             kstate st;
             orc_real c2;
-            if (kfit(cfg, m, fx, fy, fz, &st, &c2, NULL) != 0) continue;
+            if (kfit(cfg, m, fx, fy, fz, &st, &c2, NULL, dbg ? dbg->work : NULL) != 0) continue;
             if (n_tracks < out->cap_tracks && n_hits + m <= out->cap_hits) {
                 for (int i = 0; i < 5; ++i) out->params[n_tracks * 5 + i] = st.p[i];
                 for (int i = 0; i < 15; ++i) out->cov[n_tracks * 15 + i] = st.C[i];

@@ -81,6 +81,10 @@ typedef struct {               /* optional intermediate results; NULL = skip    
     int32_t* tl_nhits;         /* [cap] 0 = no tracklet                          */
     int32_t* tl_hits;          /* [cap][n_rows] in-row index per row, -1 none    */
     uint64_t* W;               /* [N] selection weight per cluster               */
+    /* step counts (written): tracklet propagations (attempts), tracklet updates,
+     * clusters inside the follow windows, final-fit propagations, final-fit updates,
+     * final-fit chi2 evaluations.  Counting changes no result. */
+    int64_t work[6];
 } orc_debug;
 
 /* Track one frame.  y, z: [n] binary32 local coordinates grouped by (sector, row);

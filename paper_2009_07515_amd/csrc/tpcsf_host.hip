@@ -586,6 +586,7 @@ tpcsf_status tpcsf_debug(tpcsf_ctx* c, tpcsf_debug_view* v)
     v->start_row = B.d_start_row;
     v->start_idx = B.d_start_idx;
     v->tl_nhits = B.d_tl_n;
+    v->work = c->d_ctr->work;
     return TPCSF_OK;
 }
 

@@ -41,6 +41,9 @@ struct Counters {
     int32_t fit_queue[8];           // fit work queue: head of each XCD's segment
     int32_t err;                    // error bits
     unsigned long long hash;        // output digest (autotuner's result-invariance check)
+    // algorithmic work of the call: tracklet propagations, updates, window candidates;
+    // final-fit propagations, updates, chi2 evaluations
+    int64_t work[6];
 };
 
 // Device pointers of one batch: inputs, arena and outputs.

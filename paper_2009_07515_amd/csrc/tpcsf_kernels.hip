@@ -152,6 +152,7 @@ __global__ void k_reset(Batch B)
         c->hit_base = 0;
         c->n_fit = 0;
         c->n_order = 0;
+        for (int w = 0; w < 6; ++w) c->work[w] = 0;
         for (int x = 0; x < kXcds; ++x) {
             c->queue[x] = 0;
             c->fit_queue[x] = 0;
@@ -1006,9 +1007,10 @@ __device__ bool trk_seed(Trk& t, const double* x, const double* y, const double*
 }
 
 // Least-chi2 cluster of row g (row record rf, ri) inside the follow window: its sorted
-// position (-1 if none) and coordinates.  Equal chi2: the smaller in-row index.
+// position (-1 if none) and coordinates.  Equal chi2: the smaller in-row index.  n_win
+// counts the clusters inside the window.
 __device__ int search_row(const Batch& B, const DevParams& P, const float4 rf, const int4 ri, int64_t g, const Trk& t,
-                          double& best_chi2, float2& best_c)
+                          double& best_chi2, float2& best_c, int& n_win)
 {
     RowView v;
     v.first = ri.x;
@@ -1047,6 +1049,7 @@ __device__ int search_row(const Batch& B, const DevParams& P, const float4 rf, c
             const double dy = (double)c2[j].x - yp;
             const double dz = (double)c2[j].y - zp;
             if (!(fabs(dy) <= wy) || !(fabs(dz) <= wz)) continue;
+            ++n_win;
             const int k = (int)(q + j);
             const double chi2 = (dy * dy * s11 - 2.0 * dy * dz * s01 + dz * dz * s00) * idet;
             bool take = best < 0 || chi2 < best_chi2;
@@ -1191,6 +1194,13 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
+// Adds a per-lane count, summed over the wave, to a device counter (one atomic per wave).
+__device__ __forceinline__ void wave_count(int64_t* ctr, int v)
+{
+    const int t = wave_sum(v);
+    if (lane_id() == 0 && t != 0) atomicAdd((unsigned long long*)ctr, (unsigned long long)t);
+}
+
 constexpr int kRowBatch = 8;   // rows per pass of the claim, keep and emit sweeps
 
 enum : int { kWait = 0, kFit = 1, kOut = 2, kUpDone = 3, kRefit = 4, kIn = 5, kDone = 6 };
@@ -1207,6 +1217,7 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
         const int L = p >= 0 ? B.tl_len[p] : 0;
         const bool live = L >= P.min_chain;
         int r0 = 0, rend = 0, rlo = 0, rhi = 0, n = 0, misses = 0, phase = kDone;
+        int nprop = 0, nupd = 0, nwin = 0;   // algorithmic work of this lane
         int64_t gs = 0;
         Trk tr;
         if (live) {
@@ -1236,7 +1247,10 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
             if (phase == kWait && r == r0) phase = kFit;
             const bool act = phase == kFit || phase == kOut;
             bool moved = true;
-            if (act && !(phase == kFit && r == r0)) moved = trk_propagate(tr, (double)P.rx[r], P);
+            if (act && !(phase == kFit && r == r0)) {
+                moved = trk_propagate(tr, (double)P.rx[r], P);
+                ++nprop;
+            }
             int k = -1;
             float2 c = make_float2(0.0f, 0.0f);
             if (act && moved) {
@@ -1245,11 +1259,14 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
                     c = B.yz[B.off[gs + r] + k];
                 } else {
                     double chi2;
-                    k = search_row(B, P, B.row_f[gs + r], B.row_i[gs + r], gs + r, tr, chi2, c);
+                    k = search_row(B, P, B.row_f[gs + r], B.row_i[gs + r], gs + r, tr, chi2, c, nwin);
                     if (k >= 0 && !(chi2 <= P.chi2_max)) k = -1;
                 }
             }
-            if (k >= 0) trk_update(tr, (double)c.x, (double)c.y, P);
+            if (k >= 0) {
+                trk_update(tr, (double)c.x, (double)c.y, P);
+                ++nupd;
+            }
             if (phase == kFit) {
                 if (!moved) {
                     phase = kDone;
@@ -1289,17 +1306,23 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
                 act = true;
             }
             bool moved = true;
-            if (act) moved = trk_propagate(tr, (double)P.rx[r], P);
+            if (act) {
+                moved = trk_propagate(tr, (double)P.rx[r], P);
+                ++nprop;
+            }
             float2 c = make_float2(0.0f, 0.0f);
             if (act && moved) {
                 if (phase == kRefit) {
                     c = B.yz[B.off[gs + r] + k];
                 } else {
                     double chi2;
-                    k = search_row(B, P, B.row_f[gs + r], B.row_i[gs + r], gs + r, tr, chi2, c);
+                    k = search_row(B, P, B.row_f[gs + r], B.row_i[gs + r], gs + r, tr, chi2, c, nwin);
                     if (k >= 0 && !(chi2 <= P.chi2_max)) k = -1;
                 }
-                if (k >= 0) trk_update(tr, (double)c.x, (double)c.y, P);
+                if (k >= 0) {
+                    trk_update(tr, (double)c.x, (double)c.y, P);
+                    ++nupd;
+                }
             }
             if (phase == kRefit && r <= rhi) {
                 if (act && !moved) {
@@ -1332,6 +1355,9 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
             B.tl_rlo[p] = (int16_t)rlo;
             B.tl_rhi[p] = (int16_t)rhi;
         }
+        wave_count(&B.ctr->work[0], nprop);
+        wave_count(&B.ctr->work[1], nupd);
+        wave_count(&B.ctr->work[2], nwin);
         // claim, kRowBatch rows per pass: the loads of all of them are issued before
         // their atomics
         const bool claim = live && n >= P.min_track_hits;
@@ -1535,31 +1561,44 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
             ok = trk_seed(tr, sx, sy, sz, P);
             if (ok) trk_reset_cov(tr, P);
         }
+        int nprop = 0, nupd = 0, nchi = 0;   // algorithmic work of this lane
         // outward over the kept rows
         const int ra = wave_min_i(ok ? rfirst : nr), rb = wave_max_i(ok ? rlast : -1);
         for (int r = ra; r <= rb; ++r) {
             if (!(ok && row_set(m0, m1, m2, m3, r))) continue;
-            if (r > rfirst && !trk_propagate(tr, (double)P.rx[r], P)) {
-                ok = false;
-                continue;
+            if (r > rfirst) {
+                ++nprop;
+                if (!trk_propagate(tr, (double)P.rx[r], P)) {
+                    ok = false;
+                    continue;
+                }
             }
             const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
             trk_update(tr, (double)c.x, (double)c.y, P);
+            ++nupd;
         }
         if (ok) trk_reset_cov(tr, P);
         // inward from the last kept row, summing chi2 before each update
         double chi2 = 0.0;
         for (int r = rb; r >= ra; --r) {
             if (!(ok && row_set(m0, m1, m2, m3, r))) continue;
-            if (r < rlast && !trk_propagate(tr, (double)P.rx[r], P)) {
-                ok = false;
-                continue;
+            if (r < rlast) {
+                ++nprop;
+                if (!trk_propagate(tr, (double)P.rx[r], P)) {
+                    ok = false;
+                    continue;
+                }
             }
             const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
             const double my = (double)c.x, mz = (double)c.y;
             chi2 += trk_chi2(tr, my, mz, P);
             trk_update(tr, my, mz, P);
+            ++nupd;
+            ++nchi;
         }
+        wave_count(&B.ctr->work[3], nprop);
+        wave_count(&B.ctr->work[4], nupd);
+        wave_count(&B.ctr->work[5], nchi);
         if (ok) {
             for (int q = 0; q < 5; ++q) ok = ok && isfinite(tr.p[q]);
             for (int q = 0; q < 15; ++q) ok = ok && isfinite(tr.c[q]);

@@ -74,7 +74,8 @@ class HostTracks(C.Structure):
 
 class DebugView(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("row_lo", "row_bin", "row_nb", "bin_start", "perm", "up", "dn",
-                                           "cup", "cdn", "n_starts", "start_row", "start_idx", "tl_nhits")]
+                                           "cup", "cdn", "n_starts", "start_row", "start_idx", "tl_nhits",
+                                           "work")]
 
 
 _lib = None
@@ -376,7 +377,7 @@ class Tracker:
                    perm=dev(v.perm, n, np.uint32), up=dev(v.up, n, np.int32), dn=dev(v.dn, n, np.int32),
                    cup=dev(v.cup, n, np.int32), cdn=dev(v.cdn, n, np.int32), n_starts=ns,
                    start_row=dev(v.start_row, ns, np.int32), start_idx=dev(v.start_idx, ns, np.int32),
-                   tl_nhits=dev(v.tl_nhits, ns, np.int32))
+                   tl_nhits=dev(v.tl_nhits, ns, np.int32), work=dev(v.work, 6, np.int64))
         t = self.tuning
         nb_total = int(t.cap_mul) * n + (int(t.cap_add) + 1) * R
         res["bin_start"] = dev(v.bin_start, nb_total, np.uint32)

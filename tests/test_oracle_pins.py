@@ -233,6 +233,27 @@ def test_noise_free_helices_recover_truth(row_x, bz):
 
 
 # --------------------------------------------------------------------------------------
+# Step counts of the method on one straight track through all rows (B = 0).  Rows 0 and
+# 151 carry no links, so the chain covers rows 1..150: 149 propagations and 150 updates.
+# The outward follow takes row 151 (1 propagation, 1 cluster in the window, 1 update),
+# the refit covers rows 151..1 and starts with a propagation to its own outermost row
+# (151 propagations and updates), the inward follow takes row 0 (1, 1, 1).  The final fit
+# takes 151 propagations and 152 updates per pass and evaluates chi2 on the inward pass.
+# --------------------------------------------------------------------------------------
+def test_step_counts_of_one_straight_track(row_x):
+    o = _orc(row_x, bz=0.0)
+    x = np.asarray(row_x, np.float64)
+    y = (1.0 + 0.05 * x).astype(np.float32)
+    z = (-3.0 + 0.2 * x).astype(np.float32)
+    counts = np.zeros(36 * 152, np.int64)
+    counts[:152] = 1
+    ro = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    r = o.track_frame(y, z, ro, debug=True)
+    assert r["n_tracks"] == 1 and r["nhits"][0] == 152
+    assert list(r["debug"]["work"]) == [149 + 1 + 151 + 1, 150 + 1 + 151 + 1, 2, 151 + 151, 152 + 152, 152]
+
+
+# --------------------------------------------------------------------------------------
 # Final fit vs nonlinear least squares: the inward pass starts at the outermost cluster
 # from the outward estimate with covariance C0, so it estimates the minimiser of
 #   sum_i |m_i - h_i(q)|^2 / sigma^2 + (q - p_outer)^T C0^-1 (q - p_outer)
