@@ -92,6 +92,9 @@ struct Batch {
     // keep and final fit: candidates listed densely
     int32_t* keep_n;                // [cap_starts] (p indexed) kept clusters, 0 = not a candidate
     int64_t* fit_pos;               // [cap_starts] (p indexed) candidate slot (scan of keep_n)
+    int64_t* cand_off;              // [cap_starts] (p indexed) first entry of the kept list
+    float4* kept_list;              // [N] kept clusters of the candidates, slot order, inner to
+                                    //     outer: y, z, row plane x, input index (as bits)
     uint64_t* keep_mask;            // [cap_starts][4] (p indexed) kept rows
     int32_t* fit_list;              // [cap_fit] p of every candidate, in p order
     double* f_par;                  // [cap_fit][5]

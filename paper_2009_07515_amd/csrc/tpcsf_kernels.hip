@@ -442,7 +442,7 @@ __device__ __forceinline__ void first_range(const RowView& V, int iy0, int iy1, 
     }
 }
 
-constexpr int kSlots = 4;
+constexpr int kSlots = 6;
 
 struct LinkBest {
     float D;
@@ -1461,8 +1461,8 @@ __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
 // Result at the innermost kept cluster; a failed fit drops the track.  Results are
 // stored at the candidate's list slot.
 //
-// Row-synchronous like the tracklet stage: a wave takes 64 consecutive candidates and
-// sweeps their kept rows outward, then inward, all lanes on the same row at each pass.
+// The kept clusters are first gathered into one contiguous list per candidate; the fit then
+// streams each lane's own list, the candidates of a block ordered by kept count.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t mask_word(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3, int w)
 {
@@ -1520,77 +1520,147 @@ __device__ __forceinline__ bool row_set(uint64_t m0, uint64_t m1, uint64_t m2, u
     return (mask_word(m0, m1, m2, m3, r >> 6) >> (r & 63)) & 1ull;
 }
 
-__global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
+// The kept clusters of every candidate, gathered into one list in slot order (inner to
+// outer), at offsets from the scan of the kept counts.  A wave takes 64 consecutive
+// candidates and sweeps their kept rows together (row-major hit table).
+__global__ void __launch_bounds__(256) k_gather(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
-    int64_t q_next = 0, q_end = 0;
-    int q_seg = (int)blockIdx.x % xcd_parts(), q_tried = 0;
-    for (;;) {
-        const int64_t i = take_item(B.ctr->fit_queue, 0, B.ctr->n_fit, ~0ull, q_next, q_end, q_seg, q_tried);
-        if (__ballot(i >= 0) == 0ull) break;
-        const bool live = i >= 0;
-        int64_t p = 0, gs = 0;
+    const int lane = lane_id();
+    int64_t first, end, stride;
+    xcd_span(0, B.ctr->n_fit, first, end, stride);
+    for (int64_t i0 = first - lane; i0 < end; i0 += stride) {
+        const int64_t i = i0 + lane;
+        const bool on = i < end;
+        int64_t p = 0, gs = 0, j = 0;
         uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-        int rfirst = nr, rlast = -1, kept = 0;
+        int rlo = nr, rhi = -1;
+        if (on) {
+            p = B.fit_list[i];
+            const int64_t g = B.st_row[p];
+            gs = g - g % nr;
+            j = B.cand_off[p];
+            m0 = B.keep_mask[p * 4 + 0]; m1 = B.keep_mask[p * 4 + 1];
+            m2 = B.keep_mask[p * 4 + 2]; m3 = B.keep_mask[p * 4 + 3];
+            rlo = B.tl_rlo[p];
+            rhi = B.tl_rhi[p];
+        }
+        const int rb = wave_max_i(rhi);
+        for (int r = wave_min_i(rlo); r <= rb; r += kRowBatch) {
+            uint32_t kk[kRowBatch];
+            int64_t ff[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int rr = r + u;
+                const bool set = on && rr <= rhi && row_set(m0, m1, m2, m3, rr);
+                kk[u] = set ? *hit_slot(B, rr, p) : 0xFFFFFFFFu;
+                ff[u] = set ? B.off[gs + rr] : 0;
+            }
+            float2 cc[kRowBatch];
+            uint32_t oo[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                cc[u] = kk[u] != 0xFFFFFFFFu ? B.yz[ff[u] + kk[u]] : make_float2(0.0f, 0.0f);
+                oo[u] = kk[u] != 0xFFFFFFFFu ? B.perm[ff[u] + kk[u]] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u)
+                if (kk[u] != 0xFFFFFFFFu)
+                    B.kept_list[j++] = make_float4(cc[u].x, cc[u].y, P.rx[r + u],
+                                                   __int_as_float((int)(ff[u] + oo[u])));
+        }
+    }
+}
+
+// Block-wide bitonic sort of 256 keys in LDS, descending.
+__device__ void bitonic_desc_256(uint32_t* key)
+{
+    const int t = threadIdx.x;
+    for (int k = 2; k <= 256; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int o = t ^ j;
+            if (o > t) {
+                const uint32_t a = key[t], b = key[o];
+                const bool desc = (t & k) == 0;
+                if (desc ? (a < b) : (a > b)) {
+                    key[t] = b;
+                    key[o] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Each block takes 256 consecutive candidates and orders them by kept count, so that the
+// lanes of a wave run passes of similar length over their own contiguous kept lists.
+__global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
+{
+    __shared__ uint32_t key[256];
+    const int t = threadIdx.x;
+    const int64_t nfit = B.ctr->n_fit;
+    const int parts = xcd_parts(), x = (int)blockIdx.x % parts, bj = (int)blockIdx.x / parts;
+    const int nbx = ((int)gridDim.x - x + parts - 1) / parts;
+    int64_t s0, s1;
+    segment(0, (nfit + 255) / 256, x, parts, s0, s1);   // chunks of 256 candidates
+    for (int64_t ch = s0 + bj; ch < s1; ch += nbx) {
+        const int64_t i_own = ch * 256 + t;
+        const int kept_own = i_own < nfit ? B.keep_n[B.fit_list[i_own]] : 0;
+        key[t] = ((uint32_t)kept_own << 8) | (uint32_t)t;
+        __syncthreads();
+        bitonic_desc_256(key);
+        const int64_t i = ch * 256 + (key[t] & 0xFFu);
+        __syncthreads();
+        const bool live = i < nfit;
+        int64_t p = 0, base = 0;
+        int kept = 0;
         bool ok = false;
         Trk tr;
         if (live) {
             p = B.fit_list[i];
             kept = B.keep_n[p];
-            const int64_t g = B.st_row[p];
-            gs = g - g % nr;
-            m0 = B.keep_mask[p * 4 + 0]; m1 = B.keep_mask[p * 4 + 1];
-            m2 = B.keep_mask[p * 4 + 2]; m3 = B.keep_mask[p * 4 + 3];
-            rfirst = row_at_or_above(m0, m1, m2, m3, 0);
-            rlast = row_at_or_below(m0, m1, m2, m3, kMaxRows - 1);
-            int want = (kept - 1) / 2, rmid = rfirst;
-            for (int w = 0; w < 4; ++w) {
-                const uint64_t x = mask_word(m0, m1, m2, m3, w);
-                const int c = __popcll(x);
-                if (want < c) { rmid = (w << 6) + nth_set_bit(x, want); break; }
-                want -= c;
-            }
-            const int rs[3] = {rfirst, rmid, rlast};
+            base = B.cand_off[p];
+            const float4 e[3] = {B.kept_list[base], B.kept_list[base + (kept - 1) / 2],
+                                 B.kept_list[base + kept - 1]};
             double sx[3], sy[3], sz[3];
             for (int q = 0; q < 3; ++q) {
-                const float2 c = B.yz[B.off[gs + rs[q]] + *hit_slot(B, rs[q], p)];
-                sx[q] = (double)P.rx[rs[q]];
-                sy[q] = (double)c.x;
-                sz[q] = (double)c.y;
+                sx[q] = (double)e[q].z;
+                sy[q] = (double)e[q].x;
+                sz[q] = (double)e[q].y;
             }
             ok = trk_seed(tr, sx, sy, sz, P);
             if (ok) trk_reset_cov(tr, P);
         }
         int nprop = 0, nupd = 0, nchi = 0;   // algorithmic work of this lane
-        // outward over the kept rows
-        const int ra = wave_min_i(ok ? rfirst : nr), rb = wave_max_i(ok ? rlast : -1);
-        for (int r = ra; r <= rb; ++r) {
-            if (!(ok && row_set(m0, m1, m2, m3, r))) continue;
-            if (r > rfirst) {
+        const int kw = wave_max_i(ok ? kept : 0);
+        // outward over the kept clusters
+        for (int j = 0; j < kw; ++j) {
+            if (!(ok && j < kept)) continue;
+            const float4 e = B.kept_list[base + j];
+            if (j > 0) {
                 ++nprop;
-                if (!trk_propagate(tr, (double)P.rx[r], P)) {
+                if (!trk_propagate(tr, (double)e.z, P)) {
                     ok = false;
                     continue;
                 }
             }
-            const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
-            trk_update(tr, (double)c.x, (double)c.y, P);
+            trk_update(tr, (double)e.x, (double)e.y, P);
             ++nupd;
         }
         if (ok) trk_reset_cov(tr, P);
-        // inward from the last kept row, summing chi2 before each update
+        // inward from the last kept cluster, summing chi2 before each update
         double chi2 = 0.0;
-        for (int r = rb; r >= ra; --r) {
-            if (!(ok && row_set(m0, m1, m2, m3, r))) continue;
-            if (r < rlast) {
+        for (int j = kw - 1; j >= 0; --j) {
+            if (!(ok && j < kept)) continue;
+            const float4 e = B.kept_list[base + j];
+            if (j < kept - 1) {
                 ++nprop;
-                if (!trk_propagate(tr, (double)P.rx[r], P)) {
+                if (!trk_propagate(tr, (double)e.z, P)) {
                     ok = false;
                     continue;
                 }
             }
-            const float2 c = B.yz[B.off[gs + r] + *hit_slot(B, r, p)];
-            const double my = (double)c.x, mz = (double)c.y;
+            const double my = (double)e.x, mz = (double)e.y;
             chi2 += trk_chi2(tr, my, mz, P);
             trk_update(tr, my, mz, P);
             ++nupd;
@@ -1619,7 +1689,7 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 
 // ------------------------------------------------------------------------------------
 // Stage 8, emit: tracks at their scanned positions (rank order), hits inner to outer as
-// input cluster indices.  Writes beyond the caller's capacity are
+// input cluster indices (from the kept list).  Writes beyond the caller's capacity are
 // dropped and flagged.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
@@ -1628,24 +1698,22 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
     const int lane = lane_id();
     int64_t first, end, stride;
     xcd_span(0, B.ctr->n_fit, first, end, stride);
-    // wave-uniform loop over 64 consecutive candidates; their hit lists are written row
-    // by row with all lanes on the same row
+    // wave-uniform loop over 64 candidates: records per lane, then each written track's
+    // hit list copied by the whole wave (64 consecutive entries per pass)
     for (int64_t i0 = first - lane; i0 < end; i0 += stride) {
         const int64_t i = i0 + lane;
         bool on = i < end;
-        int64_t p = 0, gs = 0, j = 0;
-        uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-        int rlo = nr, rhi = -1;
+        int64_t hp = 0, src = 0;
+        int nk = 0;
         if (on) {
-            p = B.fit_list[i];
+            const int64_t p = B.fit_list[i];
             const int64_t rank = B.st_rank[p];
             on = B.trk_flag[rank] != 0;
             if (on) {
                 const int64_t T = B.trk_idx[rank];
-                const int64_t hp = B.hit_pos[rank];
-                const int nk = B.hit_cnt[rank];
+                hp = B.hit_pos[rank];
+                nk = B.hit_cnt[rank];
                 const int64_t g = B.st_row[p];
-                gs = g - g % nr;
                 if (T >= B.cap_tracks || hp + nk > B.cap_hits) {
                     atomicOr(&B.ctr->err, kErrOutCap);
                     on = false;
@@ -1660,30 +1728,17 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
                     B.o_tf[T] = (int32_t)(g / ((int64_t)nr * P.n_sectors));
                     B.o_hit_off[T + 1] = hp + nk;
                     B.trk_out[rank] = (int32_t)T;
-                    m0 = B.keep_mask[p * 4 + 0]; m1 = B.keep_mask[p * 4 + 1];
-                    m2 = B.keep_mask[p * 4 + 2]; m3 = B.keep_mask[p * 4 + 3];
-                    rlo = B.tl_rlo[p];
-                    rhi = B.tl_rhi[p];
-                    j = hp;
+                    src = B.cand_off[p];
                 }
             }
         }
-        const int rb = wave_max_i(rhi);
-        for (int r = wave_min_i(rlo); r <= rb; r += kRowBatch) {
-            uint32_t kk[kRowBatch];
-            int64_t ff[kRowBatch];
-#pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) {
-                const int rr = r + u;
-                const bool set = on && rr <= rhi && row_set(m0, m1, m2, m3, rr);
-                kk[u] = set ? *hit_slot(B, rr, p) : 0xFFFFFFFFu;
-                ff[u] = set ? B.off[gs + rr] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) kk[u] = kk[u] != 0xFFFFFFFFu ? B.perm[ff[u] + kk[u]] : 0xFFFFFFFFu;
-#pragma unroll
-            for (int u = 0; u < kRowBatch; ++u)
-                if (kk[u] != 0xFFFFFFFFu) B.o_hit_ids[j++] = (int32_t)(ff[u] + kk[u]);
+        uint64_t todo = __ballot(on);
+        while (todo != 0ull) {
+            const int l = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1ull;
+            const int64_t d = __shfl(hp, l, 64), sj = __shfl(src, l, 64);
+            const int m = __shfl(nk, l, 64);
+            for (int q = lane; q < m; q += 64) B.o_hit_ids[d + q] = __float_as_int(B.kept_list[sj + q].w);
         }
     }
 }
@@ -1894,6 +1949,8 @@ void launch_fit_scan(const Batch& b, const DevParams& p, const LaunchCfg& c, hip
     J.lo_ptr = &b.ctr->rank_lo;
     J.hi_ptr = &b.ctr->rank_hi;
     J.totA = &b.ctr->n_fit;
+    J.b32 = b.keep_n;          // channel B: offsets of the candidates' kept lists
+    J.outB = b.cand_off;
     J.part = b.scan_part;
     run_scan(J, s);
     hipLaunchKernelGGL(k_fit_list, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
@@ -1901,6 +1958,7 @@ void launch_fit_scan(const Batch& b, const DevParams& p, const LaunchCfg& c, hip
 
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
+    hipLaunchKernelGGL(k_gather, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
     hipLaunchKernelGGL(k_fit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
