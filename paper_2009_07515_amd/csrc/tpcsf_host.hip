@@ -39,6 +39,7 @@ struct GraphKey {
     const void* arena = nullptr;
     tpcsf_tracks out{};
     tpcsf_tuning tuning{};
+    int32_t grid_lds = 0;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
@@ -47,7 +48,8 @@ struct GraphKey {
 struct tpcsf_ctx {
     int device = 0;
     int n_cu = 256;
-    int grid_lds = 0;               // dynamic LDS bytes of the grid kernel
+    int grid_lds_max = 0;           // dynamic LDS bytes the grid kernel may use on the device
+    int64_t frame_max_row = 0;      // largest row of the frame being tracked
     int32_t n_sectors = 36, n_rows = 152;
     std::vector<float> row_x;
     double bz = 0.5;
@@ -180,7 +182,13 @@ LaunchCfg launch_cfg(const tpcsf_ctx* c)
     L.tl_block = c->tuning.tl_block;
     L.chunk = c->tuning.chunk;
     L.n_cu = c->n_cu;
-    L.grid_lds = c->grid_lds;
+    // the grid kernel's LDS: bin counters (16-bit pairs) and the placement of the largest
+    // row.  Frames whose rows fit in 64 KB (two row blocks per compute unit) all use 64 KB,
+    // so that frames of different sizes keep one launch configuration (and one graph).
+    const int64_t m = c->frame_max_row;
+    const int64_t need = 4 * ((c->tuning.cap_mul * m + c->tuning.cap_add + 2) / 2 + 1) + 2 * m + 256;
+    const int64_t small = 65536 - 1024;   // the kernel's static LDS stays within the 64 KB
+    L.grid_lds = (int)(need <= small && small <= c->grid_lds_max ? small : c->grid_lds_max);
     return L;
 }
 
@@ -215,11 +223,14 @@ tpcsf_status check_frame(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks*
     const int64_t R = (int64_t)f->n_tf * c->n_sectors * c->n_rows;
     const int64_t* off = f->row_offsets_host;
     if (off[0] != 0 || off[R] != f->n_clusters) return fail(c, TPCSF_E_INVALID, "row offsets do not span the clusters");
+    int64_t max_row = 0;
     for (int64_t g = 0; g < R; ++g) {
         const int64_t d = off[g + 1] - off[g];
         if (d < 0) return fail(c, TPCSF_E_INVALID, "row offsets decrease");
         if (d >= 65535) return fail(c, TPCSF_E_INVALID, "a row holds 65535 clusters or more");
+        if (d > max_row) max_row = d;
     }
+    c->frame_max_row = max_row;
     if (o->cap_tracks < 0 || o->cap_hits < 0 || !o->n_tracks || !o->n_hits || !o->hit_off)
         return fail(c, TPCSF_E_INVALID, "output descriptor incomplete");
     if (o->cap_tracks > 0 && (!o->params || !o->cov || !o->x_ref || !o->chi2 || !o->ndf || !o->nhits ||
@@ -406,7 +417,7 @@ tpcsf_status tpcsf_create(const tpcsf_geometry* geo, const tpcsf_params* params,
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, c->device)) != hipSuccess) { delete c; return TPCSF_E_HIP; }
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    c->grid_lds = grid_lds_setup((int)prop.sharedMemPerBlock);
+    c->grid_lds_max = grid_lds_setup((int)prop.sharedMemPerBlock);
     if ((e = hipMalloc(&c->d_rx, sizeof(float) * c->n_rows)) != hipSuccess) { delete c; return TPCSF_E_NOMEM; }
     if ((e = hipMalloc(&c->d_ctr, sizeof(Counters))) != hipSuccess) {
         (void)hipFree(c->d_rx);
@@ -512,6 +523,7 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
     k.arena = c->arena;
     k.out = *o;
     k.tuning = c->tuning;
+    k.grid_lds = launch_cfg(c).grid_lds;
     hipError_t e;
     if (c->timing) {
         // timed calls run the same launch sequence eagerly on the caller's stream, with an

@@ -169,9 +169,9 @@ __global__ void k_reset(Batch B)
 // (once nz == 1 the y bin) doubles.  Clusters are ordered by bin iz*ny + iy, ties by
 // in-row index (a stable counting sort).
 //
-// The sort runs in LDS: bin counts by LDS atomics, an in-place block scan, placement by
-// LDS atomics (arbitrary order inside a bin), then every bin is put in index order by an
-// insertion sort (bins hold a few clusters).  All global writes are then row-contiguous:
+// The sort runs in LDS: bin counts (16-bit, two per word) by LDS atomics, an in-place
+// block scan, placement by LDS atomics (arbitrary order inside a bin), then every bin is
+// put in index order by an insertion sort (bins hold a few clusters).  All global writes are then row-contiguous:
 // sorted (y, z), perm (sorted -> in-row index), the bin table, and the inverse
 // permutation inside the row.  A row whose tables do not fit in LDS takes the same steps
 // on the global bin table, ordered chunk by chunk by one wave (a ballot match on the bin
@@ -186,6 +186,32 @@ __device__ __forceinline__ uint32_t grid_key(float y, float z, float ylo, float 
                                              int nz)
 {
     return (uint32_t)(bin_of(z, zlo, bz, nz) * ny + bin_of(y, ylo, by, ny));
+}
+
+// 16-bit counter b of an array of counter pairs (two per 32-bit word, low half first).
+__device__ __forceinline__ uint32_t half_get(const uint32_t* a2, int b) { return (a2[b >> 1] >> ((b & 1) << 4)) & 0xFFFFu; }
+__device__ __forceinline__ uint32_t half_one(int b) { return (b & 1) ? 0x10000u : 1u; }
+
+// In-place exclusive scan of m 16-bit counters packed in pairs (all sums < 2^16).
+__device__ void block_excl_scan_lds16(uint32_t* a2, int m, int* tmp /*[17]*/)
+{
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int words = (m + 1) >> 1;
+    const int seg = (words + nt - 1) / nt;
+    const int w0 = min(words, t * seg), w1 = min(words, w0 + seg);
+    uint32_t sum = 0;
+    for (int w = w0; w < w1; ++w) sum += (a2[w] & 0xFFFFu) + (a2[w] >> 16);
+    int total;
+    uint32_t run = (uint32_t)block_excl_scan((int)sum, &total, tmp);
+    for (int w = w0; w < w1; ++w) {
+        const uint32_t v = a2[w];
+        const uint32_t lo = run;
+        run += v & 0xFFFFu;
+        const uint32_t hi = run;
+        run += v >> 16;
+        a2[w] = lo | (hi << 16);
+    }
+    __syncthreads();
 }
 
 // In-place exclusive scan of a[0, m) in LDS by the whole block (sums < 2^31).
@@ -278,17 +304,23 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(Batch B, DevParams P, int
         }
         const int nb = ny * nz;
         uint32_t* bs = B.bin_start + bin_base(P, base, g);
-        // LDS: counts / cursors [nb + 1] (u32), then the placement [n] (u16)
-        bool in_lds = n <= 65535 && 4 * (int64_t)(nb + 1) + 2 * (int64_t)n <= (int64_t)lds_bytes;
+        // LDS: counts / cursors [nb + 1] (16-bit, two per word; a row holds < 65535
+        // clusters, so no count or prefix carries into the next counter), then the
+        // placement [n] (u16)
+        const int words = (nb + 2) >> 1;
+        bool in_lds = n <= 65535 && 4 * (int64_t)words + 2 * (int64_t)n <= (int64_t)lds_bytes;
         uint32_t* cnt = sm;
-        uint16_t* pl = (uint16_t*)(sm + nb + 1);
+        uint16_t* pl = (uint16_t*)(sm + words);
         if (in_lds) {
-            for (int b = t; b <= nb; b += nt) cnt[b] = 0u;
+            for (int w = t; w < words; w += nt) cnt[w] = 0u;
             if (t == 0) maxbin = 0;
             __syncthreads();
             uint32_t mx = 0;
-            for (int i = t; i < n; i += nt)
-                mx = max(mx, atomicAdd(&cnt[grid_key(yr[i], zr[i], ylo, zlo, by, bz, ny, nz)], 1u) + 1u);
+            for (int i = t; i < n; i += nt) {
+                const int b = (int)grid_key(yr[i], zr[i], ylo, zlo, by, bz, ny, nz);
+                const uint32_t old = atomicAdd(&cnt[b >> 1], half_one(b));
+                mx = max(mx, ((old >> ((b & 1) << 4)) & 0xFFFFu) + 1u);
+            }
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
             if (lane == 0) atomicMax(&maxbin, mx);
@@ -297,21 +329,22 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(Batch B, DevParams P, int
             in_lds = maxbin <= (uint32_t)kGridMaxLdsBin;
         }
         if (in_lds) {
-            block_excl_scan_lds(cnt, nb + 1, tmp);     // cnt[b] = first slot of bin b, cnt[nb] = n
-            for (int b = t; b <= nb; b += nt) bs[b] = cnt[b];
+            block_excl_scan_lds16(cnt, nb + 1, tmp);   // counter b = first slot of bin b, counter nb = n
+            for (int b = t; b <= nb; b += nt) bs[b] = half_get(cnt, b);
             __syncthreads();
             for (int i = t; i < n; i += nt) {
-                const uint32_t pos = atomicAdd(&cnt[grid_key(yr[i], zr[i], ylo, zlo, by, bz, ny, nz)], 1u);
-                pl[pos] = (uint16_t)i;
+                const int b = (int)grid_key(yr[i], zr[i], ylo, zlo, by, bz, ny, nz);
+                const uint32_t old = atomicAdd(&cnt[b >> 1], half_one(b));
+                pl[(old >> ((b & 1) << 4)) & 0xFFFFu] = (uint16_t)i;
             }
             __syncthreads();
-            // cnt[b] is now the end of bin b; order each bin by in-row index
+            // counter b is now the end of bin b; order each bin by in-row index
             for (int b = t; b < nb; b += nt) {
-                const int s = b ? (int)cnt[b - 1] : 0, e = (int)cnt[b];
-                for (int a = s + 1; a < e; ++a) {
+                const int s0 = b ? (int)half_get(cnt, b - 1) : 0, e = (int)half_get(cnt, b);
+                for (int a = s0 + 1; a < e; ++a) {
                     const uint16_t v = pl[a];
                     int c = a;
-                    while (c > s && pl[c - 1] > v) {
+                    while (c > s0 && pl[c - 1] > v) {
                         pl[c] = pl[c - 1];
                         --c;
                     }
