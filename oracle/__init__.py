@@ -45,6 +45,7 @@ class _Tracks(C.Structure):
         ("params", C.c_void_p), ("cov", C.c_void_p), ("x_ref", C.c_void_p), ("chi2", C.c_void_p),
         ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p),
         ("hit_off", C.c_void_p), ("hit_ids", C.c_void_p), ("cluster_track", C.c_void_p),
+        ("z_beam", C.c_void_p),
     ]
 
 
@@ -87,6 +88,8 @@ def _lib(mode):
         lib.orc_seed.argtypes = [C.POINTER(_Cfg), dp, dp, dp, dp]
         lib.orc_update.argtypes = [C.POINTER(_Cfg), C.c_double, C.c_double, dp, dp]
         lib.orc_update.restype = C.c_double
+        lib.orc_beamline_z.argtypes = [C.POINTER(_Cfg), C.c_double, dp]
+        lib.orc_beamline_z.restype = C.c_double
         lib.orc_fit_hits.argtypes = [C.POINTER(_Cfg), C.c_int32, dp, dp, dp, dp, dp, dp, dp]
         _LIBS[mode] = lib
     return _LIBS[mode]
@@ -126,10 +129,11 @@ class Oracle:
         o = dict(params=np.zeros((cap_t, 5)), cov=np.zeros((cap_t, 15)), x_ref=np.zeros(cap_t),
                  chi2=np.zeros(cap_t), ndf=np.zeros(cap_t, np.int32), nhits=np.zeros(cap_t, np.int32),
                  sector=np.zeros(cap_t, np.int32), hit_off=np.zeros(cap_t + 1, np.int64),
-                 hit_ids=np.zeros(cap_h, np.int64), cluster_track=np.zeros(max(n, 1), np.int32))
+                 hit_ids=np.zeros(cap_h, np.int64), cluster_track=np.zeros(max(n, 1), np.int32),
+                 z_beam=np.zeros(cap_t))
         tr = _Tracks(cap_t, cap_h, 0, 0, *[_ptr(o[k]) for k in
                                             ("params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector",
-                                             "hit_off", "hit_ids", "cluster_track")])
+                                             "hit_off", "hit_ids", "cluster_track", "z_beam")])
         dbg = None
         d = {}
         if debug:
@@ -162,7 +166,7 @@ class Oracle:
         res = dict(n_tracks=T, n_hits=H, params=o["params"][:T], cov=o["cov"][:T], x_ref=o["x_ref"][:T],
                    chi2=o["chi2"][:T], ndf=o["ndf"][:T], nhits=o["nhits"][:T], sector=o["sector"][:T],
                    hit_off=o["hit_off"][:T + 1], hit_ids=o["hit_ids"][:H],
-                   cluster_track=o["cluster_track"][:n])
+                   cluster_track=o["cluster_track"][:n], z_beam=o["z_beam"][:T])
         if debug:
             K = dbg.n_tracklets
             for k in ("tl_start", "tl_nhits"):
@@ -210,6 +214,11 @@ class Oracle:
         J = np.zeros(25)
         rc = self.lib.orc_propagate(C.byref(self.cfg), x0, x1, _dp(p), _dp(Cv), _dp(J))
         return rc == 0, p, Cv, J.reshape(5, 5)
+
+    def beamline_z(self, x0, p):
+        """z at the beam line of the helix of state p at plane x0 (reading R13)."""
+        p = np.array(p, dtype=np.float64)
+        return float(self.lib.orc_beamline_z(C.byref(self.cfg), float(x0), _dp(p)))
 
     def seed(self, x, y, z):
         x, y, z = (np.array(v, dtype=np.float64) for v in (x, y, z))

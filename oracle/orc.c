@@ -400,6 +400,30 @@ int orc_propagate(const orc_cfg* cfg, double x0, double x1, double* p, double* C
     return 0;
 }
 
+double orc_beamline_z(const orc_cfg* cfg, double x0, const double* p)
+{
+    const double y0 = p[0], z0 = p[1], s0 = p[2], tl = p[3];
+    const double c0 = sqrt((1.0 - s0) * (1.0 + s0));   /* tracks move outward: cos phi > 0 */
+    const double kap = -C_B * cfg->bz * p[4];
+    double s;                                          /* signed arc length to the DCA */
+    if (kap == 0.0) {
+        /* straight line: the point where the position is orthogonal to the direction */
+        s = -(x0 * c0 + y0 * s0);
+    } else {
+        /* circle centre; the closest point of the circle to the axis lies on the line
+         * from the centre towards the axis, where the direction angle phi_d has
+         * (sin, cos) = sign(kappa) * (-xc, yc) / |centre| */
+        const double xc = x0 - s0 / kap, yc = y0 + c0 / kap;
+        const double d = sqrt(xc * xc + yc * yc);
+        if (!(d > 0.0)) return z0;
+        const double sg = kap > 0.0 ? 1.0 : -1.0;
+        const double sd = -sg * xc / d, cd = sg * yc / d;
+        const double dphi = atan2(sd * c0 - cd * s0, cd * c0 + sd * s0);
+        s = dphi / kap;
+    }
+    return z0 + tl * s;
+}
+
 int orc_seed(const orc_cfg* cfg, const double* x, const double* y, const double* z, double* p)
 {
     orc_real xr[3], yr[3], zr[3], pr[5];
@@ -780,6 +804,11 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
                 for (int i = 0; i < 5; ++i) out->params[n_tracks * 5 + i] = st.p[i];
                 for (int i = 0; i < 15; ++i) out->cov[n_tracks * 15 + i] = st.C[i];
                 out->x_ref[n_tracks] = fx[0];
+                if (out->z_beam) {
+                    double pd[5];
+                    for (int i = 0; i < 5; ++i) pd[i] = (double)st.p[i];
+                    out->z_beam[n_tracks] = orc_beamline_z(cfg, (double)fx[0], pd);
+                }
                 out->chi2[n_tracks] = c2;
                 out->ndf[n_tracks] = 2 * m - 5;
                 out->nhits[n_tracks] = m;

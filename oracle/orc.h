@@ -61,6 +61,7 @@ typedef struct {
     int64_t* hit_off;          /* [cap_tracks+1]                                 */
     int64_t* hit_ids;          /* [cap_hits] frame cluster index, inner to outer */
     int32_t* cluster_track;    /* [N] track index or -1                          */
+    double* z_beam;            /* [cap_tracks] z at the beam line, or NULL        */
 } orc_tracks;
 
 typedef struct {               /* optional intermediate results; NULL = skip     */
@@ -121,6 +122,15 @@ double orc_update(const orc_cfg* cfg, double my, double mz, double* p, double* C
  * outward-pass state at x[n-1] if not NULL.  Returns 0 or -1 (propagation failure). */
 int orc_fit_hits(const orc_cfg* cfg, int32_t n, const double* x, const double* y,
                  const double* z, double* p, double* C, double* chi2, double* p_outer);
+
+/* z at the beam line (reading R13 of the method notes; the paper's Sec. 6 "Track
+ * reconstruction with continuous data"): the helix of the state p at plane x0 of a sector
+ * frame is followed to its point of closest approach to the beam axis in the transverse
+ * plane (the axis is the origin of every sector frame), and z there is returned.  Under
+ * the assumption that the track is a primary from a vertex at the origin, this is the
+ * most likely z of the track's origin, i.e. its drift offset in the frame's z.  The arc
+ * between the two points is the shorter one (|phi change| <= pi). */
+double orc_beamline_z(const orc_cfg* cfg, double x0, const double* p);
 
 #ifdef __cplusplus
 }

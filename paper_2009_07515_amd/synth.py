@@ -57,7 +57,7 @@ class Frame:
     label     int32[N]     Monte-Carlo track id, -1 for noise
     truth_*   float64[N]   noise-free local state at the crossing (y, z_shifted, sin(phi));
                            NaN for noise
-    trk_*     per MC track: q/pT, tan(lambda), is_secondary, event id
+    trk_*     per MC track: q/pT, tan(lambda), is_secondary, event id, vertex z, t0
     """
     y: np.ndarray
     z: np.ndarray
@@ -72,6 +72,8 @@ class Frame:
     trk_event: np.ndarray
     n_events: int
     tf_length_us: float
+    trk_vz: np.ndarray = None        # per MC track: vertex z (cm, physical)
+    trk_t0: np.ndarray = None        # per MC track: collision time in the frame (us)
 
     @property
     def n_clusters(self) -> int:
@@ -328,7 +330,8 @@ def assemble(rng, tr: Tracks, cl, sigma, noise_frac, tf_length_us, sectors=None,
         label=label[order].astype(np.int32),
         truth_y=y_true[order], truth_z=zshift[order], truth_sphi=sphi[order],
         trk_qpt=tr.q / tr.pt, trk_tgl=np.sinh(tr.eta), trk_secondary=tr.secondary,
-        trk_event=tr.event, n_events=n_events, tf_length_us=tf_length_us)
+        trk_event=tr.event, n_events=n_events, tf_length_us=tf_length_us,
+        trk_vz=np.asarray(tr.zv, dtype=np.float64), trk_t0=np.asarray(tr.t0_us, dtype=np.float64))
 
 
 # ----------------------------------------------------------------------------------------

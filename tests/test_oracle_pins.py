@@ -254,6 +254,51 @@ def test_step_counts_of_one_straight_track(row_x):
 
 
 # --------------------------------------------------------------------------------------
+# z at the beam line (reading R13): hand-worked straight lines; invariance of the result
+# when the state is moved along its own helix (a wrong circle centre, sign or branch
+# would change it); and noise-free primaries, whose tracks must point back to the
+# vertex z (the generator's, t0 = 0).
+# --------------------------------------------------------------------------------------
+def test_beamline_z_straight_line_closed_form(row_x):
+    o = _orc(row_x, bz=0.0)
+    # the line through (100, 0) with direction (0.8, 0.6) is closest to the axis 80 cm back
+    assert abs(o.beamline_z(100.0, [0.0, 10.0, 0.6, 0.5, 0.0]) - (10.0 - 0.5 * 80.0)) < 1e-12
+    # through (120, 15) with direction (0.96, -0.28): 111 cm back
+    assert abs(o.beamline_z(120.0, [15.0, -4.0, -0.28, -0.25, 0.0]) - (-4.0 + 0.25 * 111.0)) < 1e-12
+
+
+def test_beamline_z_is_invariant_along_the_helix(row_x):
+    o = _orc(row_x)
+    rng = np.random.default_rng(5)
+    n = 0
+    for _ in range(300):
+        x0, x1 = rng.uniform(85, 140), rng.uniform(150, 245)
+        p = [rng.uniform(-10, 10), rng.uniform(-200, 200), rng.uniform(-0.5, 0.5), rng.uniform(-1, 1),
+             rng.uniform(-2, 2)]
+        ok, p1, _, _ = o.propagate(x0, x1, p)
+        if not ok:
+            continue
+        assert abs(o.beamline_z(x0, p) - o.beamline_z(x1, p1)) < 1e-8
+        n += 1
+    assert n > 200
+
+
+@pytest.mark.parametrize("bz", [synth.B_Z, 0.0])
+def test_beamline_z_of_noise_free_primaries_is_the_vertex(row_x, bz):
+    f = synth.config1_single_sector(seed=93, n_tracks=80, sigma=0.0, noise_frac=0.0, bz=bz)
+    o = _orc(row_x, bz=bz)
+    r = o.track_frame(f.y, f.z, f.row_off)
+    n = 0
+    for t in range(r["n_tracks"]):
+        lab = f.label[r["hit_ids"][r["hit_off"][t]]]
+        if f.trk_secondary[lab]:
+            continue
+        assert abs(r["z_beam"][t] - f.trk_vz[lab]) < 1e-3
+        n += 1
+    assert n > 30
+
+
+# --------------------------------------------------------------------------------------
 # Final fit vs nonlinear least squares: the inward pass starts at the outermost cluster
 # from the outward estimate with covariance C0, so it estimates the minimiser of
 #   sum_i |m_i - h_i(q)|^2 / sigma^2 + (q - p_outer)^T C0^-1 (q - p_outer)
