@@ -64,8 +64,9 @@ def stage_bytes(c):
         # read candidates, masks, kept coordinates (twice); write the fit results
         "fit": 44 * F + 16 * Ha + 2 * Ha + 176 * F,
         "track_scan": 24 * S,
-        # read fit results, hit table entries and perm; write track records and hit lists
-        "emit": 176 * T + 200 * T + 10 * Ha,
+        # read fit results, hit table entries and perm; write track records (with z at the
+        # beam line) and hit lists
+        "emit": 176 * T + 208 * T + 10 * Ha,
         # read inverse perm and weights, per assigned cluster its track's flag, index and
         # hit range (once per track); write the cluster->track map
         "assign": 12 * N + 24 * T,

@@ -120,6 +120,12 @@ typedef struct {
     int64_t* hit_off;                   /* [device] [cap_tracks+1]                         */
     int32_t* hit_ids;                   /* [device] [cap_hits] batch cluster index         */
     int32_t* cluster_track;             /* [device] [n_clusters] track index or -1         */
+    double* z_beam;                     /* [device] [cap_tracks] z at the beam line, or
+                                           NULL: the track's helix followed inward to its
+                                           closest approach to the beam axis; under the
+                                           assumption of a primary from a vertex at the
+                                           origin, the most likely z of its origin (the
+                                           continuous-readout z estimate of Sec. 6)        */
 } tpcsf_tracks;
 
 /* Defaults of the method constants and of the tuning. */
@@ -231,6 +237,7 @@ typedef struct {
     double* params; double* cov; double* x_ref; double* chi2;
     int32_t* ndf; int32_t* nhits; int32_t* sector;
     int64_t* hit_off; int32_t* hit_ids; int32_t* cluster_track;
+    double* z_beam;                     /* [cap_tracks] or NULL */
 } tpcsf_host_tracks;
 
 tpcsf_status tpcsf_server_create(const tpcsf_geometry* geo, const tpcsf_params* params,

@@ -216,7 +216,7 @@ class Oracle:
         return rc == 0, p, Cv, J.reshape(5, 5)
 
     def beamline_z(self, x0, p):
-        """z at the beam line of the helix of state p at plane x0 (reading R13)."""
+        """z at the beam line of the helix of state p at plane x0 (continuous-readout z estimate, Sec. 6)."""
         p = np.array(p, dtype=np.float64)
         return float(self.lib.orc_beamline_z(C.byref(self.cfg), float(x0), _dp(p)))
 

@@ -123,7 +123,7 @@ double orc_update(const orc_cfg* cfg, double my, double mz, double* p, double* C
 int orc_fit_hits(const orc_cfg* cfg, int32_t n, const double* x, const double* y,
                  const double* z, double* p, double* C, double* chi2, double* p_outer);
 
-/* z at the beam line (reading R13 of the method notes; the paper's Sec. 6 "Track
+/* z at the beam line (Sec. 6, "Track
  * reconstruction with continuous data"): the helix of the state p at plane x0 of a sector
  * frame is followed to its point of closest approach to the beam axis in the transverse
  * plane (the axis is the origin of every sector frame), and z there is returned.  Under

@@ -319,6 +319,7 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.o_par = o->params; B.o_cov = o->cov; B.o_xref = o->x_ref; B.o_chi2 = o->chi2;
     B.o_ndf = o->ndf; B.o_nhits_trk = o->nhits; B.o_sector = o->sector; B.o_tf = o->tf;
     B.o_hit_off = o->hit_off; B.o_hit_ids = o->hit_ids; B.o_cluster_track = o->cluster_track;
+    B.o_zbeam = o->z_beam;
     B.d_up = (int32_t*)(a + L.d_up); B.d_dn = (int32_t*)(a + L.d_dn);
     B.d_cup = (int32_t*)(a + L.d_cup); B.d_cdn = (int32_t*)(a + L.d_cdn);
     B.d_start_row = (int32_t*)(a + L.d_start_row);

@@ -119,6 +119,7 @@ struct Batch {
     double* o_par; double* o_cov; double* o_xref; double* o_chi2;
     int32_t* o_ndf; int32_t* o_nhits_trk; int32_t* o_sector; int32_t* o_tf;
     int64_t* o_hit_off; int32_t* o_hit_ids; int32_t* o_cluster_track;
+    double* o_zbeam;                // may be null
     // verification views in input order (filled only by launch_debug_views)
     int32_t* d_up; int32_t* d_dn; int32_t* d_cup; int32_t* d_cdn;   // [N]
     int32_t* d_start_row; int32_t* d_start_idx; int32_t* d_tl_n;     // [cap_starts] by rank

@@ -1039,6 +1039,29 @@ __device__ bool trk_seed(Trk& t, const double* x, const double* y, const double*
     return true;
 }
 
+// z at the beam line: the helix of state p at plane x0 followed to its point of closest
+// approach to the beam axis (the origin of the sector frame) in the transverse plane,
+// along the shorter arc; z there.  For a primary from a vertex at the origin this is the
+// most likely z of the track's origin (its drift offset in a time frame).
+__device__ double trk_beamline_z(const DevParams& P, double x0, const double* p)
+{
+    const double y0 = p[0], z0 = p[1], s0 = p[2], tl = p[3];
+    const double c0 = sqrt((1.0 - s0) * (1.0 + s0));
+    const double kap = P.a * p[4];
+    double s;
+    if (kap == 0.0) {
+        s = -(x0 * c0 + y0 * s0);
+    } else {
+        const double xc = x0 - s0 / kap, yc = y0 + c0 / kap;   // circle centre
+        const double d = sqrt(xc * xc + yc * yc);
+        if (!(d > 0.0)) return z0;
+        const double sg = kap > 0.0 ? 1.0 : -1.0;
+        const double sd = -sg * xc / d, cd = sg * yc / d;       // direction at the closest point
+        s = atan2(sd * c0 - cd * s0, cd * c0 + sd * s0) / kap;
+    }
+    return z0 + tl * s;
+}
+
 // Least-chi2 cluster of row g (row record rf, ri) inside the follow window: its sorted
 // position (-1 if none) and coordinates.  Equal chi2: the smaller in-row index.  n_win
 // counts the clusters inside the window.
@@ -1722,7 +1745,7 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 
 // ------------------------------------------------------------------------------------
 // Stage 8, emit: tracks at their scanned positions (rank order), hits inner to outer as
-// input cluster indices (from the kept list).  Writes beyond the caller's capacity are
+// input cluster indices (from the kept list), and each track's z at the beam line.  Writes beyond the caller's capacity are
 // dropped and flagged.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
@@ -1761,6 +1784,7 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
                     B.o_tf[T] = (int32_t)(g / ((int64_t)nr * P.n_sectors));
                     B.o_hit_off[T + 1] = hp + nk;
                     B.trk_out[rank] = (int32_t)T;
+                    if (B.o_zbeam) B.o_zbeam[T] = trk_beamline_z(P, B.f_xref[i], B.f_par + i * 5);
                     src = B.cand_off[p];
                 }
             }
@@ -1865,6 +1889,7 @@ __global__ void __launch_bounds__(256) k_hash(Batch B, int64_t n_clusters)
         for (int q = 0; q < 15; ++q) h ^= elem_hash(4, i * 15 + q, __double_as_longlong(B.o_cov[i * 15 + q]));
         h ^= elem_hash(5, i, (unsigned long long)B.o_hit_off[i + 1]);
         h ^= elem_hash(6, i, __double_as_longlong(B.o_chi2[i]));
+        if (B.o_zbeam) h ^= elem_hash(9, i, __double_as_longlong(B.o_zbeam[i]));
     }
     for (int64_t i = t0; i < H; i += stride) h ^= elem_hash(7, i, (unsigned long long)(uint32_t)B.o_hit_ids[i]);
     for (int64_t i = t0; i < n_clusters; i += stride)

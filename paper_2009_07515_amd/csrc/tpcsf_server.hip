@@ -35,11 +35,13 @@ struct Slot {
     // device outputs
     int64_t* d_n = nullptr;            // [2] n_tracks, n_hits
     double* d_par = nullptr; double* d_cov = nullptr; double* d_x = nullptr; double* d_chi2 = nullptr;
+    double* d_zb = nullptr;
     int32_t* d_ndf = nullptr; int32_t* d_nh = nullptr; int32_t* d_sec = nullptr; int32_t* d_tf = nullptr;
     int64_t* d_hoff = nullptr; int32_t* d_hid = nullptr; int32_t* d_ct = nullptr;
     // pinned host outputs
     int64_t* h_n = nullptr;
     double* h_par = nullptr; double* h_cov = nullptr; double* h_x = nullptr; double* h_chi2 = nullptr;
+    double* h_zb = nullptr;
     int32_t* h_ndf = nullptr; int32_t* h_nh = nullptr; int32_t* h_sec = nullptr;
     int64_t* h_hoff = nullptr; int32_t* h_hid = nullptr; int32_t* h_ct = nullptr;
     std::vector<int64_t> h_off;        // host row offsets of the frame being tracked
@@ -77,18 +79,18 @@ tpcsf_status srv_fail(tpcsf_server* s, tpcsf_status st, const std::string& m)
 
 void free_slot_buffers(Slot& sl)
 {
-    void* dev[] = {sl.d_y, sl.d_z, sl.d_off, sl.d_n, sl.d_par, sl.d_cov, sl.d_x, sl.d_chi2, sl.d_ndf,
+    void* dev[] = {sl.d_y, sl.d_z, sl.d_off, sl.d_n, sl.d_par, sl.d_cov, sl.d_x, sl.d_chi2, sl.d_zb, sl.d_ndf,
                    sl.d_nh, sl.d_sec, sl.d_tf, sl.d_hoff, sl.d_hid, sl.d_ct};
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    void* host[] = {sl.h_n, sl.h_par, sl.h_cov, sl.h_x, sl.h_chi2, sl.h_ndf, sl.h_nh, sl.h_sec,
+    void* host[] = {sl.h_n, sl.h_par, sl.h_cov, sl.h_x, sl.h_chi2, sl.h_zb, sl.h_ndf, sl.h_nh, sl.h_sec,
                     sl.h_hoff, sl.h_hid, sl.h_ct};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     sl.d_y = sl.d_z = nullptr; sl.d_off = nullptr; sl.d_n = nullptr;
-    sl.d_par = sl.d_cov = sl.d_x = sl.d_chi2 = nullptr;
+    sl.d_par = sl.d_cov = sl.d_x = sl.d_chi2 = sl.d_zb = nullptr;
     sl.d_ndf = sl.d_nh = sl.d_sec = sl.d_tf = nullptr; sl.d_hoff = nullptr; sl.d_hid = sl.d_ct = nullptr;
-    sl.h_n = nullptr; sl.h_par = sl.h_cov = sl.h_x = sl.h_chi2 = nullptr;
+    sl.h_n = nullptr; sl.h_par = sl.h_cov = sl.h_x = sl.h_chi2 = sl.h_zb = nullptr;
     sl.h_ndf = sl.h_nh = sl.h_sec = nullptr; sl.h_hoff = nullptr; sl.h_hid = sl.h_ct = nullptr;
 }
 
@@ -98,7 +100,7 @@ size_t slot_bytes(const tpcsf_server* s, int64_t cap)
     const int64_t R = (int64_t)s->geo.n_sectors * s->geo.n_rows;
     const int64_t T = cap_tracks_for(cap, s->params.min_track_hits);
     size_t io = (size_t)cap * (4 + 4) + (size_t)(R + 1) * 8 + 16;
-    io += (size_t)T * (5 + 15 + 1 + 1) * 8 + (size_t)T * 4 * 4 + (size_t)(T + 1) * 8 + (size_t)cap * 8;
+    io += (size_t)T * (5 + 15 + 1 + 1 + 1) * 8 + (size_t)T * 4 * 4 + (size_t)(T + 1) * 8 + (size_t)cap * 8;
     return io;
 }
 
@@ -135,11 +137,11 @@ tpcsf_status grow_slot(tpcsf_server* s, Slot& sl, int64_t n)
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
     chk(dmalloc(&sl.d_y, cap)); chk(dmalloc(&sl.d_z, cap)); chk(dmalloc(&sl.d_off, R + 1));
     chk(dmalloc(&sl.d_n, 2)); chk(dmalloc(&sl.d_par, T * 5)); chk(dmalloc(&sl.d_cov, T * 15));
-    chk(dmalloc(&sl.d_x, T)); chk(dmalloc(&sl.d_chi2, T)); chk(dmalloc(&sl.d_ndf, T)); chk(dmalloc(&sl.d_nh, T));
+    chk(dmalloc(&sl.d_x, T)); chk(dmalloc(&sl.d_chi2, T)); chk(dmalloc(&sl.d_zb, T)); chk(dmalloc(&sl.d_ndf, T)); chk(dmalloc(&sl.d_nh, T));
     chk(dmalloc(&sl.d_sec, T)); chk(dmalloc(&sl.d_tf, T)); chk(dmalloc(&sl.d_hoff, T + 1));
     chk(dmalloc(&sl.d_hid, cap)); chk(dmalloc(&sl.d_ct, cap));
     chk(hmalloc(&sl.h_n, 2)); chk(hmalloc(&sl.h_par, T * 5)); chk(hmalloc(&sl.h_cov, T * 15));
-    chk(hmalloc(&sl.h_x, T)); chk(hmalloc(&sl.h_chi2, T)); chk(hmalloc(&sl.h_ndf, T)); chk(hmalloc(&sl.h_nh, T));
+    chk(hmalloc(&sl.h_x, T)); chk(hmalloc(&sl.h_chi2, T)); chk(hmalloc(&sl.h_zb, T)); chk(hmalloc(&sl.h_ndf, T)); chk(hmalloc(&sl.h_nh, T));
     chk(hmalloc(&sl.h_sec, T)); chk(hmalloc(&sl.h_hoff, T + 1)); chk(hmalloc(&sl.h_hid, cap));
     chk(hmalloc(&sl.h_ct, cap));
     if (e != hipSuccess) {
@@ -246,7 +248,7 @@ tpcsf_status tpcsf_server_submit(tpcsf_server* s, const float* y, const float* z
     o.cap_tracks = T;
     o.cap_hits = sl.cap;
     o.n_tracks = sl.d_n; o.n_hits = sl.d_n + 1;
-    o.params = sl.d_par; o.cov = sl.d_cov; o.x_ref = sl.d_x; o.chi2 = sl.d_chi2;
+    o.params = sl.d_par; o.cov = sl.d_cov; o.x_ref = sl.d_x; o.chi2 = sl.d_chi2; o.z_beam = sl.d_zb;
     o.ndf = sl.d_ndf; o.nhits = sl.d_nh; o.sector = sl.d_sec; o.tf = sl.d_tf;
     o.hit_off = sl.d_hoff; o.hit_ids = sl.d_hid; o.cluster_track = sl.d_ct;
     hipStream_t st_ = sl.stream;
@@ -266,6 +268,7 @@ tpcsf_status tpcsf_server_submit(tpcsf_server* s, const float* y, const float* z
     chk(hipMemcpyAsync(sl.h_cov, sl.d_cov, sizeof(double) * 15 * T, hipMemcpyDeviceToHost, st_));
     chk(hipMemcpyAsync(sl.h_x, sl.d_x, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
     chk(hipMemcpyAsync(sl.h_chi2, sl.d_chi2, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
+    chk(hipMemcpyAsync(sl.h_zb, sl.d_zb, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
     chk(hipMemcpyAsync(sl.h_ndf, sl.d_ndf, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
     chk(hipMemcpyAsync(sl.h_nh, sl.d_nh, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
     chk(hipMemcpyAsync(sl.h_sec, sl.d_sec, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
@@ -347,6 +350,7 @@ tpcsf_status tpcsf_server_result(tpcsf_server* s, uint64_t ticket, tpcsf_host_tr
         cp(out->cov, sl->h_cov, sizeof(double) * 15 * T);
         cp(out->x_ref, sl->h_x, sizeof(double) * T);
         cp(out->chi2, sl->h_chi2, sizeof(double) * T);
+        cp(out->z_beam, sl->h_zb, sizeof(double) * T);
         cp(out->ndf, sl->h_ndf, sizeof(int32_t) * T);
         cp(out->nhits, sl->h_nh, sizeof(int32_t) * T);
         cp(out->sector, sl->h_sec, sizeof(int32_t) * T);

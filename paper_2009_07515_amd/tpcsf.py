@@ -62,14 +62,14 @@ class TracksDesc(C.Structure):
                 ("n_hits", C.c_void_p), ("params", C.c_void_p), ("cov", C.c_void_p), ("x_ref", C.c_void_p),
                 ("chi2", C.c_void_p), ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p),
                 ("tf", C.c_void_p), ("hit_off", C.c_void_p), ("hit_ids", C.c_void_p),
-                ("cluster_track", C.c_void_p)]
+                ("cluster_track", C.c_void_p), ("z_beam", C.c_void_p)]
 
 
 class HostTracks(C.Structure):
     _fields_ = [("cap_tracks", C.c_int64), ("cap_hits", C.c_int64), ("n_tracks", C.c_int64), ("n_hits", C.c_int64),
                 ("params", C.c_void_p), ("cov", C.c_void_p), ("x_ref", C.c_void_p), ("chi2", C.c_void_p),
                 ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p), ("hit_off", C.c_void_p),
-                ("hit_ids", C.c_void_p), ("cluster_track", C.c_void_p)]
+                ("hit_ids", C.c_void_p), ("cluster_track", C.c_void_p), ("z_beam", C.c_void_p)]
 
 
 class DebugView(C.Structure):
@@ -227,12 +227,13 @@ class TrackBuffers:
         self.hit_off = torch.zeros(T + 1, dtype=torch.int64, **kw)
         self.hit_ids = torch.empty(max(H, 1), dtype=torch.int32, **kw)
         self.cluster_track = torch.empty(max(n, 1), dtype=torch.int32, **kw)
+        self.z_beam = torch.empty(max(T, 1), dtype=torch.float64, **kw)
 
     def desc(self):
         d = TracksDesc()
         d.cap_tracks, d.cap_hits = self.cap_tracks, self.cap_hits
         for k in ("n_tracks", "n_hits", "params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector", "tf",
-                  "hit_off", "hit_ids", "cluster_track"):
+                  "hit_off", "hit_ids", "cluster_track", "z_beam"):
             setattr(d, k, _ptr(getattr(self, k)))
         return d
 
@@ -243,7 +244,7 @@ class TrackBuffers:
         return dict(n_tracks=T, n_hits=H, params=self.params[:T], cov=self.cov[:T], x_ref=self.x_ref[:T],
                     chi2=self.chi2[:T], ndf=self.ndf[:T], nhits=self.nhits[:T], sector=self.sector[:T],
                     tf=self.tf[:T], hit_off=self.hit_off[:T + 1], hit_ids=self.hit_ids[:H],
-                    cluster_track=self.cluster_track[:n_clusters])
+                    cluster_track=self.cluster_track[:n_clusters], z_beam=self.z_beam[:T])
 
 
 class Tracker:
@@ -480,10 +481,10 @@ class Server:
         o = dict(params=np.zeros((T, 5)), cov=np.zeros((T, 15)), x_ref=np.zeros(T), chi2=np.zeros(T),
                  ndf=np.zeros(T, np.int32), nhits=np.zeros(T, np.int32), sector=np.zeros(T, np.int32),
                  hit_off=np.zeros(T + 1, np.int64), hit_ids=np.zeros(max(n, 1), np.int32),
-                 cluster_track=np.zeros(max(n, 1), np.int32))
+                 cluster_track=np.zeros(max(n, 1), np.int32), z_beam=np.zeros(T))
         ht = HostTracks(T, n, 0, 0, *[o[k].ctypes.data_as(C.c_void_p) for k in
                                       ("params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector", "hit_off",
-                                       "hit_ids", "cluster_track")])
+                                       "hit_ids", "cluster_track", "z_beam")])
         st = self.lib.tpcsf_server_result(self.h, ticket, C.byref(ht))
         del self._inputs[ticket]
         self._check(st)

@@ -72,7 +72,21 @@ def _check_tracks(f, res, ref, o64, label_check=True):
     sg, sr = np.sqrt(res["cov"][:, [0, 2, 5, 9, 14]]), np.sqrt(ref["cov"][:, [0, 2, 5, 9, 14]])
     assert np.all(np.abs(sg - sr) <= 1e-4 * sr)
     assert np.allclose(res["chi2"], ref["chi2"], rtol=1e-6, atol=1e-9)
+    _check_zbeam(res, ref)
     return err / np.maximum(np.abs(q), FLOORS)
+
+
+def _check_zbeam(res, ref, orc=None):
+    """z at the beam line: the oracle's function of the GPU's own (x_ref, params) to rounding
+    (both FP64; atan2 and sqrt may differ by an ulp, which the arc length 1/kappa scales
+    to well below 1e-7 cm); and the oracle's own estimate within the tolerance of the z
+    parameter, 1e-4 * max(|z|, 10 cm)."""
+    zg, zo = res["z_beam"], ref["z_beam"]
+    assert zg.shape == zo.shape and np.all(np.isfinite(zg))
+    assert np.all(np.abs(zg - zo) <= 1e-4 * np.maximum(np.abs(zo), 10.0)), np.abs(zg - zo).max()
+    orc = orc or oracle.Oracle(synth.row_x())
+    own = np.array([orc.beamline_z(res["x_ref"][t], res["params"][t]) for t in range(len(zg))])
+    assert np.all(np.abs(zg - own) <= 1e-7 + 1e-12 * np.abs(own)), np.abs(zg - own).max()
 
 
 @pytest.mark.parametrize("which", ["cfg1", "small", "cfg2"])
@@ -125,7 +139,7 @@ def test_plain_equals_batch_and_is_deterministic(small_pbpb_frame):
     a = _np(trk.track(fr, mode="plain"))
     b = _np(trk.track(fr, mode="batch"))
     c = _np(trk.track(fr, mode="batch"))
-    for k in ("hit_off", "hit_ids", "params", "cov", "chi2", "cluster_track", "sector", "tf"):
+    for k in ("hit_off", "hit_ids", "params", "cov", "chi2", "cluster_track", "sector", "tf", "z_beam"):
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(b[k], c[k]), k
 
@@ -143,6 +157,7 @@ def test_multi_frame_batch_equals_frames_alone():
         assert sel.sum() == one["n_tracks"]
         idx = np.flatnonzero(sel)
         assert np.array_equal(both["params"][idx], one["params"])
+        assert np.array_equal(both["z_beam"][idx], one["z_beam"])
         for t in range(one["n_tracks"]):
             hb = both["hit_ids"][both["hit_off"][idx[t]]:both["hit_off"][idx[t] + 1]]
             ho = one["hit_ids"][one["hit_off"][t]:one["hit_off"][t + 1]]
@@ -161,7 +176,7 @@ def test_tuning_does_not_change_tracks(small_pbpb_frame, tun):
     fr = _frame(f)
     ref = _np(_tracker().track(fr))
     got = _np(_tracker(tuning=tun).track(fr))
-    for k in ("hit_off", "hit_ids", "params", "cov", "cluster_track"):
+    for k in ("hit_off", "hit_ids", "params", "cov", "cluster_track", "z_beam"):
         assert np.array_equal(ref[k], got[k]), k
 
 

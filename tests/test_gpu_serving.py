@@ -10,7 +10,7 @@ from paper_2009_07515_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("hit_off", "hit_ids", "params", "cov", "chi2", "sector", "cluster_track")
+KEYS = ("hit_off", "hit_ids", "params", "cov", "chi2", "sector", "cluster_track", "z_beam")
 
 
 def _np(res):

@@ -254,7 +254,7 @@ def test_step_counts_of_one_straight_track(row_x):
 
 
 # --------------------------------------------------------------------------------------
-# z at the beam line (reading R13): hand-worked straight lines; invariance of the result
+# z at the beam line (Sec. 6): hand-worked straight lines; invariance of the result
 # when the state is moved along its own helix (a wrong circle centre, sign or branch
 # would change it); and noise-free primaries, whose tracks must point back to the
 # vertex z (the generator's, t0 = 0).
