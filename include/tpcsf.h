@@ -74,6 +74,7 @@ typedef struct {
     double sigma_y, sigma_z, chi2_max, sinphi_max, nsig;
     double c0[5];
     int32_t min_chain, min_track_hits, max_miss;
+    double merge_edge, merge_window, merge_chi2;   /* tpcsf_merge, see there */
 } tpcsf_params;
 
 /* Tuning: changes speed and the grid tables, never links or tracks.
@@ -126,6 +127,11 @@ typedef struct {
                                            assumption of a primary from a vertex at the
                                            origin, the most likely z of its origin (the
                                            continuous-readout z estimate of Sec. 6)        */
+    double* params_outer;               /* [device] [cap_tracks][5] or NULL: the final
+                                           fit's outward-pass state at the outermost
+                                           cluster's row (input of tpcsf_merge)            */
+    double* cov_outer;                  /* [device] [cap_tracks][15] or NULL: its
+                                           covariance                                      */
 } tpcsf_tracks;
 
 /* Defaults of the method constants and of the tuning. */
@@ -210,6 +216,82 @@ tpcsf_status tpcsf_set_stage_timing(tpcsf_ctx* ctx, int32_t on);
 int32_t tpcsf_stage_count(void);
 const char* tpcsf_stage_name(int32_t stage);
 tpcsf_status tpcsf_stage_times(tpcsf_ctx* ctx, float* ms, int32_t n);
+
+/* ---------------------------------------------------------------------------------------
+ * Merging across sector boundaries and refit across sector frames: the track-fit stage
+ * that follows sector tracking (Sec. 7, Table 1 "Track Fit"; the paper names the stage
+ * and gives no procedure, so the rule below is this library's definition).
+ *
+ * Sector s lies on side s / S (S = n_sectors / 2) at azimuth ((s mod S) + 1/2) 2 pi / S;
+ * its frame has x along that direction and y towards larger azimuth, so its edges are
+ * |y| = x tan(pi / S).  A track is matched from its outer end A to the inner end B of a
+ * track of the neighbouring sector of the same side when
+ *   - A's outermost cluster is within merge_edge (cm) of an edge, at a larger radius
+ *     than A's innermost cluster; B lies in the sector beyond that edge (larger azimuth
+ *     if A's outermost y >= 0, else smaller) and its innermost cluster is within
+ *     merge_edge of the shared edge, at a larger radius than A's outermost cluster (radii
+ *     from the cluster coordinates; edge and radius tests without contraction);
+ *   - A's outer state (params_outer, cov_outer), rotated into B's frame, predicts B's
+ *     inner y and z linearly (y' + dx tan phi', z' + dx tan lambda / cos phi', dx the
+ *     distance to B's innermost row) within merge_window (cm);
+ *   - the rotated state propagates to B's innermost row, and the chi2 of the difference
+ *     of the two 5-parameter states with the sum of their covariances is <= merge_chi2.
+ * Each A takes its least-chi2 candidate (ties: smaller B); each B keeps, of the A that
+ * took it, the least-chi2 one (ties: smaller A); those pairs are linked.  Radii grow
+ * strictly along links, so links form simple chains.  A chain of several tracks is
+ * refitted over all its clusters in chain order with the final fit (seed from the first,
+ * middle and last cluster in the first cluster's frame; outward pass from C0; inward pass
+ * from C0 keeping the parameters), the state being rotated into a cluster's sector frame
+ * before the step to its row; if that fit fails, the chain is dissolved into its tracks.
+ * A single track keeps its sector fit.  Merged tracks come in the order of their first
+ * (innermost) track.  Rotation: with c = cos(delta), s = sin(delta) for a frame at an
+ * azimuth larger by delta, x' = x c + y s, y' = -x s + y c, sin phi' = sin phi c -
+ * cos phi s (cos phi' must stay > 0), the state given at the plane x' through the rotated
+ * point; its covariance follows the first-order change of that state.
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+    int64_t cap_merged, cap_hits;
+    int64_t* n_merged;                  /* [device] scalar: merged tracks of the batch      */
+    int64_t* n_hits;                    /* [device] scalar: their clusters                 */
+    double* params;                     /* [device] [cap_merged][5] at x_ref, in the frame
+                                           of the first track's sector                     */
+    double* cov;                        /* [device] [cap_merged][15]                       */
+    double* x_ref;                      /* [device] [cap_merged] innermost cluster's row x */
+    double* chi2;                       /* [device] [cap_merged]                           */
+    double* z_beam;                     /* [device] [cap_merged] or NULL: z at the beam
+                                           line, as in tpcsf_tracks                        */
+    int32_t* ndf;                       /* [device] [cap_merged] 2*nhits - 5               */
+    int32_t* nhits;                     /* [device] [cap_merged]                           */
+    int32_t* sector;                    /* [device] [cap_merged] first track's sector      */
+    int32_t* tf;                        /* [device] [cap_merged]                           */
+    int32_t* n_segments;                /* [device] [cap_merged] tracks joined             */
+    int64_t* hit_off;                   /* [device] [cap_merged+1]                         */
+    int32_t* hit_ids;                   /* [device] [cap_hits] batch cluster index, track
+                                           by track in chain order, each inner to outer    */
+    int32_t* track_merged;              /* [device] [input cap_tracks] merged track of each
+                                           input track                                     */
+    int32_t* next;                      /* [device] [input cap_tracks] or NULL: the input
+                                           track linked after this one, or -1 (links of a
+                                           dissolved chain included)                       */
+    double* link_chi2;                  /* [device] [input cap_tracks] or NULL: chi2 of
+                                           that link (0 without one)                       */
+} tpcsf_merged;
+
+/* Merge a batch's sector tracks (the output of tpcsf_track_batch or tpcsf_track_plain on
+ * the same frame, with params_outer and cov_outer requested) and refit the merged tracks.
+ * All device pointers; asynchronous on `stream`; the tracks stay owned by the caller.
+ * Host validation: TPCSF_E_INVALID for missing arrays or an odd sector count; device
+ * validation (reported by tpcsf_sync): TPCSF_E_INVALID if the tracks are not in (time
+ * frame, sector) order or hold clusters outside their own sector (nothing is then
+ * merged), TPCSF_E_CAPACITY if the merged output is too small (*n_merged and *n_hits
+ * hold the required sizes).  Scratch: about 350 bytes per input track capacity, kept by
+ * the context, within its HBM budget (TPCSF_E_NOMEM beyond). */
+tpcsf_status tpcsf_merge(tpcsf_ctx* ctx, const tpcsf_frame* frame, const tpcsf_tracks* tracks,
+                         tpcsf_merged* out, void* stream);
+
+/* Work of the last merge call, after a sync: candidate pairs through the gate, their
+ * propagations, chi2 evaluations; refit rotations, propagations, updates. */
+tpcsf_status tpcsf_merge_work(tpcsf_ctx* ctx, int64_t* work6);
 
 /* Message of the last error on this context (static storage of the context). */
 const char* tpcsf_last_error(const tpcsf_ctx* ctx);

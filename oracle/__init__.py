@@ -21,6 +21,7 @@ DEFAULT_PARAMS = dict(
     sigma_y=0.1, sigma_z=0.1, chi2_max=16.0, sinphi_max=0.99, nsig=5.0,
     c0=(1.0, 1.0, 1.0, 1.0, 100.0),
     min_chain=5, min_track_hits=20, max_miss=4,
+    merge_edge=6.0, merge_window=5.0, merge_chi2=30.0,
 )
 # Grid tuning (changes the grid tables, never links or tracks).
 DEFAULT_GRID = dict(bin_y=2.0, bin_z=2.0, cap_mul=2, cap_add=64)
@@ -35,6 +36,7 @@ class _Cfg(C.Structure):
         ("sinphi_max", C.c_double), ("nsig", C.c_double), ("c0", C.c_double * 5),
         ("min_chain", C.c_int32), ("min_track_hits", C.c_int32), ("max_miss", C.c_int32),
         ("bin_y", C.c_float), ("bin_z", C.c_float), ("cap_mul", C.c_int32), ("cap_add", C.c_int32),
+        ("merge_edge", C.c_double), ("merge_window", C.c_double), ("merge_chi2", C.c_double),
     ]
 
 
@@ -45,7 +47,18 @@ class _Tracks(C.Structure):
         ("params", C.c_void_p), ("cov", C.c_void_p), ("x_ref", C.c_void_p), ("chi2", C.c_void_p),
         ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p),
         ("hit_off", C.c_void_p), ("hit_ids", C.c_void_p), ("cluster_track", C.c_void_p),
-        ("z_beam", C.c_void_p),
+        ("z_beam", C.c_void_p), ("params_outer", C.c_void_p), ("cov_outer", C.c_void_p),
+    ]
+
+
+class _Merged(C.Structure):
+    _fields_ = [
+        ("cap_merged", C.c_int64), ("cap_hits", C.c_int64),
+        ("n_merged", C.c_int64), ("n_hits", C.c_int64),
+        ("params", C.c_void_p), ("cov", C.c_void_p), ("x_ref", C.c_void_p), ("chi2", C.c_void_p),
+        ("z_beam", C.c_void_p), ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p),
+        ("n_segments", C.c_void_p), ("hit_off", C.c_void_p), ("hit_ids", C.c_void_p),
+        ("track_merged", C.c_void_p), ("next", C.c_void_p), ("link_chi2", C.c_void_p),
     ]
 
 
@@ -91,6 +104,10 @@ def _lib(mode):
         lib.orc_beamline_z.argtypes = [C.POINTER(_Cfg), C.c_double, dp]
         lib.orc_beamline_z.restype = C.c_double
         lib.orc_fit_hits.argtypes = [C.POINTER(_Cfg), C.c_int32, dp, dp, dp, dp, dp, dp, dp]
+        lib.orc_rotate.argtypes = [C.POINTER(_Cfg), C.c_double, dp, dp, dp, dp]
+        lib.orc_fit_hits_sectors.argtypes = [C.POINTER(_Cfg), C.c_int32, dp, dp, dp, C.c_void_p, dp, dp, dp]
+        lib.orc_merge_frame.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.POINTER(_Tracks), C.POINTER(_Merged)]
         _LIBS[mode] = lib
     return _LIBS[mode]
 
@@ -116,7 +133,8 @@ class Oracle:
                         p["win_y"], p["win_z"], p["kink_max"], p["sigma_y"], p["sigma_z"],
                         p["chi2_max"], p["sinphi_max"], p["nsig"], (C.c_double * 5)(*p["c0"]),
                         p["min_chain"], p["min_track_hits"], p["max_miss"],
-                        g["bin_y"], g["bin_z"], g["cap_mul"], g["cap_add"])
+                        g["bin_y"], g["bin_z"], g["cap_mul"], g["cap_add"],
+                        p["merge_edge"], p["merge_window"], p["merge_chi2"])
 
     # -- whole frame ----------------------------------------------------------------
     def track_frame(self, y, z, row_off, debug=False, shuffle_seed=0):
@@ -130,10 +148,11 @@ class Oracle:
                  chi2=np.zeros(cap_t), ndf=np.zeros(cap_t, np.int32), nhits=np.zeros(cap_t, np.int32),
                  sector=np.zeros(cap_t, np.int32), hit_off=np.zeros(cap_t + 1, np.int64),
                  hit_ids=np.zeros(cap_h, np.int64), cluster_track=np.zeros(max(n, 1), np.int32),
-                 z_beam=np.zeros(cap_t))
+                 z_beam=np.zeros(cap_t), params_outer=np.zeros((cap_t, 5)), cov_outer=np.zeros((cap_t, 15)))
         tr = _Tracks(cap_t, cap_h, 0, 0, *[_ptr(o[k]) for k in
                                             ("params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector",
-                                             "hit_off", "hit_ids", "cluster_track", "z_beam")])
+                                             "hit_off", "hit_ids", "cluster_track", "z_beam",
+                                             "params_outer", "cov_outer")])
         dbg = None
         d = {}
         if debug:
@@ -166,7 +185,8 @@ class Oracle:
         res = dict(n_tracks=T, n_hits=H, params=o["params"][:T], cov=o["cov"][:T], x_ref=o["x_ref"][:T],
                    chi2=o["chi2"][:T], ndf=o["ndf"][:T], nhits=o["nhits"][:T], sector=o["sector"][:T],
                    hit_off=o["hit_off"][:T + 1], hit_ids=o["hit_ids"][:H],
-                   cluster_track=o["cluster_track"][:n], z_beam=o["z_beam"][:T])
+                   cluster_track=o["cluster_track"][:n], z_beam=o["z_beam"][:T],
+                   params_outer=o["params_outer"][:T], cov_outer=o["cov_outer"][:T])
         if debug:
             K = dbg.n_tracklets
             for k in ("tl_start", "tl_nhits"):
@@ -177,6 +197,45 @@ class Oracle:
                 d[k] = d[k][:n]
             d["work"] = np.array(list(dbg.work), np.int64)
             res["debug"] = d
+        return res
+
+    def merge_frame(self, y, z, row_off, trk):
+        """Merge one frame's sector tracks (a track_frame result) across sector edges and
+        refit the merged tracks (orc_merge_frame)."""
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        z = np.ascontiguousarray(z, dtype=np.float32)
+        row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+        n = int(y.shape[0])
+        T = int(trk["n_tracks"])
+        H = int(trk["n_hits"]) if "n_hits" in trk else int(len(trk["hit_ids"]))
+        conv = dict(params=np.float64, cov=np.float64, x_ref=np.float64, chi2=np.float64, ndf=np.int32,
+                    nhits=np.int32, sector=np.int32, hit_off=np.int64, hit_ids=np.int64,
+                    params_outer=np.float64, cov_outer=np.float64)
+        keep = {k: np.ascontiguousarray(np.asarray(trk[k]), dtype=t) for k, t in conv.items()}
+        tr = _Tracks(T, H, T, H,
+                     *[_ptr(keep[k]) if k in keep else None for k in
+                       ("params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector", "hit_off", "hit_ids",
+                        "cluster_track", "z_beam", "params_outer", "cov_outer")])
+        cm, ch = max(T, 1), max(H, 1)
+        o = dict(params=np.zeros((cm, 5)), cov=np.zeros((cm, 15)), x_ref=np.zeros(cm), chi2=np.zeros(cm),
+                 z_beam=np.zeros(cm), ndf=np.zeros(cm, np.int32), nhits=np.zeros(cm, np.int32),
+                 sector=np.zeros(cm, np.int32), n_segments=np.zeros(cm, np.int32),
+                 hit_off=np.zeros(cm + 1, np.int64), hit_ids=np.zeros(ch, np.int64),
+                 track_merged=np.full(cm, -1, np.int32), next=np.full(cm, -1, np.int32),
+                 link_chi2=np.zeros(cm))
+        mo = _Merged(cm, ch, 0, 0, *[_ptr(o[k]) for k in
+                                     ("params", "cov", "x_ref", "chi2", "z_beam", "ndf", "nhits", "sector",
+                                      "n_segments", "hit_off", "hit_ids", "track_merged", "next",
+                                      "link_chi2")])
+        rc = self.lib.orc_merge_frame(C.byref(self.cfg), n, _ptr(y), _ptr(z), _ptr(row_off),
+                                      C.byref(tr), C.byref(mo))
+        if rc != 0:
+            raise RuntimeError(f"orc_merge_frame failed with {rc}")
+        M, Hm = mo.n_merged, mo.n_hits
+        res = {k: v[:M] for k, v in o.items() if k not in ("hit_off", "hit_ids", "track_merged", "next",
+                                                          "link_chi2")}
+        res.update(n_merged=M, n_hits=Hm, hit_off=o["hit_off"][:M + 1], hit_ids=o["hit_ids"][:Hm],
+                   track_merged=o["track_merged"][:T], next=o["next"][:T], link_chi2=o["link_chi2"][:T])
         return res
 
     # -- single steps ----------------------------------------------------------------
@@ -214,6 +273,25 @@ class Oracle:
         J = np.zeros(25)
         rc = self.lib.orc_propagate(C.byref(self.cfg), x0, x1, _dp(p), _dp(Cv), _dp(J))
         return rc == 0, p, Cv, J.reshape(5, 5)
+
+    def rotate(self, delta, x, p, Cov=None):
+        """State (x, p, C) in the frame of a sector at azimuth larger by delta."""
+        xx = np.array([x], dtype=np.float64)
+        p = np.array(p, dtype=np.float64)
+        Cv = np.zeros(15) if Cov is None else np.array(Cov, dtype=np.float64)
+        J = np.zeros(25)
+        rc = self.lib.orc_rotate(C.byref(self.cfg), float(delta), _dp(xx), _dp(p), _dp(Cv), _dp(J))
+        return rc == 0, float(xx[0]), p, Cv, J.reshape(5, 5)
+
+    def fit_hits_sectors(self, x, y, z, sec):
+        x, y, z = (np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, z))
+        sec = np.ascontiguousarray(sec, dtype=np.int32)
+        p = np.zeros(5)
+        Cv = np.zeros(15)
+        chi2 = np.zeros(1)
+        rc = self.lib.orc_fit_hits_sectors(C.byref(self.cfg), int(x.shape[0]), _dp(x), _dp(y), _dp(z),
+                                           _ptr(sec), _dp(p), _dp(Cv), _dp(chi2))
+        return rc == 0, p, Cv, float(chi2[0])
 
     def beamline_z(self, x0, p):
         """z at the beam line of the helix of state p at plane x0 (continuous-readout z estimate, Sec. 6)."""

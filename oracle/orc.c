@@ -15,6 +15,8 @@
  *   5. tracklets   seed, Kalman fit along the chain, follow outward, refit and follow inward
  *   6. selection   per-cluster max-weight claim, accept tracklets that keep enough clusters
  *   7. final fit   two-pass Kalman refit of each accepted track's kept clusters
+ *   8. merging     links of sector tracks across azimuthal sector edges, refit of the
+ *                  merged tracks across sector frames (orc_merge_frame)
  */
 #include "orc.h"
 
@@ -38,6 +40,7 @@ typedef double orc_real;
 
 /* kappa [1/cm] = -C_B * B [T] * q/pT [c/GeV] */
 #define C_B 0.00299792458
+#define ORC_PI 3.14159265358979323846
 
 /* ---------------------------------------------------------------------------------- */
 /* Step 1: per-row search grid (binary32).                                             */
@@ -445,9 +448,85 @@ double orc_update(const orc_cfg* cfg, double my, double mz, double* p, double* C
     return chi2;
 }
 
+/* ---------------------------------------------------------------------------------- */
+/* Sector frames.  Sector s lies on side s / S (S = n_sectors / 2 sectors per side) at   */
+/* centre azimuth alpha = ((s mod S) + 1/2) * 2 pi / S; its frame has x along the centre */
+/* direction and y towards larger azimuth.  A state moves into the frame of a sector     */
+/* whose azimuth is larger by delta: the point (x, y) and the direction phi are rotated,  */
+/* and the state is then given at the plane x' through the rotated point.                */
+/* ---------------------------------------------------------------------------------- */
+static int side_sectors(const orc_cfg* cfg) { return cfg->n_sectors / 2; }
+
+/* azimuth step from the frame of sector s0 to that of s1 (same side), in (-pi, pi] */
+static double frame_delta(const orc_cfg* cfg, int s0, int s1)
+{
+    const int S = side_sectors(cfg);
+    int d = (s1 % S) - (s0 % S);
+    if (2 * d > S) d -= S;
+    if (2 * d <= -S) d += S;
+    return d * (2.0 * ORC_PI / S);
+}
+
+/* Rotation of the state by delta.  With c = cos delta, s = sin delta:
+ *   x' = x c + y s,  y' = -x s + y c,  sin phi' = sin phi c - cos phi s,
+ *   cos phi' = cos phi c + sin phi s (must stay > 0: the track moves outward),
+ *   z, tan lambda and q/pT are unchanged.
+ * Covariance: a change dy of y moves the point by (s dy, c dy) in the new frame; the
+ * state at the fixed plane x' follows the helix back by s dy, which gives
+ *   dy'/dy = c - s tan phi',  dz'/dy = -s tan(lambda) / cos phi',
+ *   d sin phi'/dy = -kappa s,  d sin phi'/d sin phi = cos phi' / cos phi. */
+static int krotate(const orc_cfg* cfg, kstate* st, double delta, orc_real* Jout)
+{
+    if (delta == 0.0) {
+        if (Jout) { for (int i = 0; i < 25; ++i) Jout[i] = 0; for (int i = 0; i < 5; ++i) Jout[i * 5 + i] = 1; }
+        return 0;
+    }
+    const orc_real c = (orc_real)cos(delta), sn = (orc_real)sin(delta);
+    const orc_real a = -(orc_real)C_B * (orc_real)cfg->bz;
+    orc_real s0 = st->p[2];
+    if (!(R_FABS(s0) < 1)) return -1;
+    orc_real c0 = R_SQRT(1 - s0 * s0);
+    orc_real s1 = s0 * c - c0 * sn;
+    orc_real c1 = c0 * c + s0 * sn;
+    if (!(c1 > 0) || !(R_FABS(s1) < (orc_real)cfg->sinphi_max)) return -1;
+    orc_real x1 = st->x * c + st->p[0] * sn;
+    orc_real y1 = -st->x * sn + st->p[0] * c;
+    orc_real J[25];
+    for (int i = 0; i < 25; ++i) J[i] = 0;
+    for (int i = 0; i < 5; ++i) J[i * 5 + i] = 1;
+    J[0 * 5 + 0] = c - sn * s1 / c1;
+    J[1 * 5 + 0] = -sn * st->p[3] / c1;
+    J[2 * 5 + 0] = -a * st->p[4] * sn;
+    J[2 * 5 + 2] = c1 / c0;
+    st->x = x1;
+    st->p[0] = y1;
+    st->p[2] = s1;
+    orc_real Cf[25], T[25];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) Cf[i * 5 + j] = st->C[li(i, j)];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) {
+            orc_real v = 0;
+            for (int k = 0; k < 5; ++k) v += J[i * 5 + k] * Cf[k * 5 + j];
+            T[i * 5 + j] = v;
+        }
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j) {
+            orc_real v = 0;
+            for (int k = 0; k < 5; ++k) v += T[i * 5 + k] * J[j * 5 + k];
+            st->C[li(i, j)] = v;
+        }
+    if (Jout)
+        for (int i = 0; i < 25; ++i) Jout[i] = J[i];
+    return 0;
+}
+
 /* Step 7: final fit of n ordered clusters.  Seed from first/middle/last, C = C0, update
  * at the first cluster and outward over the rest; then C = C0 keeping p, update at the
- * last cluster and inward to the first.  Result at the innermost cluster. */
+ * last cluster and inward to the first.  Result at the innermost cluster.
+ * sec (NULL: one sector) gives each cluster's sector, for tracks merged across sectors:
+ * the seed points are rotated into the first cluster's frame, and the state is rotated
+ * into a cluster's frame before it is propagated to that cluster's row. */
 /* Counts one step of kind k (see orc_debug.work); no effect on any result. */
 static void count(int64_t* work, int k)
 {
@@ -455,18 +534,34 @@ static void count(int64_t* work, int k)
 }
 
 static int kfit(const orc_cfg* cfg, int32_t n, const orc_real* x, const orc_real* y,
-                const orc_real* z, kstate* st, orc_real* chi2, orc_real* p_outer, int64_t* work)
+                const orc_real* z, const int32_t* sec, kstate* st, orc_real* chi2,
+                orc_real* p_outer, orc_real* C_outer, int64_t* work)
 {
     if (n < 3) return -1;
-    orc_real sx[3] = {x[0], x[(n - 1) / 2], x[n - 1]};
-    orc_real sy[3] = {y[0], y[(n - 1) / 2], y[n - 1]};
-    orc_real sz[3] = {z[0], z[(n - 1) / 2], z[n - 1]};
+    const int32_t ids[3] = {0, (n - 1) / 2, n - 1};
+    orc_real sx[3], sy[3], sz[3];
+    for (int k = 0; k < 3; ++k) {
+        int32_t i = ids[k];
+        sx[k] = x[i]; sy[k] = y[i]; sz[k] = z[i];
+        if (sec && sec[i] != sec[0]) {
+            /* point of sector sec[i] in the frame of sec[0] (rotation by -delta) */
+            double d = frame_delta(cfg, sec[0], sec[i]);
+            orc_real c = (orc_real)cos(d), sn = (orc_real)sin(d);
+            sx[k] = x[i] * c - y[i] * sn;
+            sy[k] = x[i] * sn + y[i] * c;
+        }
+    }
     if (kseed(cfg, sx, sy, sz, st->p) != 0) return -1;
     st->x = x[0];
+    int32_t frame = sec ? sec[0] : 0;
     kreset(cfg, st);
     count(work, 4);
     kupdate(cfg, st, y[0], z[0]);
     for (int32_t i = 1; i < n; ++i) {
+        if (sec && sec[i] != frame) {
+            if (krotate(cfg, st, frame_delta(cfg, frame, sec[i]), NULL) != 0) return -1;
+            frame = sec[i];
+        }
         count(work, 3);
         if (kprop(cfg, st, x[i], NULL) != 0) return -1;
         count(work, 4);
@@ -474,11 +569,17 @@ static int kfit(const orc_cfg* cfg, int32_t n, const orc_real* x, const orc_real
     }
     if (p_outer)
         for (int i = 0; i < 5; ++i) p_outer[i] = st->p[i];
+    if (C_outer)
+        for (int i = 0; i < 15; ++i) C_outer[i] = st->C[i];
     kreset(cfg, st);
     count(work, 4);
     count(work, 5);
     orc_real c2 = kupdate(cfg, st, y[n - 1], z[n - 1]);
     for (int32_t i = n - 2; i >= 0; --i) {
+        if (sec && sec[i] != frame) {
+            if (krotate(cfg, st, frame_delta(cfg, frame, sec[i]), NULL) != 0) return -1;
+            frame = sec[i];
+        }
         count(work, 3);
         if (kprop(cfg, st, x[i], NULL) != 0) return -1;
         count(work, 4);
@@ -502,7 +603,7 @@ int orc_fit_hits(const orc_cfg* cfg, int32_t n, const double* x, const double* y
     for (int32_t i = 0; i < n; ++i) { xr[i] = (orc_real)x[i]; yr[i] = (orc_real)y[i]; zr[i] = (orc_real)z[i]; }
     kstate st;
     orc_real c2 = 0, po[5];
-    int rc = kfit(cfg, n, xr, yr, zr, &st, &c2, po, NULL);
+    int rc = kfit(cfg, n, xr, yr, zr, NULL, &st, &c2, po, NULL, NULL);
     free(xr);
     if (rc != 0) return -1;
     for (int i = 0; i < 5; ++i) p[i] = st.p[i];
@@ -799,7 +900,8 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
             if (m < cfg->min_track_hits) continue;
             kstate st;
             orc_real c2;
-            if (kfit(cfg, m, fx, fy, fz, &st, &c2, NULL, dbg ? dbg->work : NULL) != 0) continue;
+            orc_real po[5], Co[15];
+            if (kfit(cfg, m, fx, fy, fz, NULL, &st, &c2, po, Co, dbg ? dbg->work : NULL) != 0) continue;
             if (n_tracks < out->cap_tracks && n_hits + m <= out->cap_hits) {
                 for (int i = 0; i < 5; ++i) out->params[n_tracks * 5 + i] = st.p[i];
                 for (int i = 0; i < 15; ++i) out->cov[n_tracks * 15 + i] = st.C[i];
@@ -809,6 +911,10 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
                     for (int i = 0; i < 5; ++i) pd[i] = (double)st.p[i];
                     out->z_beam[n_tracks] = orc_beamline_z(cfg, (double)fx[0], pd);
                 }
+                if (out->params_outer)
+                    for (int i = 0; i < 5; ++i) out->params_outer[n_tracks * 5 + i] = po[i];
+                if (out->cov_outer)
+                    for (int i = 0; i < 15; ++i) out->cov_outer[n_tracks * 15 + i] = Co[i];
                 out->chi2[n_tracks] = c2;
                 out->ndf[n_tracks] = 2 * m - 5;
                 out->nhits[n_tracks] = m;
@@ -831,5 +937,275 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
     out->n_tracks = n_tracks;
     out->n_hits = n_hits;
     if (dbg) dbg->n_tracklets = n_tl;
+    return rc;
+}
+
+int orc_rotate(const orc_cfg* cfg, double delta, double* x, double* p, double* C, double* J)
+{
+    kstate st;
+    st.x = (orc_real)*x;
+    for (int i = 0; i < 5; ++i) st.p[i] = (orc_real)p[i];
+    for (int i = 0; i < 15; ++i) st.C[i] = (orc_real)C[i];
+    orc_real Jr[25];
+    if (krotate(cfg, &st, delta, Jr) != 0) return -1;
+    *x = st.x;
+    for (int i = 0; i < 5; ++i) p[i] = st.p[i];
+    for (int i = 0; i < 15; ++i) C[i] = st.C[i];
+    if (J)
+        for (int i = 0; i < 25; ++i) J[i] = Jr[i];
+    return 0;
+}
+
+int orc_fit_hits_sectors(const orc_cfg* cfg, int32_t n, const double* x, const double* y,
+                         const double* z, const int32_t* sec, double* p, double* C, double* chi2)
+{
+    orc_real* xr = (orc_real*)malloc(sizeof(orc_real) * (size_t)(n > 0 ? n : 1) * 3);
+    orc_real* yr = xr + n;
+    orc_real* zr = yr + n;
+    for (int32_t i = 0; i < n; ++i) { xr[i] = (orc_real)x[i]; yr[i] = (orc_real)y[i]; zr[i] = (orc_real)z[i]; }
+    kstate st;
+    orc_real c2 = 0;
+    int rc = kfit(cfg, n, xr, yr, zr, sec, &st, &c2, NULL, NULL, NULL);
+    free(xr);
+    if (rc != 0) return -1;
+    for (int i = 0; i < 5; ++i) p[i] = st.p[i];
+    for (int i = 0; i < 15; ++i) C[i] = st.C[i];
+    *chi2 = c2;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------- */
+/* Merging across sector boundaries (the track-fit stage after sector tracking, Sec. 7,  */
+/* Table 1 "Track Fit").  The paper gives no procedure; this is the definition used:     */
+/*                                                                                        */
+/* A track leaving its sector through an azimuthal edge continues in the neighbouring    */
+/* sector of the same side.  A link A -> B is a candidate when                             */
+/*   - A's outermost cluster lies within merge_edge of an edge (|y| >= x tan(pi/S) -      */
+/*     merge_edge), at a larger radius than A's innermost cluster;                         */
+/*   - B lies in the sector beyond that edge (the one at larger azimuth if that y >= 0,   */
+/*     else the one at smaller azimuth), and B's innermost cluster lies within merge_edge */
+/*     of the shared edge (y < 0, resp. y >= 0, in B's frame) at a larger radius than A's  */
+/*     outermost cluster (radii from the cluster coordinates);                             */
+/*   - A's outer state (the outward pass's state at its outermost cluster), rotated into  */
+/*     B's frame, predicts B's inner state linearly within merge_window in y and in z:    */
+/*     |y' + dx tan phi' - y_B| and |z' + dx tan(lambda) / cos phi' - z_B| <= merge_window */
+/*     with dx = x_B - x';                                                                */
+/*   - the rotated state propagates to B's innermost row, and the chi2 of the difference  */
+/*     of the two 5-parameter states with the sum of their covariances is at most          */
+/*     merge_chi2.                                                                        */
+/* Every A takes its candidate of least chi2 (ties: smaller B); every B keeps, of the A   */
+/* that took it, the one of least chi2 (ties: smaller A); that pair is linked.  Radii     */
+/* grow strictly along links, so links form simple chains.  A chain of several tracks    */
+/* becomes one track with the clusters of its segments in chain order, refitted across    */
+/* the sectors (kfit with sector frames); if that fit fails the chain is dissolved into  */
+/* its segments.  Merged tracks are emitted in the order of their first input track; a  */
+/* single segment keeps its sector fit.                                                   */
+/* ---------------------------------------------------------------------------------- */
+
+/* d^T S^-1 d for a symmetric 5x5 S (lower triangle) by Cholesky; -1 if S is not
+ * positive definite */
+static int chi2_5(const orc_real* S15, const orc_real* d, orc_real* out)
+{
+    orc_real L[5][5];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j) {
+            orc_real v = S15[li(i, j)];
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(v > 0)) return -1;
+                L[i][i] = R_SQRT(v);
+            } else {
+                L[i][j] = v / L[j][j];
+            }
+        }
+    orc_real u[5], c2 = 0;
+    for (int i = 0; i < 5; ++i) {
+        orc_real v = d[i];
+        for (int k = 0; k < i; ++k) v -= L[i][k] * u[k];
+        u[i] = v / L[i][i];
+        c2 += u[i] * u[i];
+    }
+    *out = c2;
+    return 0;
+}
+
+int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
+                    const int64_t* row_off, const orc_tracks* trk, orc_merged* out)
+{
+    const int nr = cfg->n_rows, ns = cfg->n_sectors;
+    const int S = ns / 2;
+    const int64_t T = trk->n_tracks;
+    if (ns < 2 || ns % 2 || !trk->params_outer || !trk->cov_outer || T < 0) return -1;
+    if (row_off[0] != 0 || row_off[(int64_t)ns * nr] != n) return -1;
+    const size_t nT = (size_t)(T > 0 ? T : 1);
+
+    int32_t* row = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t g = 0; g < (int64_t)ns * nr; ++g)
+        for (int64_t i = row_off[g]; i < row_off[g + 1]; ++i) row[i] = (int32_t)(g % nr);
+
+    /* cluster coordinates of each track's innermost and outermost cluster */
+    double* xi = (double*)malloc(sizeof(double) * nT * 4);
+    double* yi = xi + nT;
+    double* xo = yi + nT;
+    double* yo = xo + nT;
+    for (int64_t t = 0; t < T; ++t) {
+        int64_t hi = trk->hit_ids[trk->hit_off[t]], ho = trk->hit_ids[trk->hit_off[t + 1] - 1];
+        xi[t] = (double)cfg->row_x[row[hi]]; yi[t] = (double)y[hi];
+        xo[t] = (double)cfg->row_x[row[ho]]; yo[t] = (double)y[ho];
+    }
+    const double te = tan(ORC_PI / S), m = cfg->merge_edge, W = cfg->merge_window;
+    /* the tracks of each sector, in index order */
+    int64_t* sec_start = (int64_t*)calloc((size_t)ns + 1, sizeof(int64_t));
+    int64_t* sec_list = (int64_t*)malloc(sizeof(int64_t) * nT);
+    for (int64_t t = 0; t < T; ++t) {
+        if (trk->sector[t] < 0 || trk->sector[t] >= ns) { free(row); free(xi); free(sec_start); free(sec_list); return -1; }
+        sec_start[trk->sector[t] + 1] += 1;
+    }
+    for (int s = 0; s < ns; ++s) sec_start[s + 1] += sec_start[s];
+    {
+        int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)ns);
+        for (int s = 0; s < ns; ++s) fill[s] = sec_start[s];
+        for (int64_t t = 0; t < T; ++t) sec_list[fill[trk->sector[t]]++] = t;
+        free(fill);
+    }
+
+    /* candidates: each A's best B */
+    int64_t* bestB = (int64_t*)malloc(sizeof(int64_t) * nT);
+    orc_real* bestC = (orc_real*)malloc(sizeof(orc_real) * nT);
+    for (int64_t a = 0; a < T; ++a) {
+        bestB[a] = -1;
+        bestC[a] = 0;
+        const double ro2 = xo[a] * xo[a] + yo[a] * yo[a];
+        if (!(fabs(yo[a]) >= xo[a] * te - m)) continue;
+        if (!(ro2 > xi[a] * xi[a] + yi[a] * yi[a])) continue;
+        const int sa = trk->sector[a], up = yo[a] >= 0;
+        const int sb = (sa / S) * S + ((sa % S) + (up ? 1 : S - 1)) % S;
+        kstate A0;
+        A0.x = (orc_real)xo[a];
+        for (int i = 0; i < 5; ++i) A0.p[i] = (orc_real)trk->params_outer[a * 5 + i];
+        for (int i = 0; i < 15; ++i) A0.C[i] = (orc_real)trk->cov_outer[a * 15 + i];
+        if (krotate(cfg, &A0, frame_delta(cfg, sa, sb), NULL) != 0) continue;
+        const orc_real c1 = R_SQRT(1 - A0.p[2] * A0.p[2]);
+        for (int64_t j = sec_start[sb]; j < sec_start[sb + 1]; ++j) {
+            const int64_t b = sec_list[j];
+            if (up ? !(yi[b] < 0) : !(yi[b] >= 0)) continue;
+            if (!(fabs(yi[b]) >= xi[b] * te - m)) continue;
+            if (!(xi[b] * xi[b] + yi[b] * yi[b] > ro2)) continue;
+            const double* pb = trk->params + b * 5;
+            const orc_real dx = (orc_real)xi[b] - A0.x;
+            const orc_real ylin = A0.p[0] + dx * A0.p[2] / c1;
+            const orc_real zlin = A0.p[1] + dx * A0.p[3] / c1;
+            if (!(R_FABS(ylin - (orc_real)pb[0]) <= (orc_real)W && R_FABS(zlin - (orc_real)pb[1]) <= (orc_real)W))
+                continue;
+            kstate A1 = A0;
+            if (kprop(cfg, &A1, (orc_real)xi[b], NULL) != 0) continue;
+            orc_real d[5], Ssum[15], c2;
+            for (int i = 0; i < 5; ++i) d[i] = A1.p[i] - (orc_real)pb[i];
+            for (int i = 0; i < 15; ++i) Ssum[i] = A1.C[i] + (orc_real)trk->cov[b * 15 + i];
+            if (chi2_5(Ssum, d, &c2) != 0) continue;
+            if (!(c2 <= (orc_real)cfg->merge_chi2)) continue;
+            if (bestB[a] < 0 || c2 < bestC[a]) { bestB[a] = b; bestC[a] = c2; }
+        }
+    }
+    /* each B keeps the best A that took it; links */
+    int64_t* keepA = (int64_t*)malloc(sizeof(int64_t) * nT);
+    int64_t* next = (int64_t*)malloc(sizeof(int64_t) * nT);
+    int64_t* prev = (int64_t*)malloc(sizeof(int64_t) * nT);
+    for (int64_t t = 0; t < T; ++t) { keepA[t] = -1; next[t] = -1; prev[t] = -1; }
+    for (int64_t a = 0; a < T; ++a) {
+        int64_t b = bestB[a];
+        if (b < 0) continue;
+        if (keepA[b] < 0 || bestC[a] < bestC[keepA[b]]) keepA[b] = a;
+    }
+    for (int64_t b = 0; b < T; ++b)
+        if (keepA[b] >= 0) { next[keepA[b]] = b; prev[b] = keepA[b]; }
+    if (out->next)
+        for (int64_t t = 0; t < T; ++t) out->next[t] = (int32_t)next[t];
+    if (out->link_chi2)
+        for (int64_t t = 0; t < T; ++t) out->link_chi2[t] = next[t] >= 0 ? (double)bestC[t] : 0.0;
+
+    /* chains: refit those of several segments; a failed fit dissolves the chain */
+    int8_t* dissolved = (int8_t*)calloc(nT, 1);
+    int8_t* fitted = (int8_t*)calloc(nT, 1);
+    kstate* fit = (kstate*)malloc(sizeof(kstate) * nT);
+    orc_real* fit_c2 = (orc_real*)malloc(sizeof(orc_real) * nT);
+    int32_t* chain_hits = (int32_t*)calloc(nT, sizeof(int32_t));
+    int32_t* chain_seg = (int32_t*)calloc(nT, sizeof(int32_t));
+    int64_t max_h = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        if (prev[t] >= 0) continue;
+        int32_t nh = 0, nseg = 0;
+        for (int64_t u = t; u >= 0; u = next[u]) { nh += (int32_t)(trk->hit_off[u + 1] - trk->hit_off[u]); ++nseg; }
+        chain_hits[t] = nh;
+        chain_seg[t] = nseg;
+        if (nh > max_h) max_h = nh;
+    }
+    orc_real* fx = (orc_real*)malloc(sizeof(orc_real) * (size_t)(max_h > 0 ? max_h : 1) * 3);
+    orc_real* fy = fx + (max_h > 0 ? max_h : 1);
+    orc_real* fz = fy + (max_h > 0 ? max_h : 1);
+    int32_t* fs = (int32_t*)malloc(sizeof(int32_t) * (size_t)(max_h > 0 ? max_h : 1));
+    for (int64_t t = 0; t < T; ++t) {
+        if (prev[t] >= 0 || chain_seg[t] < 2) continue;
+        int32_t k = 0;
+        for (int64_t u = t; u >= 0; u = next[u])
+            for (int64_t j = trk->hit_off[u]; j < trk->hit_off[u + 1]; ++j) {
+                int64_t h = trk->hit_ids[j];
+                fx[k] = (orc_real)cfg->row_x[row[h]];
+                fy[k] = (orc_real)y[h];
+                fz[k] = (orc_real)z[h];
+                fs[k] = trk->sector[u];
+                ++k;
+            }
+        if (kfit(cfg, k, fx, fy, fz, fs, &fit[t], &fit_c2[t], NULL, NULL, NULL) == 0) {
+            fitted[t] = 1;
+        } else {
+            for (int64_t u = t; u >= 0; u = next[u]) dissolved[u] = 1;
+        }
+    }
+
+    /* emit in the order of the first input track */
+    int rc = 0;
+    int64_t M = 0, H = 0;
+    if (out->hit_off && out->cap_merged >= 0) out->hit_off[0] = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        const int whole = prev[t] < 0 && fitted[t];
+        const int single = !whole && (prev[t] < 0 || dissolved[t]);
+        if (!whole && !single) continue;
+        const int32_t nh = whole ? chain_hits[t] : (int32_t)(trk->hit_off[t + 1] - trk->hit_off[t]);
+        if (M < out->cap_merged && H + nh <= out->cap_hits) {
+            double pd[5];
+            if (whole) {
+                for (int i = 0; i < 5; ++i) pd[i] = out->params[M * 5 + i] = fit[t].p[i];
+                for (int i = 0; i < 15; ++i) out->cov[M * 15 + i] = fit[t].C[i];
+                out->chi2[M] = fit_c2[t];
+                out->n_segments[M] = chain_seg[t];
+            } else {
+                for (int i = 0; i < 5; ++i) pd[i] = out->params[M * 5 + i] = trk->params[t * 5 + i];
+                for (int i = 0; i < 15; ++i) out->cov[M * 15 + i] = trk->cov[t * 15 + i];
+                out->chi2[M] = trk->chi2[t];
+                out->n_segments[M] = 1;
+            }
+            out->x_ref[M] = trk->x_ref[t];
+            if (out->z_beam) out->z_beam[M] = orc_beamline_z(cfg, trk->x_ref[t], pd);
+            out->ndf[M] = 2 * nh - 5;
+            out->nhits[M] = nh;
+            out->sector[M] = trk->sector[t];
+            int64_t k = H;
+            for (int64_t u = t; u >= 0; u = whole ? next[u] : -1) {
+                out->track_merged[u] = (int32_t)M;
+                for (int64_t j = trk->hit_off[u]; j < trk->hit_off[u + 1]; ++j) out->hit_ids[k++] = trk->hit_ids[j];
+            }
+            out->hit_off[M + 1] = H + nh;
+        } else {
+            rc = -3;
+        }
+        ++M;
+        H += nh;
+    }
+    out->n_merged = M;
+    out->n_hits = H;
+    free(row); free(xi); free(sec_start); free(sec_list); free(bestB); free(bestC); free(keepA); free(next); free(prev);
+    free(dissolved); free(fitted); free(fit); free(fit_c2); free(chain_hits); free(chain_seg);
+    free(fx); free(fs);
     return rc;
 }

@@ -46,6 +46,10 @@ typedef struct {
     /* grid (tuning: changes the grid tables only, never links or tracks) */
     float bin_y, bin_z;
     int32_t cap_mul, cap_add; /* a row of n clusters has at most cap_mul*n+cap_add bins */
+    /* merging across sector boundaries (orc_merge_frame) */
+    double merge_edge;        /* a track end within this distance of a sector edge (cm) */
+    double merge_window;      /* linear-prediction gate on y and z (cm)              */
+    double merge_chi2;        /* largest accepted 5-parameter chi2 of a match        */
 } orc_cfg;
 
 typedef struct {
@@ -62,6 +66,9 @@ typedef struct {
     int64_t* hit_ids;          /* [cap_hits] frame cluster index, inner to outer */
     int32_t* cluster_track;    /* [N] track index or -1                          */
     double* z_beam;            /* [cap_tracks] z at the beam line, or NULL        */
+    double* params_outer;      /* [cap_tracks][5] outward-pass state at the outermost
+                                  cluster's row, or NULL                           */
+    double* cov_outer;         /* [cap_tracks][15] its covariance, or NULL        */
 } orc_tracks;
 
 typedef struct {               /* optional intermediate results; NULL = skip     */
@@ -131,6 +138,46 @@ int orc_fit_hits(const orc_cfg* cfg, int32_t n, const double* x, const double* y
  * most likely z of the track's origin, i.e. its drift offset in the frame's z.  The arc
  * between the two points is the shorter one (|phi change| <= pi). */
 double orc_beamline_z(const orc_cfg* cfg, double x0, const double* p);
+
+/* Rotation of the state (x, p, C) into the frame of a sector whose azimuth is larger by
+ * delta; J receives the 5x5 Jacobian if not NULL.  Returns -1 if the rotated track
+ * would not move outward or |sin phi'| >= sinphi_max. */
+int orc_rotate(const orc_cfg* cfg, double delta, double* x, double* p, double* C, double* J);
+
+/* Final fit across sectors: as orc_fit_hits, with sec[i] the sector of cluster i (its
+ * x, y in that sector's frame); the result is in the frame of sec[0]. */
+int orc_fit_hits_sectors(const orc_cfg* cfg, int32_t n, const double* x, const double* y,
+                         const double* z, const int32_t* sec, double* p, double* C, double* chi2);
+
+/* Tracks merged across sector boundaries.  Every input track belongs to exactly one
+ * merged track; merged tracks come in the order of their first input track. */
+typedef struct {
+    int64_t cap_merged, cap_hits;
+    int64_t n_merged, n_hits;  /* written                                         */
+    double* params;            /* [cap_merged][5] at the innermost cluster, in the
+                                  frame of its sector                              */
+    double* cov;               /* [cap_merged][15]                                 */
+    double* x_ref;             /* [cap_merged]                                     */
+    double* chi2;              /* [cap_merged]                                     */
+    double* z_beam;            /* [cap_merged] or NULL                             */
+    int32_t* ndf;              /* [cap_merged] 2*nhits - 5                         */
+    int32_t* nhits;            /* [cap_merged]                                     */
+    int32_t* sector;           /* [cap_merged] sector of the innermost cluster     */
+    int32_t* n_segments;       /* [cap_merged] input tracks joined                 */
+    int64_t* hit_off;          /* [cap_merged+1]                                   */
+    int64_t* hit_ids;          /* [cap_hits] frame cluster index, segment by segment */
+    int32_t* track_merged;     /* [n_tracks] merged track of each input track       */
+    int32_t* next;             /* [n_tracks] accepted link to the next segment or -1;
+                                  NULL to skip                                     */
+    double* link_chi2;         /* [n_tracks] chi2 of that link; NULL to skip       */
+} orc_merged;
+
+/* Merge one frame's sector tracks (orc_track_frame output with params_outer and
+ * cov_outer) across the azimuthal sector boundaries of each side, and refit each merged
+ * track over all its clusters.  Returns 0, -1 on invalid input, -3 if an output is too
+ * small (sizes are still written). */
+int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
+                    const int64_t* row_off, const orc_tracks* trk, orc_merged* out);
 
 #ifdef __cplusplus
 }

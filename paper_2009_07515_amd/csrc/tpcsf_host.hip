@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -25,7 +26,7 @@ struct Layout {
     size_t st_row, st_k, st_rank, tl_len, order, tl_n, tl_rlo, tl_rhi, tl_hits;
     size_t keep_n, fit_pos, cand_off, kept_list, keep_mask, fit_list;
     size_t trk_flag, hit_cnt, trk_idx, hit_pos, trk_out;
-    size_t f_par, f_cov, f_chi2, f_xref, scan_part;
+    size_t f_par, f_cov, f_chi2, f_xref, f_pout, f_cout, scan_part;
     size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n;
 };
 
@@ -62,6 +63,9 @@ struct tpcsf_ctx {
     Counters* d_ctr = nullptr;
     void* arena = nullptr;
     size_t arena_size = 0;
+    void* marena = nullptr;         // scratch of tpcsf_merge
+    size_t marena_size = 0;
+    MergeCounters* d_mc = nullptr;
     Layout lay{};
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -146,6 +150,8 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.f_cov = take(F * 15 * 8);
     L.f_chi2 = take(F * 8);
     L.f_xref = take(F * 8);
+    L.f_pout = take(F * 5 * 8);
+    L.f_cout = take(F * 15 * 8);
     L.scan_part = take((4 * kScanBlocks + 2) * 8);
     L.d_up = take(N * 4);
     L.d_dn = take(N * 4);
@@ -208,6 +214,7 @@ bool params_ok(const tpcsf_params* p)
     if (!(p->sinphi_max > 0 && p->sinphi_max < 1)) return false;
     for (int i = 0; i < 5; ++i)
         if (!(p->c0[i] > 0)) return false;
+    if (!(p->merge_edge >= 0 && p->merge_window >= 0 && p->merge_chi2 >= 0)) return false;
     return p->min_chain >= 3 && p->min_track_hits >= 3 && p->max_miss >= 0;
 }
 
@@ -243,7 +250,7 @@ tpcsf_status check_frame(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks*
 
 tpcsf_status ensure_arena(tpcsf_ctx* c, const Layout& L)
 {
-    if (c->budget && L.total > c->budget)
+    if (c->budget && L.total + c->marena_size > c->budget)
         return fail(c, TPCSF_E_NOMEM, "scratch of " + std::to_string(L.total) + " bytes exceeds the HBM budget");
     if (c->arena && c->arena_size >= L.total) return TPCSF_OK;
     hipError_t e;
@@ -255,7 +262,7 @@ tpcsf_status ensure_arena(tpcsf_ctx* c, const Layout& L)
     }
     // reserved layouts are sized exactly; otherwise leave room for slightly larger batches
     const size_t want = c->reserve_n ? L.total : L.total + L.total / 8;
-    const size_t sz = (c->budget && want > c->budget) ? L.total : want;
+    const size_t sz = (c->budget && want + c->marena_size > c->budget) ? L.total : want;
     if ((e = hipMalloc(&c->arena, sz)) != hipSuccess) {
         c->arena = nullptr;
         return fail(c, TPCSF_E_NOMEM, std::string("hipMalloc of the arena: ") + hipGetErrorString(e));
@@ -305,6 +312,9 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.f_cov = (double*)(a + L.f_cov);
     B.f_chi2 = (double*)(a + L.f_chi2);
     B.f_xref = (double*)(a + L.f_xref);
+    const bool outer = o->params_outer && o->cov_outer;
+    B.f_pout = outer ? (double*)(a + L.f_pout) : nullptr;
+    B.f_cout = outer ? (double*)(a + L.f_cout) : nullptr;
     B.cap_fit = (int32_t)L.cap_fit;
     B.trk_flag = (int32_t*)(a + L.trk_flag);
     B.hit_cnt = (int32_t*)(a + L.hit_cnt);
@@ -320,6 +330,8 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.o_ndf = o->ndf; B.o_nhits_trk = o->nhits; B.o_sector = o->sector; B.o_tf = o->tf;
     B.o_hit_off = o->hit_off; B.o_hit_ids = o->hit_ids; B.o_cluster_track = o->cluster_track;
     B.o_zbeam = o->z_beam;
+    B.o_par_out = outer ? o->params_outer : nullptr;
+    B.o_cov_out = outer ? o->cov_outer : nullptr;
     B.d_up = (int32_t*)(a + L.d_up); B.d_dn = (int32_t*)(a + L.d_dn);
     B.d_cup = (int32_t*)(a + L.d_cup); B.d_cdn = (int32_t*)(a + L.d_cdn);
     B.d_start_row = (int32_t*)(a + L.d_start_row);
@@ -358,7 +370,165 @@ void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t
     mark();
 }
 
+// Scratch of one merge call: T = input track capacity, K = n_tf * n_sectors.
+struct MergeLayout {
+    size_t total = 0;
+    size_t ends, a_list, b_list, sec_first, cnt, brec, bidx, mstate, bestB, bestChi, keepChi, keepA;
+    size_t next, prev, nseg, chain_hits, fit_ok, diss, lead, nh, fit_list, m_idx, m_hpos, scan_part;
+};
+
+MergeLayout make_merge_layout(int64_t T, int64_t K)
+{
+    MergeLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    const size_t t = (size_t)(T > 0 ? T : 1), k = (size_t)(K > 0 ? K : 1);
+    L.ends = take(t * 16);
+    L.a_list = take(t * 4);
+    L.b_list = take(t * 4);
+    L.sec_first = take(k * 4);
+    L.cnt = take(2 * k * 4);
+    L.brec = take(2 * t * 32);
+    L.bidx = take(2 * t * 4);
+    L.mstate = take(t * 21 * 8);
+    L.bestB = take(t * 4);
+    L.bestChi = take(t * 8);
+    L.keepChi = take(t * 8);
+    L.keepA = take(t * 4);
+    L.next = take(t * 4);
+    L.prev = take(t * 4);
+    L.nseg = take(t * 4);
+    L.chain_hits = take(t * 4);
+    L.fit_ok = take(t * 4);
+    L.diss = take(t * 4);
+    L.lead = take(t * 4);
+    L.nh = take(t * 4);
+    L.fit_list = take(t * 4);
+    L.m_idx = take(t * 8);
+    L.m_hpos = take(t * 8);
+    L.scan_part = take((4 * kScanBlocks + 2) * 8);
+    L.total = o;
+    return L;
+}
+
 }  // namespace
+
+extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks* t, tpcsf_merged* o,
+                                    void* stream)
+{
+    if (!c) return TPCSF_E_INVALID;
+    if (!f || !t || !o) return fail(c, TPCSF_E_INVALID, "null frame, tracks or output");
+    if (c->n_sectors < 2 || c->n_sectors % 2 || c->n_sectors / 2 > kMergeMaxSide)
+        return fail(c, TPCSF_E_INVALID, "merging needs an even number of sectors, at most 128");
+    if (f->n_tf < 1 || !f->row_offsets || !f->row_offsets_host || f->n_clusters < 0)
+        return fail(c, TPCSF_E_INVALID, "frame incomplete");
+    if (f->n_clusters > 0 && (!f->y || !f->z)) return fail(c, TPCSF_E_INVALID, "cluster arrays missing");
+    const int64_t R = (int64_t)f->n_tf * c->n_sectors * c->n_rows;
+    if (f->row_offsets_host[0] != 0 || f->row_offsets_host[R] != f->n_clusters)
+        return fail(c, TPCSF_E_INVALID, "row offsets do not span the clusters");
+    if (t->cap_tracks < 0 || !t->n_tracks || !t->hit_off)
+        return fail(c, TPCSF_E_INVALID, "track input incomplete");
+    if (t->cap_tracks > 0 && (!t->params || !t->cov || !t->x_ref || !t->chi2 || !t->sector || !t->tf ||
+                              !t->hit_ids || !t->params_outer || !t->cov_outer))
+        return fail(c, TPCSF_E_INVALID, "track input arrays missing (outer states are required)");
+    if (t->cap_tracks >= ((int64_t)1 << 31) - 1) return fail(c, TPCSF_E_INVALID, "too many input tracks");
+    if (o->cap_merged < 0 || o->cap_hits < 0 || !o->n_merged || !o->n_hits || !o->hit_off)
+        return fail(c, TPCSF_E_INVALID, "merged output descriptor incomplete");
+    if (o->cap_merged > 0 && (!o->params || !o->cov || !o->x_ref || !o->chi2 || !o->ndf || !o->nhits ||
+                              !o->sector || !o->tf || !o->n_segments))
+        return fail(c, TPCSF_E_INVALID, "merged output arrays missing");
+    if (o->cap_hits > 0 && !o->hit_ids) return fail(c, TPCSF_E_INVALID, "merged hit array missing");
+    if (t->cap_tracks > 0 && !o->track_merged) return fail(c, TPCSF_E_INVALID, "track_merged missing");
+    const int64_t K = (int64_t)f->n_tf * c->n_sectors;
+    const MergeLayout L = make_merge_layout(t->cap_tracks, K);
+    hipError_t e;
+    if (c->marena_size < L.total) {
+        if (c->budget && c->arena_size + L.total > c->budget)
+            return fail(c, TPCSF_E_NOMEM, "merge scratch of " + std::to_string(L.total) + " bytes exceeds the HBM budget");
+        if (c->marena) {
+            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+            if ((e = hipFree(c->marena)) != hipSuccess) return hip_fail(c, e, "hipFree");
+            c->marena = nullptr;
+            c->marena_size = 0;
+        }
+        if ((e = hipMalloc(&c->marena, L.total)) != hipSuccess) {
+            c->marena = nullptr;
+            return fail(c, TPCSF_E_NOMEM, std::string("hipMalloc of the merge scratch: ") + hipGetErrorString(e));
+        }
+        c->marena_size = L.total;
+    }
+    if (!c->d_mc && (e = hipMalloc(&c->d_mc, sizeof(MergeCounters))) != hipSuccess) {
+        c->d_mc = nullptr;
+        return fail(c, TPCSF_E_NOMEM, "hipMalloc of the merge counters");
+    }
+    char* a = (char*)c->marena;
+    MergeBatch M{};
+    M.y = f->y; M.z = f->z; M.off = f->row_offsets;
+    M.n_tracks = t->n_tracks; M.cap_tracks = t->cap_tracks;
+    M.hit_off = t->hit_off; M.hit_ids = t->hit_ids;
+    M.par = t->params; M.cov = t->cov; M.xref = t->x_ref; M.chi2 = t->chi2;
+    M.sector = t->sector; M.tf = t->tf;
+    M.par_out = t->params_outer; M.cov_out = t->cov_outer;
+    M.n_tf = f->n_tf;
+    M.ends = (float4*)(a + L.ends);
+    M.a_list = (int32_t*)(a + L.a_list);
+    M.b_list = (int32_t*)(a + L.b_list);
+    M.sec_first = (int32_t*)(a + L.sec_first);
+    M.cnt = (int32_t*)(a + L.cnt);
+    M.brec = (double4*)(a + L.brec);
+    M.bidx = (int32_t*)(a + L.bidx);
+    M.mstate = (double*)(a + L.mstate);
+    M.bestB = (int32_t*)(a + L.bestB);
+    M.bestChi = (double*)(a + L.bestChi);
+    M.keepChi = (unsigned long long*)(a + L.keepChi);
+    M.keepA = (int32_t*)(a + L.keepA);
+    M.next = (int32_t*)(a + L.next);
+    M.prev = (int32_t*)(a + L.prev);
+    M.nseg = (int32_t*)(a + L.nseg);
+    M.chain_hits = (int32_t*)(a + L.chain_hits);
+    M.fit_ok = (int32_t*)(a + L.fit_ok);
+    M.diss = (int32_t*)(a + L.diss);
+    M.lead = (int32_t*)(a + L.lead);
+    M.nh = (int32_t*)(a + L.nh);
+    M.fit_list = (int32_t*)(a + L.fit_list);
+    M.m_idx = (int64_t*)(a + L.m_idx);
+    M.m_hpos = (int64_t*)(a + L.m_hpos);
+    M.scan_part = (int64_t*)(a + L.scan_part);
+    M.mc = c->d_mc;
+    M.ctr = c->d_ctr;
+    M.cap_merged = o->cap_merged; M.cap_hits = o->cap_hits;
+    M.o_n = o->n_merged; M.o_nhits = o->n_hits;
+    M.o_par = o->params; M.o_cov = o->cov; M.o_xref = o->x_ref; M.o_chi2 = o->chi2; M.o_zbeam = o->z_beam;
+    M.o_ndf = o->ndf; M.o_nhits_trk = o->nhits; M.o_sector = o->sector; M.o_tf = o->tf;
+    M.o_nseg = o->n_segments;
+    M.o_hit_off = o->hit_off; M.o_hit_ids = o->hit_ids;
+    M.o_track_merged = o->track_merged; M.o_next = o->next; M.o_link_chi2 = o->link_chi2;
+    MergeParams Q{};
+    const tpcsf_params& p = c->params;
+    Q.edge = p.merge_edge; Q.window = p.merge_window; Q.chi2 = p.merge_chi2;
+    Q.S = c->n_sectors / 2;
+    const double pi = 3.14159265358979323846;
+    Q.te = std::tan(pi / Q.S);
+    for (int d = -(Q.S - 1) / 2; d <= Q.S / 2; ++d) {
+        const double delta = d * (2.0 * pi / Q.S);
+        Q.rc[d + Q.S / 2] = std::cos(delta);
+        Q.rs[d + Q.S / 2] = std::sin(delta);
+    }
+    launch_merge(M, dev_params(c), Q, c->n_cu, (hipStream_t)stream);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "merge kernel launch");
+    return TPCSF_OK;
+}
+
+extern "C" tpcsf_status tpcsf_merge_work(tpcsf_ctx* c, int64_t* work6)
+{
+    if (!c || !work6) return TPCSF_E_INVALID;
+    if (!c->d_mc) return fail(c, TPCSF_E_INVALID, "no merge call yet");
+    MergeCounters mc;
+    hipError_t e = hipMemcpy(&mc, c->d_mc, sizeof mc, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "reading the merge counters");
+    for (int k = 0; k < 6; ++k) work6[k] = mc.work[k];
+    return TPCSF_OK;
+}
 
 extern "C" {
 
@@ -377,6 +547,9 @@ void tpcsf_default_params(tpcsf_params* p)
     p->min_chain = 5;
     p->min_track_hits = 20;
     p->max_miss = 4;
+    p->merge_edge = 6.0;
+    p->merge_window = 5.0;
+    p->merge_chi2 = 30.0;
 }
 
 void tpcsf_default_tuning(tpcsf_tuning* t)
@@ -446,6 +619,8 @@ tpcsf_status tpcsf_destroy(tpcsf_ctx* c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->arena) (void)hipFree(c->arena);
+    if (c->marena) (void)hipFree(c->marena);
+    if (c->d_mc) (void)hipFree(c->d_mc);
     for (int i = 0; i <= kStages; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->d_rx) (void)hipFree(c->d_rx);
@@ -581,6 +756,7 @@ tpcsf_status tpcsf_sync(tpcsf_ctx* c, void* stream)
     if (err & kErrInvalid) return fail(c, TPCSF_E_INVALID, "non-finite or out-of-range cluster coordinates");
     if (err & kErrOutCap) return fail(c, TPCSF_E_CAPACITY, "output capacity too small");
     if (err & kErrTrackletCap) return fail(c, TPCSF_E_CAPACITY, "tracklet slots exhausted");
+    if (err & kErrMergeChain) return fail(c, TPCSF_E_INVALID, "a merged chain exceeds the walk bound");
     return TPCSF_OK;
 }
 

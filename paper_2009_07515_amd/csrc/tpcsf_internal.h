@@ -101,6 +101,9 @@ struct Batch {
     double* f_cov;                  // [cap_fit][15]
     double* f_chi2;                 // [cap_fit]
     double* f_xref;                 // [cap_fit]
+    double* f_pout;                 // [cap_fit][5] outward-pass state at the outermost
+                                    //     cluster, or null when not requested
+    double* f_cout;                 // [cap_fit][15] its covariance
     int32_t cap_fit;
     // rank indexed
     int32_t* trk_flag;              // 1 = accepted and fitted
@@ -120,9 +123,32 @@ struct Batch {
     int32_t* o_ndf; int32_t* o_nhits_trk; int32_t* o_sector; int32_t* o_tf;
     int64_t* o_hit_off; int32_t* o_hit_ids; int32_t* o_cluster_track;
     double* o_zbeam;                // may be null
+    double* o_par_out;              // may be null
+    double* o_cov_out;              // may be null
     // verification views in input order (filled only by launch_debug_views)
     int32_t* d_up; int32_t* d_dn; int32_t* d_cup; int32_t* d_cdn;   // [N]
     int32_t* d_start_row; int32_t* d_start_idx; int32_t* d_tl_n;     // [cap_starts] by rank
+};
+
+// Device-wide exclusive scan of up to two channels over [lo, hi) (bounds read from
+// device memory where the pointers are given).
+struct ScanJob {
+    const int64_t* a64;       // channel A input (int64) or null
+    const int32_t* a32;       // channel A input (int32) if a64 is null
+    const int32_t* b32;       // channel B input (int32) or null
+    int32_t a_min;            // > 0: channel A counts a32[i] >= a_min as 1, else 0
+    int64_t* outA;
+    int64_t* outB;
+    int64_t lo, hi;           // range if lo_ptr is null
+    const int64_t* lo_ptr;
+    const int64_t* hi_ptr;
+    int64_t* baseA;           // running base, advanced by the total
+    int64_t* baseB;
+    int64_t* totA;            // receives base + total (optional)
+    int64_t* totB;
+    int64_t* rangeA_lo;       // receives [base, base + total) (optional)
+    int64_t* rangeA_hi;
+    int64_t* part;            // [4 * kScanBlocks]
 };
 
 struct LaunchCfg {
@@ -132,6 +158,72 @@ struct LaunchCfg {
     int n_cu;       // compute units
     int grid_lds;   // dynamic LDS bytes of the grid kernel
 };
+
+// Merging across sector boundaries (tpcsf_merge).
+constexpr int kMergeMaxSide = 64;    // sectors per side the merge supports
+constexpr int kMergeMaxChain = 64;   // walk bound of a chain (links raise the radius
+                                     // strictly, so chains never revisit a track)
+constexpr int32_t kErrMergeChain = 8;
+
+struct MergeParams {
+    double edge, window, chi2;      // merge_edge, merge_window, merge_chi2
+    double te;                      // tan(pi / S): |y| = x te at a sector's edges
+    int32_t S;                      // sectors per side
+    // cos and sin of the azimuth step d * 2 pi / S between two sectors of one side, at
+    // [d + S/2] for d in (-S/2, S/2]
+    double rc[kMergeMaxSide + 1], rs[kMergeMaxSide + 1];
+};
+
+struct MergeCounters {
+    int64_t T;                      // input tracks (min(n_tracks, cap_tracks))
+    int32_t n_fit;                  // chains of several segments
+    int32_t bad;                    // invalid input seen: nothing is merged
+    // algorithmic work: candidate pairs through the gate, their propagations (attempts),
+    // chi2 evaluations; merged-fit rotations, propagations, updates
+    int64_t work[6];
+};
+
+// Device pointers of one merge call (T = cap_tracks of the input, K = n_tf * n_sectors).
+struct MergeBatch {
+    // inputs: the frame's clusters and the sector tracks with their outer states
+    const float* y; const float* z; const int64_t* off;
+    const int64_t* n_tracks; int64_t cap_tracks;
+    const int64_t* hit_off; const int32_t* hit_ids;
+    const double* par; const double* cov; const double* xref; const double* chi2;
+    const int32_t* sector; const int32_t* tf;
+    const double* par_out; const double* cov_out;
+    int32_t n_tf;
+    // scratch
+    float4* ends;                   // [T] innermost (x, y) and outermost (x, y) cluster
+    int32_t* a_list;                // [T] list an outer end is matched against, or -1
+    int32_t* b_list;                // [T] list of an inner end, or -1
+    int32_t* sec_first;             // [K] first track of each (time frame, sector)
+    int32_t* cnt;                   // [2K] entries per list (list = key * 2 + edge)
+    double4* brec;                  // [2T] entries: x_in, radius^2 of the inner cluster, y, z
+    int32_t* bidx;                  // [2T] their tracks
+    double* mstate;                 // [T][21] rotated outer state (x, p, C); later the
+                                    //     merged fit of a chain head (p, C, chi2)
+    int32_t* bestB; double* bestChi;
+    unsigned long long* keepChi;    // [T] least chi2 (bits) of the outer ends that chose B
+    int32_t* keepA;                 // [T] smallest such end at that chi2
+    int32_t* next; int32_t* prev;
+    int32_t* nseg; int32_t* chain_hits; int32_t* fit_ok; int32_t* diss;
+    int32_t* lead; int32_t* nh;     // scan inputs
+    int32_t* fit_list;
+    int64_t* m_idx; int64_t* m_hpos;
+    int64_t* scan_part;
+    MergeCounters* mc;
+    Counters* ctr;                  // error bits
+    // outputs
+    int64_t cap_merged, cap_hits;
+    int64_t* o_n; int64_t* o_nhits;
+    double* o_par; double* o_cov; double* o_xref; double* o_chi2; double* o_zbeam;
+    int32_t* o_ndf; int32_t* o_nhits_trk; int32_t* o_sector; int32_t* o_tf; int32_t* o_nseg;
+    int64_t* o_hit_off; int32_t* o_hit_ids;
+    int32_t* o_track_merged; int32_t* o_next; double* o_link_chi2;
+};
+
+void launch_merge(const MergeBatch& b, const DevParams& p, const MergeParams& m, int n_cu, hipStream_t s);
 
 // Stage launchers (all asynchronous on `stream`).  Row ranges are [g0, g1).
 // Allows the grid kernel the device's LDS per block; returns the dynamic LDS bytes to use.
@@ -153,5 +245,6 @@ void launch_emit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStre
 void launch_assign(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
 void launch_debug_views(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_hash(const Batch& b, int64_t n_clusters, const LaunchCfg& c, hipStream_t s);
+void launch_scan(const ScanJob& job, hipStream_t s);
 
 }  // namespace tpcsf

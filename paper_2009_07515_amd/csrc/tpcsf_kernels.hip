@@ -8,6 +8,7 @@
 // binary32 and which keeps the covariance updates well conditioned after a reset to the
 // (deliberately loose) initial covariance.
 #include "tpcsf_internal.h"
+#include "tpcsf_kalman.h"
 
 #include <math.h>
 
@@ -729,24 +730,6 @@ __global__ void __launch_bounds__(1024) k_starts(Batch B, DevParams P, int64_t g
 // sums that also advances the running bases, per-block scans).  Ranges may come from
 // device memory, so one graph serves every batch of the same shape.
 // ------------------------------------------------------------------------------------
-struct ScanJob {
-    const int64_t* a64;       // channel A input (int64) or null
-    const int32_t* a32;       // channel A input (int32) if a64 is null
-    const int32_t* b32;       // channel B input (int32) or null
-    int32_t a_min;            // > 0: channel A counts a32[i] >= a_min as 1, else 0
-    int64_t* outA;
-    int64_t* outB;
-    int64_t lo, hi;           // range if lo_ptr is null
-    const int64_t* lo_ptr;
-    const int64_t* hi_ptr;
-    int64_t* baseA;           // running base, advanced by the total
-    int64_t* baseB;
-    int64_t* totA;            // receives base + total (optional)
-    int64_t* totB;
-    int64_t* rangeA_lo;       // receives [base, base + total) (optional)
-    int64_t* rangeA_hi;
-    int64_t* part;            // [4 * kScanBlocks]
-};
 
 __device__ __forceinline__ void scan_range(const ScanJob& J, int64_t& lo, int64_t& hi)
 {
@@ -878,188 +861,9 @@ static void run_scan(ScanJob J, hipStream_t s)
     hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanThreads), 0, s, J);
 }
 
-// ------------------------------------------------------------------------------------
-// Kalman filter in binary64.  State (y, z, sin phi, tan lambda, q/pT) at plane x;
-// curvature kappa = a * q/pT.  Covariance: 15-element lower triangle.
-// ------------------------------------------------------------------------------------
-struct Trk {
-    double x;
-    double p[5];
-    double c[15];
-};
-
-// asin(h)/h and its derivative; Taylor series near 0
-__device__ __forceinline__ void arc_factor(double h, double& A, double& Ap)
+void launch_scan(const ScanJob& job, hipStream_t s)
 {
-    if (fabs(h) < 0.01) {
-        const double h2 = h * h;
-        A = 1.0 + h2 * (1.0 / 6.0 + h2 * (3.0 / 40.0 + h2 * (5.0 / 112.0)));
-        Ap = h * (1.0 / 3.0 + h2 * (3.0 / 10.0 + h2 * (15.0 / 56.0 + h2 * (35.0 / 144.0))));
-    } else {
-        const double as = asin(h);
-        const double ih = 1.0 / h;
-        A = as * ih;
-        Ap = (h / sqrt((1.0 - h) * (1.0 + h)) - as) * ih * ih;
-    }
-}
-
-// Exact helix step to the plane x1 with the analytic Jacobian.  sin(phi) is linear in x;
-// y follows the chord at the mean angle; z follows the arc length chord*asin(h)/h with
-// h = kappa*chord/2.  Fails (state unchanged) when |sin(phi)| would reach sinphi_max.
-__device__ bool trk_propagate(Trk& t, double x1, const DevParams& P)
-{
-    const double dx = x1 - t.x;
-    const double s0 = t.p[2];
-    const double tl = t.p[3];
-    const double kap = P.a * t.p[4];
-    const double s1 = s0 + kap * dx;
-    if (!(fabs(s0) < P.sinphi_max) || !(fabs(s1) < P.sinphi_max)) return false;
-    // cos(phi) at both ends and their reciprocals from one reciprocal square root each
-    const double u0 = (1.0 - s0) * (1.0 + s0), u1 = (1.0 - s1) * (1.0 + s1);
-    const double ic0 = rsqrt(u0), ic1 = rsqrt(u1);
-    const double c0 = u0 * ic0, c1 = u1 * ic1;
-    const double ics = 1.0 / (c0 + c1);
-    const double tb = (s0 + s1) * ics;
-    const double sec2 = 1.0 + tb * tb;
-    const double sec = sqrt(sec2);
-    const double chord = dx * sec;
-    const double h = 0.5 * kap * chord;
-    if (!(fabs(h) < 1.0)) return false;
-    double A, Ap;
-    arc_factor(h, A, Ap);
-    const double ds = chord * A;
-    const double q = 0.5 * tb * dx * ic1;
-    const double j02 = 0.5 * dx * sec2 * (ic0 + ic1);
-    const double j04 = P.a * (0.5 * dx * dx * sec2 * ic1);
-    const double j12 = tl * (dx * (s0 + s1) * ic0 * ic1 * ics);
-    const double j13 = ds;
-    const double j14 = tl * P.a * (chord * (q * A + Ap * (0.5 * chord) * (1.0 + kap * q)));
-    const double j24 = P.a * dx;
-
-    t.p[0] += dx * tb;
-    t.p[1] += tl * ds;
-    t.p[2] = s1;
-    t.x = x1;
-
-    // C <- J C J^T with J = identity + {j02, j04, j12, j13, j14, j24}
-    double* c = t.c;
-    const double c00 = c[0], c10 = c[1], c11 = c[2], c20 = c[3], c21 = c[4], c22 = c[5];
-    const double c30 = c[6], c31 = c[7], c32 = c[8], c33 = c[9];
-    const double c40 = c[10], c41 = c[11], c42 = c[12], c43 = c[13], c44 = c[14];
-    // rows of A = J C (A_ij for all i, j)
-    const double a00 = c00 + j02 * c20 + j04 * c40, a01 = c10 + j02 * c21 + j04 * c41;
-    const double a02 = c20 + j02 * c22 + j04 * c42, a03 = c30 + j02 * c32 + j04 * c43;
-    const double a04 = c40 + j02 * c42 + j04 * c44;
-    const double a10 = c10 + j12 * c20 + j13 * c30 + j14 * c40;
-    const double a11 = c11 + j12 * c21 + j13 * c31 + j14 * c41;
-    const double a12 = c21 + j12 * c22 + j13 * c32 + j14 * c42;
-    const double a13 = c31 + j12 * c32 + j13 * c33 + j14 * c43;
-    const double a14 = c41 + j12 * c42 + j13 * c43 + j14 * c44;
-    const double a20 = c20 + j24 * c40, a21 = c21 + j24 * c41, a22 = c22 + j24 * c42;
-    const double a23 = c32 + j24 * c43, a24 = c42 + j24 * c44;
-    // C' = A J^T (lower triangle); rows 3 and 4 of A equal those of C
-    c[0] = a00 + j02 * a02 + j04 * a04;
-    c[1] = a10 + j02 * a12 + j04 * a14;
-    c[2] = a11 + j12 * a12 + j13 * a13 + j14 * a14;
-    c[3] = a20 + j02 * a22 + j04 * a24;
-    c[4] = a21 + j12 * a22 + j13 * a23 + j14 * a24;
-    c[5] = a22 + j24 * a24;
-    c[6] = c30 + j02 * c32 + j04 * c43;
-    c[7] = c31 + j12 * c32 + j13 * c33 + j14 * c43;
-    c[8] = c32 + j24 * c43;
-    c[9] = c33;
-    c[10] = c40 + j02 * c42 + j04 * c44;
-    c[11] = c41 + j12 * c42 + j13 * c43 + j14 * c44;
-    c[12] = c42 + j24 * c44;
-    c[13] = c43;
-    c[14] = c44;
-    return true;
-}
-
-__device__ __forceinline__ double trk_chi2(const Trk& t, double my, double mz, const DevParams& P)
-{
-    const double r0 = my - t.p[0], r1 = mz - t.p[1];
-    const double s00 = t.c[0] + P.sy2, s01 = t.c[1], s11 = t.c[2] + P.sz2;
-    return (r0 * r0 * s11 - 2.0 * r0 * r1 * s01 + r1 * r1 * s00) / (s00 * s11 - s01 * s01);
-}
-
-// Kalman update with the cluster (my, mz), R = diag(sy2, sz2).
-__device__ void trk_update(Trk& t, double my, double mz, const DevParams& P)
-{
-    const double r0 = my - t.p[0], r1 = mz - t.p[1];
-    double* c = t.c;
-    const double s00 = c[0] + P.sy2, s01 = c[1], s11 = c[2] + P.sz2;
-    const double idet = 1.0 / (s00 * s11 - s01 * s01);
-    const double i00 = s11 * idet, i01 = -s01 * idet, i11 = s00 * idet;
-    const double h0[5] = {c[0], c[1], c[3], c[6], c[10]};
-    const double h1[5] = {c[1], c[2], c[4], c[7], c[11]};
-    double k0[5], k1[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        k0[i] = h0[i] * i00 + h1[i] * i01;
-        k1[i] = h0[i] * i01 + h1[i] * i11;
-        t.p[i] += k0[i] * r0 + k1[i] * r1;
-    }
-    int k = 0;
-#pragma unroll
-    for (int i = 0; i < 5; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j, ++k) c[k] -= k0[i] * h0[j] + k1[i] * h1[j];
-}
-
-__device__ __forceinline__ void trk_reset_cov(Trk& t, const DevParams& P)
-{
-#pragma unroll
-    for (int i = 0; i < 15; ++i) t.c[i] = 0.0;
-    t.c[0] = P.c0[0]; t.c[2] = P.c0[1]; t.c[5] = P.c0[2]; t.c[9] = P.c0[3]; t.c[14] = P.c0[4];
-}
-
-// Circle through three (x, y) points, traversed in order: curvature and sin(phi) at the
-// first; tan(lambda) from the z change over the arc to the last.
-__device__ bool trk_seed(Trk& t, const double* x, const double* y, const double* z, const DevParams& P)
-{
-    const double ax = x[1] - x[0], ay = y[1] - y[0];
-    const double bx = x[2] - x[1], by = y[2] - y[1];
-    const double ex = x[2] - x[0], ey = y[2] - y[0];
-    const double la = sqrt(ax * ax + ay * ay), lb = sqrt(bx * bx + by * by), lc = sqrt(ex * ex + ey * ey);
-    const double den = la * lb * lc;
-    if (!(den > 0.0)) return false;
-    const double kap = 2.0 * (ax * by - ay * bx) / den;
-    const double h = 0.5 * kap * lc;
-    if (!(fabs(h) < 1.0)) return false;
-    double A, Ap;
-    arc_factor(h, A, Ap);
-    const double il = 1.0 / lc;
-    t.x = x[0];
-    t.p[0] = y[0];
-    t.p[1] = z[0];
-    t.p[2] = ey * il * sqrt((1.0 - h) * (1.0 + h)) - ex * il * h;
-    t.p[3] = (z[2] - z[0]) / (lc * A);
-    t.p[4] = (P.a != 0.0) ? kap / P.a : 0.0;
-    return true;
-}
-
-// z at the beam line: the helix of state p at plane x0 followed to its point of closest
-// approach to the beam axis (the origin of the sector frame) in the transverse plane,
-// along the shorter arc; z there.  For a primary from a vertex at the origin this is the
-// most likely z of the track's origin (its drift offset in a time frame).
-__device__ double trk_beamline_z(const DevParams& P, double x0, const double* p)
-{
-    const double y0 = p[0], z0 = p[1], s0 = p[2], tl = p[3];
-    const double c0 = sqrt((1.0 - s0) * (1.0 + s0));
-    const double kap = P.a * p[4];
-    double s;
-    if (kap == 0.0) {
-        s = -(x0 * c0 + y0 * s0);
-    } else {
-        const double xc = x0 - s0 / kap, yc = y0 + c0 / kap;   // circle centre
-        const double d = sqrt(xc * xc + yc * yc);
-        if (!(d > 0.0)) return z0;
-        const double sg = kap > 0.0 ? 1.0 : -1.0;
-        const double sd = -sg * xc / d, cd = sg * yc / d;       // direction at the closest point
-        s = atan2(sd * c0 - cd * s0, cd * c0 + sd * s0) / kap;
-    }
-    return z0 + tl * s;
+    run_scan(job, s);
 }
 
 // Least-chi2 cluster of row g (row record rf, ri) inside the follow window: its sorted
@@ -1703,6 +1507,10 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
             trk_update(tr, (double)e.x, (double)e.y, P);
             ++nupd;
         }
+        if (ok && B.f_pout) {
+            for (int q = 0; q < 5; ++q) B.f_pout[i * 5 + q] = tr.p[q];
+            for (int q = 0; q < 15; ++q) B.f_cout[i * 15 + q] = tr.c[q];
+        }
         if (ok) trk_reset_cov(tr, P);
         // inward from the last kept cluster, summing chi2 before each update
         double chi2 = 0.0;
@@ -1745,8 +1553,8 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 
 // ------------------------------------------------------------------------------------
 // Stage 8, emit: tracks at their scanned positions (rank order), hits inner to outer as
-// input cluster indices (from the kept list), and each track's z at the beam line.  Writes beyond the caller's capacity are
-// dropped and flagged.
+// input cluster indices (from the kept list), each track's z at the beam line and, on
+// request, its outer state.  Writes beyond the caller's capacity are dropped and flagged.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
 {
@@ -1785,6 +1593,10 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
                     B.o_hit_off[T + 1] = hp + nk;
                     B.trk_out[rank] = (int32_t)T;
                     if (B.o_zbeam) B.o_zbeam[T] = trk_beamline_z(P, B.f_xref[i], B.f_par + i * 5);
+                    if (B.o_par_out) {
+                        for (int q = 0; q < 5; ++q) B.o_par_out[T * 5 + q] = B.f_pout[i * 5 + q];
+                        for (int q = 0; q < 15; ++q) B.o_cov_out[T * 15 + q] = B.f_cout[i * 15 + q];
+                    }
                     src = B.cand_off[p];
                 }
             }

@@ -244,7 +244,7 @@ tpcsf_status tpcsf_server_submit(tpcsf_server* s, const float* y, const float* z
     f.row_offsets = sl.d_off;
     f.row_offsets_host = sl.h_off.data();
     const int64_t T = cap_tracks_for(sl.cap, s->params.min_track_hits);
-    tpcsf_tracks o;
+    tpcsf_tracks o{};
     o.cap_tracks = T;
     o.cap_hits = sl.cap;
     o.n_tracks = sl.d_n; o.n_hits = sl.d_n + 1;

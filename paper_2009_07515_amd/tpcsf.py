@@ -36,7 +36,8 @@ class Params(C.Structure):
     _fields_ = [("win_y", C.c_float), ("win_z", C.c_float), ("kink_max", C.c_float),
                 ("sigma_y", C.c_double), ("sigma_z", C.c_double), ("chi2_max", C.c_double),
                 ("sinphi_max", C.c_double), ("nsig", C.c_double), ("c0", C.c_double * 5),
-                ("min_chain", C.c_int32), ("min_track_hits", C.c_int32), ("max_miss", C.c_int32)]
+                ("min_chain", C.c_int32), ("min_track_hits", C.c_int32), ("max_miss", C.c_int32),
+                ("merge_edge", C.c_double), ("merge_window", C.c_double), ("merge_chi2", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -62,7 +63,16 @@ class TracksDesc(C.Structure):
                 ("n_hits", C.c_void_p), ("params", C.c_void_p), ("cov", C.c_void_p), ("x_ref", C.c_void_p),
                 ("chi2", C.c_void_p), ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p),
                 ("tf", C.c_void_p), ("hit_off", C.c_void_p), ("hit_ids", C.c_void_p),
-                ("cluster_track", C.c_void_p), ("z_beam", C.c_void_p)]
+                ("cluster_track", C.c_void_p), ("z_beam", C.c_void_p), ("params_outer", C.c_void_p),
+                ("cov_outer", C.c_void_p)]
+
+
+class MergedDesc(C.Structure):
+    _fields_ = [("cap_merged", C.c_int64), ("cap_hits", C.c_int64), ("n_merged", C.c_void_p),
+                ("n_hits", C.c_void_p)] + [(k, C.c_void_p) for k in
+                                           ("params", "cov", "x_ref", "chi2", "z_beam", "ndf", "nhits", "sector",
+                                            "tf", "n_segments", "hit_off", "hit_ids", "track_merged", "next",
+                                            "link_chi2")]
 
 
 class HostTracks(C.Structure):
@@ -109,6 +119,10 @@ def load():
     for fn in ("tpcsf_track_plain", "tpcsf_track_batch"):
         getattr(lib, fn).argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), vp]
         getattr(lib, fn).restype = C.c_int
+    lib.tpcsf_merge.argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), C.POINTER(MergedDesc), vp]
+    lib.tpcsf_merge.restype = C.c_int
+    lib.tpcsf_merge_work.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.tpcsf_merge_work.restype = C.c_int
     lib.tpcsf_sync.argtypes = [vp, vp]
     lib.tpcsf_sync.restype = C.c_int
     lib.tpcsf_debug.argtypes = [vp, C.POINTER(DebugView)]
@@ -207,7 +221,8 @@ class TrackBuffers:
     """Caller-owned output buffers (device).  Default capacities are exact upper bounds:
     a track keeps >= min_track_hits clusters and no cluster is in two tracks."""
 
-    def __init__(self, n_clusters, cap_tracks=None, cap_hits=None, min_track_hits=20, device="cuda"):
+    def __init__(self, n_clusters, cap_tracks=None, cap_hits=None, min_track_hits=20, device="cuda",
+                 outer=False):
         import torch
         n = int(n_clusters)
         self.cap_tracks = int(cap_tracks if cap_tracks is not None else n // max(1, min_track_hits) + 1)
@@ -228,6 +243,9 @@ class TrackBuffers:
         self.hit_ids = torch.empty(max(H, 1), dtype=torch.int32, **kw)
         self.cluster_track = torch.empty(max(n, 1), dtype=torch.int32, **kw)
         self.z_beam = torch.empty(max(T, 1), dtype=torch.float64, **kw)
+        # outer states (input of the merge) only on request
+        self.params_outer = torch.empty((max(T, 1), 5), dtype=torch.float64, **kw) if outer else None
+        self.cov_outer = torch.empty((max(T, 1), 15), dtype=torch.float64, **kw) if outer else None
 
     def desc(self):
         d = TracksDesc()
@@ -235,6 +253,8 @@ class TrackBuffers:
         for k in ("n_tracks", "n_hits", "params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector", "tf",
                   "hit_off", "hit_ids", "cluster_track", "z_beam"):
             setattr(d, k, _ptr(getattr(self, k)))
+        if self.params_outer is not None:
+            d.params_outer, d.cov_outer = _ptr(self.params_outer), _ptr(self.cov_outer)
         return d
 
     def result(self, n_clusters):
@@ -244,7 +264,57 @@ class TrackBuffers:
         return dict(n_tracks=T, n_hits=H, params=self.params[:T], cov=self.cov[:T], x_ref=self.x_ref[:T],
                     chi2=self.chi2[:T], ndf=self.ndf[:T], nhits=self.nhits[:T], sector=self.sector[:T],
                     tf=self.tf[:T], hit_off=self.hit_off[:T + 1], hit_ids=self.hit_ids[:H],
-                    cluster_track=self.cluster_track[:n_clusters], z_beam=self.z_beam[:T])
+                    cluster_track=self.cluster_track[:n_clusters], z_beam=self.z_beam[:T],
+                    **({} if self.params_outer is None else
+                       dict(params_outer=self.params_outer[:T], cov_outer=self.cov_outer[:T])))
+
+
+class MergedBuffers:
+    """Caller-owned output of the merge (device).  Default capacities hold every input
+    track as its own merged track."""
+
+    def __init__(self, tracks: "TrackBuffers", device="cuda"):
+        import torch
+        T, H = tracks.cap_tracks, tracks.cap_hits
+        self.cap_merged, self.cap_hits = T, H
+        kw = dict(device=device)
+        f64 = dict(dtype=torch.float64, **kw)
+        i32 = dict(dtype=torch.int32, **kw)
+        self.n_merged = torch.zeros(1, dtype=torch.int64, **kw)
+        self.n_hits = torch.zeros(1, dtype=torch.int64, **kw)
+        self.params = torch.empty((max(T, 1), 5), **f64)
+        self.cov = torch.empty((max(T, 1), 15), **f64)
+        self.x_ref = torch.empty(max(T, 1), **f64)
+        self.chi2 = torch.empty(max(T, 1), **f64)
+        self.z_beam = torch.empty(max(T, 1), **f64)
+        self.ndf = torch.empty(max(T, 1), **i32)
+        self.nhits = torch.empty(max(T, 1), **i32)
+        self.sector = torch.empty(max(T, 1), **i32)
+        self.tf = torch.empty(max(T, 1), **i32)
+        self.n_segments = torch.empty(max(T, 1), **i32)
+        self.hit_off = torch.zeros(T + 1, dtype=torch.int64, **kw)
+        self.hit_ids = torch.empty(max(H, 1), **i32)
+        self.track_merged = torch.empty(max(T, 1), **i32)
+        self.next = torch.empty(max(T, 1), **i32)
+        self.link_chi2 = torch.empty(max(T, 1), **f64)
+
+    def desc(self):
+        d = MergedDesc()
+        d.cap_merged, d.cap_hits = self.cap_merged, self.cap_hits
+        for k, _ in MergedDesc._fields_[2:]:
+            setattr(d, k, _ptr(getattr(self, k)))
+        return d
+
+    def result(self, n_tracks):
+        """Slices holding the last merge's output (after a sync); n_tracks input tracks."""
+        M = int(self.n_merged.item())
+        H = int(self.n_hits.item())
+        out = {k: getattr(self, k)[:M] for k in ("params", "cov", "x_ref", "chi2", "z_beam", "ndf", "nhits",
+                                                  "sector", "tf", "n_segments")}
+        out.update(n_merged=M, n_hits=H, hit_off=self.hit_off[:M + 1], hit_ids=self.hit_ids[:H],
+                   track_merged=self.track_merged[:n_tracks], next=self.next[:n_tracks],
+                   link_chi2=self.link_chi2[:n_tracks])
+        return out
 
 
 class Tracker:
@@ -320,6 +390,25 @@ class Tracker:
         self.launch(frame, out, mode, stream)
         self.sync(stream)
         return out.result(frame.n_clusters)
+
+    def launch_merge(self, frame: DeviceFrame, tracks: TrackBuffers, out: "MergedBuffers", stream=None):
+        """Enqueue the merge of a batch's sector tracks (no sync)."""
+        fd, td, md = frame.desc(), tracks.desc(), out.desc()
+        self._check(self.lib.tpcsf_merge(self.h, C.byref(fd), C.byref(td), C.byref(md), self._stream(stream)))
+
+    def merge(self, frame: DeviceFrame, tracks: TrackBuffers, out=None, stream=None):
+        """Merge the sector tracks of the last tracking call on `frame` (held in `tracks`,
+        made with outer=True) across sector edges and refit; returns the merged tracks."""
+        if out is None:
+            out = MergedBuffers(tracks)
+        self.launch_merge(frame, tracks, out, stream)
+        self.sync(stream)
+        return out.result(int(tracks.n_tracks.item()))
+
+    def merge_work(self):
+        w = (C.c_int64 * 6)()
+        self._check(self.lib.tpcsf_merge_work(self.h, w))
+        return np.array(list(w), np.int64)
 
     def reserve(self, max_clusters, max_tf=1):
         """Fix the scratch layout to this capacity (one graph then serves smaller batches)."""
