@@ -262,6 +262,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the serving run (Poisson arrivals at 80%% of capacity); 0 skips it")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--merge-steps", type=int, default=20,
+                    help="timed calls of the merge across sector edges (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for byte-counter calibration)")
     args = ap.parse_args()
@@ -386,6 +388,35 @@ def main():
     kalman = {k: {"TFLOPs": sf[k] / (stages[k] * 1e-3) / 1e12, "frac_fp64_peak": sf[k] / (stages[k] * 1e-3) / 1e12
                   / FP64_PEAK_TFS} for k in sf}
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+    trk.set_stage_timing(False)
+
+    # merging across sector edges and refit across sector frames (the stage after sector
+    # tracking): timed calls on this frame's sector tracks, tracked with the outer states
+    # the merge needs.  Not part of the step above.
+    merge = None
+    if args.merge_steps > 0:
+        tb = tpcsf.TrackBuffers(N, outer=True)
+        trk.track(frame, out=tb)
+        mb = tpcsf.MergedBuffers(tb)
+        mres = trk.merge(frame, tb, out=mb)
+        M = mres["n_merged"]
+        n_multi = int((mres["n_segments"] >= 2).sum().item())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.merge_steps):
+            trk.launch_merge(frame, tb, mb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        trk.sync()
+        m_ms = e0.elapsed_time(e1) / args.merge_steps
+        assert int(mb.n_merged.item()) == M
+        w = trk.merge_work()
+        merge = {"ms_per_call": m_ms, "calls": args.merge_steps, "sector_tracks": T0, "merged_tracks": M,
+                 "merged_of_several": n_multi, "tracks_per_s": T0 / (m_ms * 1e-3),
+                 "work": {"gate_pairs": int(w[0]), "match_propagations": int(w[1]), "match_chi2": int(w[2]),
+                          "fit_rotations": int(w[3]), "fit_propagations": int(w[4]), "fit_updates": int(w[5])}}
+        log(f"merge: {T0} sector tracks -> {M} ({n_multi} of several) in {m_ms:.3f} ms")
 
     line = {
         "metric": METRIC,
@@ -410,6 +441,7 @@ def main():
         "counts": cnt,
         "roofline": roofline,
         "kalman_stages": kalman,
+        "merge": merge,
         "path_hbm": {"bytes_per_cluster": path_bytes / N,
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
                      "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

@@ -464,7 +464,7 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     char* a = (char*)c->marena;
     MergeBatch M{};
     M.y = f->y; M.z = f->z; M.off = f->row_offsets;
-    M.n_tracks = t->n_tracks; M.cap_tracks = t->cap_tracks;
+    M.n_tracks = t->n_tracks; M.cap_tracks = t->cap_tracks; M.cap_in_hits = t->cap_hits;
     M.hit_off = t->hit_off; M.hit_ids = t->hit_ids;
     M.par = t->params; M.cov = t->cov; M.xref = t->x_ref; M.chi2 = t->chi2;
     M.sector = t->sector; M.tf = t->tf;

@@ -187,7 +187,7 @@ struct MergeCounters {
 struct MergeBatch {
     // inputs: the frame's clusters and the sector tracks with their outer states
     const float* y; const float* z; const int64_t* off;
-    const int64_t* n_tracks; int64_t cap_tracks;
+    const int64_t* n_tracks; int64_t cap_tracks, cap_in_hits;
     const int64_t* hit_off; const int32_t* hit_ids;
     const double* par; const double* cov; const double* xref; const double* chi2;
     const int32_t* sector; const int32_t* tf;

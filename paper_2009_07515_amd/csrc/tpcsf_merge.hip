@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_ends(MergeBatch M, DevParam
         if (valid && t > 0 && (int64_t)M.tf[t - 1] * ns + M.sector[t - 1] > key) valid = false;
         const int64_t g0 = key * nr;
         const int64_t hb = M.hit_off[t], he = M.hit_off[t + 1];
-        if (!(he - hb >= 3)) valid = false;
+        if (!(hb >= 0 && he - hb >= 3 && he <= M.cap_in_hits)) valid = false;
         for (int64_t j = hb; valid && j < he; ++j) {
             const int64_t h = M.hit_ids[j];
             valid = h >= M.off[g0] && h < M.off[g0 + nr];
@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_fit(MergeBatch M, DevParams
             int frame = s0;
             int32_t u = t;
             bool first = true;
-            while (ok && u >= 0) {
+            for (int seg = 0; ok && u >= 0 && seg < M.nseg[t]; ++seg) {
                 const int su = M.sector[u];
                 const int64_t g0 = (tfb + su) * nr;
                 if (su != frame) {
@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_fit(MergeBatch M, DevParams
                 trk_reset_cov(tr, P);
                 u = last;
                 bool lastc = true;
-                while (ok && u >= 0) {
+                for (int seg = 0; ok && u >= 0 && seg < M.nseg[t]; ++seg) {
                     const int su = M.sector[u];
                     const int64_t g0 = (tfb + su) * nr;
                     if (su != frame) {
@@ -441,7 +441,8 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_fit(MergeBatch M, DevParams
             ms[20] = chi2;
             M.fit_ok[t] = 1;
         } else {
-            for (int32_t u = t; u >= 0; u = M.next[u]) M.diss[u] = 1;
+            int32_t u = t;
+            for (int seg = 0; u >= 0 && seg < M.nseg[t]; ++seg, u = M.next[u]) M.diss[u] = 1;
         }
     }
     wave_add(&M.mc->work[3], n_rot);
@@ -508,7 +509,9 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_emit(MergeBatch M, DevParam
         M.o_tf[m] = M.tf[t];
         M.o_hit_off[m + 1] = hp + nh;
         int64_t k = hp;
-        for (int32_t u = (int32_t)t; u >= 0; u = whole ? M.next[u] : -1) {
+        const int32_t nseg = whole ? M.nseg[t] : 1;
+        int32_t u = (int32_t)t;
+        for (int seg = 0; u >= 0 && seg < nseg; ++seg, u = M.next[u]) {
             M.o_track_merged[u] = (int32_t)m;
             for (int64_t j = M.hit_off[u]; j < M.hit_off[u + 1]; ++j) M.o_hit_ids[k++] = M.hit_ids[j];
         }
