@@ -1085,7 +1085,9 @@ int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
         for (int i = 0; i < 5; ++i) A0.p[i] = (orc_real)trk->params_outer[a * 5 + i];
         for (int i = 0; i < 15; ++i) A0.C[i] = (orc_real)trk->cov_outer[a * 15 + i];
         if (krotate(cfg, &A0, frame_delta(cfg, sa, sb), NULL) != 0) continue;
+        /* slopes of the linear prediction: tan phi' and tan(lambda) / cos phi' */
         const orc_real c1 = R_SQRT(1 - A0.p[2] * A0.p[2]);
+        const orc_real ty = A0.p[2] / c1, tz = A0.p[3] / c1;
         for (int64_t j = sec_start[sb]; j < sec_start[sb + 1]; ++j) {
             const int64_t b = sec_list[j];
             if (up ? !(yi[b] < 0) : !(yi[b] >= 0)) continue;
@@ -1093,8 +1095,8 @@ int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
             if (!(xi[b] * xi[b] + yi[b] * yi[b] > ro2)) continue;
             const double* pb = trk->params + b * 5;
             const orc_real dx = (orc_real)xi[b] - A0.x;
-            const orc_real ylin = A0.p[0] + dx * A0.p[2] / c1;
-            const orc_real zlin = A0.p[1] + dx * A0.p[3] / c1;
+            const orc_real ylin = A0.p[0] + dx * ty;
+            const orc_real zlin = A0.p[1] + dx * tz;
             if (!(R_FABS(ylin - (orc_real)pb[0]) <= (orc_real)W && R_FABS(zlin - (orc_real)pb[1]) <= (orc_real)W))
                 continue;
             kstate A1 = A0;

@@ -373,11 +373,12 @@ void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t
 // Scratch of one merge call: T = input track capacity, K = n_tf * n_sectors.
 struct MergeLayout {
     size_t total = 0;
-    size_t ends, a_list, b_list, sec_first, cnt, brec, bidx, mstate, bestB, bestChi, keepChi, keepA;
-    size_t next, prev, nseg, chain_hits, fit_ok, diss, lead, nh, fit_list, m_idx, m_hpos, scan_part;
+    size_t ends, a_list, b_list, sec_first, cnt, brec, bidx, brec_s, bidx_s, zs, lsorted, mstate, bestB, bestChi,
+        keepChi, keepA;
+    size_t next, prev, nseg, chain_hits, fit_ok, diss, lead, nh, fit_list, fit_off, grec, m_idx, m_hpos, scan_part;
 };
 
-MergeLayout make_merge_layout(int64_t T, int64_t K)
+MergeLayout make_merge_layout(int64_t T, int64_t K, int64_t H)
 {
     MergeLayout L;
     size_t o = 0;
@@ -390,6 +391,10 @@ MergeLayout make_merge_layout(int64_t T, int64_t K)
     L.cnt = take(2 * k * 4);
     L.brec = take(2 * t * 32);
     L.bidx = take(2 * t * 4);
+    L.brec_s = take(2 * t * 32);
+    L.bidx_s = take(2 * t * 4);
+    L.zs = take(2 * t * 4);
+    L.lsorted = take(2 * k * 4);
     L.mstate = take(t * 21 * 8);
     L.bestB = take(t * 4);
     L.bestChi = take(t * 8);
@@ -404,6 +409,8 @@ MergeLayout make_merge_layout(int64_t T, int64_t K)
     L.lead = take(t * 4);
     L.nh = take(t * 4);
     L.fit_list = take(t * 4);
+    L.fit_off = take(t * 8);
+    L.grec = take((size_t)(H > 0 ? H : 1) * 16);
     L.m_idx = take(t * 8);
     L.m_hpos = take(t * 8);
     L.scan_part = take((4 * kScanBlocks + 2) * 8);
@@ -440,7 +447,7 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     if (o->cap_hits > 0 && !o->hit_ids) return fail(c, TPCSF_E_INVALID, "merged hit array missing");
     if (t->cap_tracks > 0 && !o->track_merged) return fail(c, TPCSF_E_INVALID, "track_merged missing");
     const int64_t K = (int64_t)f->n_tf * c->n_sectors;
-    const MergeLayout L = make_merge_layout(t->cap_tracks, K);
+    const MergeLayout L = make_merge_layout(t->cap_tracks, K, t->cap_hits);
     hipError_t e;
     if (c->marena_size < L.total) {
         if (c->budget && c->arena_size + L.total > c->budget)
@@ -477,6 +484,10 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     M.cnt = (int32_t*)(a + L.cnt);
     M.brec = (double4*)(a + L.brec);
     M.bidx = (int32_t*)(a + L.bidx);
+    M.brec_s = (double4*)(a + L.brec_s);
+    M.bidx_s = (int32_t*)(a + L.bidx_s);
+    M.zs = (float*)(a + L.zs);
+    M.lsorted = (int32_t*)(a + L.lsorted);
     M.mstate = (double*)(a + L.mstate);
     M.bestB = (int32_t*)(a + L.bestB);
     M.bestChi = (double*)(a + L.bestChi);
@@ -491,6 +502,8 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     M.lead = (int32_t*)(a + L.lead);
     M.nh = (int32_t*)(a + L.nh);
     M.fit_list = (int32_t*)(a + L.fit_list);
+    M.fit_off = (int64_t*)(a + L.fit_off);
+    M.grec = (float4*)(a + L.grec);
     M.m_idx = (int64_t*)(a + L.m_idx);
     M.m_hpos = (int64_t*)(a + L.m_hpos);
     M.scan_part = (int64_t*)(a + L.scan_part);

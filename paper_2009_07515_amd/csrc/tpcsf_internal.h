@@ -178,6 +178,7 @@ struct MergeCounters {
     int64_t T;                      // input tracks (min(n_tracks, cap_tracks))
     int32_t n_fit;                  // chains of several segments
     int32_t bad;                    // invalid input seen: nothing is merged
+    unsigned long long fit_hits;    // clusters of those chains (gather offsets)
     // algorithmic work: candidate pairs through the gate, their propagations (attempts),
     // chi2 evaluations; merged-fit rotations, propagations, updates
     int64_t work[6];
@@ -201,6 +202,10 @@ struct MergeBatch {
     int32_t* cnt;                   // [2K] entries per list (list = key * 2 + edge)
     double4* brec;                  // [2T] entries: x_in, radius^2 of the inner cluster, y, z
     int32_t* bidx;                  // [2T] their tracks
+    double4* brec_s;                // [2T] the same, each list ordered by z
+    int32_t* bidx_s;                // [2T]
+    float* zs;                      // [2T] z of the ordered entries (binary32)
+    int32_t* lsorted;               // [2K] 1 if the list is ordered by z (short enough)
     double* mstate;                 // [T][21] rotated outer state (x, p, C); later the
                                     //     merged fit of a chain head (p, C, chi2)
     int32_t* bestB; double* bestChi;
@@ -210,6 +215,9 @@ struct MergeBatch {
     int32_t* nseg; int32_t* chain_hits; int32_t* fit_ok; int32_t* diss;
     int32_t* lead; int32_t* nh;     // scan inputs
     int32_t* fit_list;
+    int64_t* fit_off;               // [T] first gathered record of a chain head
+    float4* grec;                   // [input cap_hits] clusters of the chains to refit, in
+                                    //     chain order: y, z, row plane x, sector (as bits)
     int64_t* m_idx; int64_t* m_hpos;
     int64_t* scan_part;
     MergeCounters* mc;

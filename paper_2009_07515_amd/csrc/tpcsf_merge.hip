@@ -55,6 +55,14 @@ __device__ __forceinline__ int row_of(const int64_t* off, int64_t g0, int nr, in
     return lo;
 }
 
+// orders the LDS accesses of the lanes of one wave (no block barrier)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // azimuth step index between two sectors of one side, d in (-S/2, S/2], as a table index
 __device__ __forceinline__ int step_index(int s0, int s1, int S)
 {
@@ -111,6 +119,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_init(MergeBatch M, int64_t 
         M.mc->T = T;
         M.mc->n_fit = 0;
         M.mc->bad = 0;
+        M.mc->fit_hits = 0;
         for (int k = 0; k < 6; ++k) M.mc->work[k] = 0;
     }
     for (int64_t i = i0; i < M.cap_tracks; i += stride) {
@@ -129,36 +138,60 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_init(MergeBatch M, int64_t 
 }
 
 // ------------------------------------------------------------------------------------
-// 1: track ends (cluster coordinates), first track of each sector, outer ends rotated
-// into the neighbouring sector's frame, list membership
+// 1: input checks, track ends (cluster coordinates), first track of each sector, outer
+// ends rotated into the neighbouring sector's frame, list membership.  The input must be
+// tracks of this batch in (time frame, sector) order, each with >= 3 clusters of its own
+// sector; otherwise nothing is merged (invalid input).  A wave checks its 64 tracks' hit
+// lists together, 64 clusters per pass.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kMergeThreads) k_m_ends(MergeBatch M, DevParams P, MergeParams Q)
 {
 #pragma clang fp contract(off)
     const int64_t T = M.mc->T;
     const int nr = P.n_rows, ns = P.n_sectors, S = Q.S;
+    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += stride) {
-        const int s = M.sector[t], f = M.tf[t];
-        // the input must be tracks of this batch in (time frame, sector) order, each with
-        // >= 3 clusters of its own sector: otherwise nothing is merged (invalid input)
-        bool valid = s >= 0 && s < ns && f >= 0 && f < M.n_tf;
-        const int64_t key = (int64_t)f * ns + s;
-        if (valid && t > 0 && (int64_t)M.tf[t - 1] * ns + M.sector[t - 1] > key) valid = false;
-        const int64_t g0 = key * nr;
-        const int64_t hb = M.hit_off[t], he = M.hit_off[t + 1];
-        if (!(hb >= 0 && he - hb >= 3 && he <= M.cap_in_hits)) valid = false;
-        for (int64_t j = hb; valid && j < he; ++j) {
-            const int64_t h = M.hit_ids[j];
-            valid = h >= M.off[g0] && h < M.off[g0 + nr];
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < T; t0 += stride) {
+        const int64_t t = t0 + lane;
+        bool valid = t < T;
+        int s = 0, f = 0;
+        int64_t key = 0, hb = 0, he = 0, lo = 0, hi = 0;
+        if (valid) {
+            s = M.sector[t];
+            f = M.tf[t];
+            valid = s >= 0 && s < ns && f >= 0 && f < M.n_tf;
+            key = (int64_t)f * ns + s;
+            if (valid && t > 0 && (int64_t)M.tf[t - 1] * ns + M.sector[t - 1] > key) valid = false;
+            hb = M.hit_off[t];
+            he = M.hit_off[t + 1];
+            if (!(hb >= 0 && he - hb >= 3 && he <= M.cap_in_hits)) valid = false;
+            if (valid) {
+                lo = M.off[key * nr];
+                hi = M.off[key * nr + nr];
+            }
         }
-        if (!valid) {
+        // every cluster inside the track's own sector
+        uint64_t todo = __ballot(valid);
+        while (todo) {
+            const int l = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1ull;
+            const int64_t b0 = __shfl(hb, l, 64), b1 = __shfl(he, l, 64);
+            const int64_t c0 = __shfl(lo, l, 64), c1 = __shfl(hi, l, 64);
+            bool out = false;
+            for (int64_t j = b0 + lane; j < b1; j += 64) {
+                const int64_t h = M.hit_ids[j];
+                out = out || h < c0 || h >= c1;
+            }
+            if (__ballot(out) != 0ull && lane == l) valid = false;
+        }
+        if (t < T && !valid) {
             atomicOr(&M.mc->bad, 1);
             atomicOr(&M.ctr->err, kErrInvalid);
-            continue;
         }
+        if (!valid) continue;
         if (t == 0 || (int64_t)M.tf[t - 1] * ns + M.sector[t - 1] != key) M.sec_first[key] = (int32_t)t;
-        const int64_t hi_ = M.hit_ids[M.hit_off[t]], ho = M.hit_ids[M.hit_off[t + 1] - 1];
+        const int64_t g0 = key * nr;
+        const int64_t hi_ = M.hit_ids[hb], ho = M.hit_ids[he - 1];
         const float xi = P.rx[row_of(M.off, g0, nr, hi_)], yi = M.y[hi_];
         const float xo = P.rx[row_of(M.off, g0, nr, ho)], yo = M.y[ho];
         M.ends[t] = make_float4(xi, yi, xo, yo);
@@ -184,22 +217,99 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_ends(MergeBatch M, DevParam
 
 // ------------------------------------------------------------------------------------
 // 2: inner ends into their lists (order inside a list is free: every decision below
-// breaks ties on track indices)
+// breaks ties on track indices).  Neighbouring tracks share lists, so a wave takes the
+// positions of each of its lists with one atomic.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kMergeThreads) k_m_lists(MergeBatch M)
 {
     if (M.mc->bad) return;
     const int64_t T = M.mc->T;
+    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += stride) {
-        const int32_t L = M.b_list[t];
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < T; t0 += stride) {
+        const int64_t t = t0 + lane;
+        const int32_t L = t < T ? M.b_list[t] : -1;
+        uint64_t todo = __ballot(L >= 0);
+        int32_t pos = 0;
+        while (todo) {
+            const int l = __ffsll((unsigned long long)todo) - 1;
+            const int32_t L0 = __shfl(L, l, 64);
+            const uint64_t same = __ballot(L == L0);
+            int32_t base = 0;
+            if (lane == l) base = atomicAdd(&M.cnt[L0], (int32_t)__popcll(same));
+            base = __shfl(base, l, 64);
+            if (L == L0) pos = base + (int32_t)__popcll(same & ((1ull << lane) - 1ull));
+            todo &= ~same;
+        }
         if (L < 0) continue;
-        const int32_t pos = atomicAdd(&M.cnt[L], 1);
         const int64_t at = (int64_t)(L & 1) * M.cap_tracks + M.sec_first[L >> 1] + pos;
         const float4 e = M.ends[t];
         const double xi = e.x, yi = e.y;
         M.brec[at] = make_double4(xi, xi * xi + yi * yi, M.par[t * 5 + 0], M.par[t * 5 + 1]);
         M.bidx[at] = (int32_t)t;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// 2b: each list ordered by z (binary32 keys), so that an outer end scans only the entries
+// its gate can accept; lists longer than kSortMax keep their order and are scanned whole
+// ------------------------------------------------------------------------------------
+constexpr int kSortMax = 8192;
+constexpr int kSortThreads = 1024;
+
+__device__ __forceinline__ uint32_t float_order_key(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_m_sort(MergeBatch M, int64_t n_lists)
+{
+    __shared__ unsigned long long keys[kSortMax];
+    if (M.mc->bad) return;
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int64_t L = blockIdx.x; L < n_lists; L += gridDim.x) {
+        const int32_t n = M.cnt[L];
+        if (n == 0) continue;
+        const int64_t base = (L & 1) * M.cap_tracks + M.sec_first[L >> 1];
+        if (n > kSortMax) {
+            for (int32_t j = t; j < n; j += nt) {
+                M.brec_s[base + j] = M.brec[base + j];
+                M.bidx_s[base + j] = M.bidx[base + j];
+                M.zs[base + j] = (float)M.brec[base + j].w;
+            }
+            if (t == 0) M.lsorted[L] = 0;
+            continue;
+        }
+        int np = 2;
+        while (np < n) np <<= 1;
+        for (int j = t; j < np; j += nt)
+            keys[j] = j < n ? ((unsigned long long)float_order_key((float)M.brec[base + j].w) << 32) | (uint32_t)j
+                            : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= np; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = t; i < np; i += nt) {
+                    const int o = i ^ j;
+                    if (o > i) {
+                        const unsigned long long a = keys[i], b = keys[o];
+                        if (((i & k) == 0) ? a > b : a < b) {
+                            keys[i] = b;
+                            keys[o] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int32_t j = t; j < n; j += nt) {
+            const int32_t src = (int32_t)(keys[j] & 0xFFFFFFFFull);
+            const double4 r = M.brec[base + src];
+            M.brec_s[base + j] = r;
+            M.bidx_s[base + j] = M.bidx[base + src];
+            M.zs[base + j] = (float)r.w;
+        }
+        if (t == 0) M.lsorted[L] = 1;
+        __syncthreads();
     }
 }
 
@@ -224,28 +334,49 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_match(MergeBatch M, DevPara
         for (int q = 0; q < 5; ++q) a.p[q] = ms[1 + q];
         for (int q = 0; q < 15; ++q) a.c[q] = ms[6 + q];
         const float4 e = M.ends[t];
-        double ro2, c1;
+        double ro2, ty, tz;
         {
 #pragma clang fp contract(off)
             const double xo = e.z, yo = e.w;
             ro2 = xo * xo + yo * yo;
-            c1 = sqrt(1.0 - a.p[2] * a.p[2]);
+            const double c1 = sqrt(1.0 - a.p[2] * a.p[2]);
+            ty = a.p[2] / c1;
+            tz = a.p[3] / c1;
+        }
+        int32_t j0 = 0, j1 = n;
+        if (M.lsorted[L]) {
+            // entries the gate can accept have z within W of z' + dx tz for some dx between
+            // the first and the last row; the binary32 keys get a margin of their rounding
+            const double za = a.p[1] + ((double)P.rx[0] - a.x) * tz;
+            const double zb = a.p[1] + ((double)P.rx[P.n_rows - 1] - a.x) * tz;
+            const double zlo = fmin(za, zb) - Q.window, zhi = fmax(za, zb) + Q.window;
+            const double marg = 1.0e-3 + 1.0e-6 * fmax(fabs(zlo), fabs(zhi));
+            const double qlo = zlo - marg, qhi = zhi + marg;
+            int32_t lo = 0, hi = n;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if ((double)M.zs[base + mid] < qlo) lo = mid + 1; else hi = mid;
+            }
+            j0 = lo;
+            int32_t e1 = j0;
+            while (e1 < n && (double)M.zs[base + e1] <= qhi) ++e1;
+            j1 = e1;
         }
         int32_t best = -1;
         double bestc = 0.0;
-        for (int32_t j = 0; j < n; ++j) {
-            const double4 r = M.brec[base + j];
+        for (int32_t j = j0; j < j1; ++j) {
+            const double4 r = M.brec_s[base + j];
             bool pass;
             {
 #pragma clang fp contract(off)
                 const double dx = r.x - a.x;
-                const double ylin = a.p[0] + dx * a.p[2] / c1;
-                const double zlin = a.p[1] + dx * a.p[3] / c1;
+                const double ylin = a.p[0] + dx * ty;
+                const double zlin = a.p[1] + dx * tz;
                 pass = r.y > ro2 && fabs(ylin - r.z) <= Q.window && fabs(zlin - r.w) <= Q.window;
             }
             if (!pass) continue;
             ++n_gate;
-            const int32_t b = M.bidx[base + j];
+            const int32_t b = M.bidx_s[base + j];
             Trk a1 = a;
             ++n_prop;
             if (!trk_propagate(a1, r.x, P)) continue;
@@ -313,51 +444,102 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_chain(MergeBatch M)
         if (u >= 0) atomicOr(&M.ctr->err, kErrMergeChain);
         M.nseg[t] = ns;
         M.chain_hits[t] = nh;
-        if (ns >= 2) M.fit_list[atomicAdd(&M.mc->n_fit, 1)] = (int32_t)t;
+        if (ns >= 2) {
+            M.fit_list[atomicAdd(&M.mc->n_fit, 1)] = (int32_t)t;
+            M.fit_off[t] = (int64_t)atomicAdd(&M.mc->fit_hits, (unsigned long long)nh);
+        }
     }
-}
-
-// k-th cluster of the chain from head t (k < its cluster count): index and segment
-__device__ __forceinline__ int64_t chain_hit(const MergeBatch& M, int32_t t, int32_t k, int32_t& seg)
-{
-    int32_t u = t;
-    for (;;) {
-        const int32_t n = (int32_t)(M.hit_off[u + 1] - M.hit_off[u]);
-        if (k < n) break;
-        k -= n;
-        u = M.next[u];
-    }
-    seg = u;
-    return M.hit_ids[M.hit_off[u] + k];
 }
 
 // ------------------------------------------------------------------------------------
-// 7: refit of each chain over all its clusters, across the sector frames: the final fit
+// 7a: the clusters of every chain to refit, in chain order, as records (y, z, row plane x,
+// sector); one wave per chain, 64 clusters per pass
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kMergeThreads) k_m_gather(MergeBatch M, DevParams P)
+{
+    if (M.mc->bad) return;
+    __shared__ int64_t offs[kMergeThreads / 64][kMaxRows + 1];
+    const int nr = P.n_rows, ns = P.n_sectors;
+    const int64_t nf = M.mc->n_fit;
+    const int lane = threadIdx.x & 63;
+    int64_t* o = offs[threadIdx.x >> 6];
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < nf; i += nw) {
+        const int32_t t = M.fit_list[i];
+        const int64_t tfb = (int64_t)M.tf[t] * ns;
+        int64_t k = M.fit_off[t];
+        int32_t u = t;
+        for (int seg = 0; u >= 0 && seg < M.nseg[t]; ++seg, u = M.next[u]) {
+            const int su = M.sector[u];
+            const int64_t g0 = (tfb + su) * nr;
+            // the sector's row offsets in this wave's LDS slot
+            wave_lds_sync();
+            for (int r = lane; r <= nr; r += 64) o[r] = M.off[g0 + r];
+            wave_lds_sync();
+            const int64_t hb = M.hit_off[u], n = M.hit_off[u + 1] - hb;
+            for (int64_t j = lane; j < n; j += 64) {
+                const int64_t h = M.hit_ids[hb + j];
+                M.grec[k + j] = make_float4(M.y[h], M.z[h], P.rx[row_of(o, 0, nr, h)], __int_as_float(su));
+            }
+            k += n;
+        }
+    }
+}
+
+// descending bitonic sort of 256 keys in LDS (all threads of the block call it)
+__device__ void sort_desc_256(uint32_t* key)
+{
+    const int t = threadIdx.x;
+    for (int k = 2; k <= 256; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int o = t ^ j;
+            if (o > t) {
+                const uint32_t a = key[t], b = key[o];
+                const bool desc = (t & k) == 0;
+                if (desc ? a < b : a > b) {
+                    key[t] = b;
+                    key[o] = a;
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// ------------------------------------------------------------------------------------
+// 7b: refit of each chain over all its clusters, across the sector frames: the final fit
 // (seed from the first, middle and last cluster in the first cluster's frame; outward
 // pass from C0; inward pass from C0 keeping the parameters), with the state rotated into
-// a cluster's frame before the step to its row.  A failure dissolves the chain.
+// a cluster's frame before the step to its row.  A failure dissolves the chain.  Blocks
+// take 256 chains and order them by length, so that a wave's lanes run similar lengths.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kMergeThreads) k_m_fit(MergeBatch M, DevParams P, MergeParams Q)
 {
+    __shared__ uint32_t key[kMergeThreads];
     if (M.mc->bad) return;
-    const int nr = P.n_rows, ns = P.n_sectors, S = Q.S;
+    const int S = Q.S;
     const int64_t nf = M.mc->n_fit;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t n_rot = 0, n_prop = 0, n_upd = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += stride) {
+    for (int64_t ch = blockIdx.x; ch * kMergeThreads < nf; ch += gridDim.x) {
+        const int64_t i_own = ch * kMergeThreads + threadIdx.x;
+        const uint32_t n_own = i_own < nf ? (uint32_t)M.chain_hits[M.fit_list[i_own]] : 0u;
+        key[threadIdx.x] = ((n_own < 0xFFFFFFu ? n_own : 0xFFFFFFu) << 8) | (uint32_t)threadIdx.x;
+        __syncthreads();
+        sort_desc_256(key);
+        const int64_t i = ch * kMergeThreads + (key[threadIdx.x] & 0xFFu);
+        __syncthreads();
+        if (i >= nf) continue;
         const int32_t t = M.fit_list[i];
         const int32_t n = M.chain_hits[t];
+        const int64_t base = M.fit_off[t];
         const int s0 = M.sector[t];
-        const int64_t tfb = (int64_t)M.tf[t] * ns;
         // seed points in the frame of the first cluster's sector
         double sx[3], sy[3], sz[3];
         const int32_t ids[3] = {0, (n - 1) / 2, n - 1};
         for (int q = 0; q < 3; ++q) {
-            int32_t u;
-            const int64_t h = chain_hit(M, t, ids[q], u);
-            const int su = M.sector[u];
-            const double x = P.rx[row_of(M.off, (tfb + su) * nr, nr, h)], y = M.y[h];
-            sz[q] = M.z[h];
+            const float4 e = M.grec[base + ids[q]];
+            const int su = __float_as_int(e.w);
+            const double x = e.z, y = e.x;
+            sz[q] = e.y;
             if (su == s0) {
                 sx[q] = x;
                 sy[q] = y;
@@ -371,62 +553,44 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_fit(MergeBatch M, DevParams
         Trk tr;
         bool ok = trk_seed(tr, sx, sy, sz, P);
         double chi2 = 0.0;
-        int32_t last = t;
         if (ok) {
             trk_reset_cov(tr, P);
             int frame = s0;
-            int32_t u = t;
-            bool first = true;
-            for (int seg = 0; ok && u >= 0 && seg < M.nseg[t]; ++seg) {
-                const int su = M.sector[u];
-                const int64_t g0 = (tfb + su) * nr;
+            for (int32_t k = 0; k < n; ++k) {
+                const float4 e = M.grec[base + k];
+                const int su = __float_as_int(e.w);
                 if (su != frame) {
                     const int di = step_index(frame, su, S);
                     ++n_rot;
-                    ok = trk_rotate(tr, Q.rc[di], Q.rs[di], P);
+                    if (!trk_rotate(tr, Q.rc[di], Q.rs[di], P)) { ok = false; break; }
                     frame = su;
                 }
-                for (int64_t j = M.hit_off[u]; ok && j < M.hit_off[u + 1]; ++j) {
-                    const int64_t h = M.hit_ids[j];
-                    if (!first) {
-                        ++n_prop;
-                        ok = trk_propagate(tr, (double)P.rx[row_of(M.off, g0, nr, h)], P);
-                        if (!ok) break;
-                    }
-                    first = false;
-                    trk_update(tr, (double)M.y[h], (double)M.z[h], P);
-                    ++n_upd;
+                if (k > 0) {
+                    ++n_prop;
+                    if (!trk_propagate(tr, (double)e.z, P)) { ok = false; break; }
                 }
-                last = u;
-                u = M.next[u];
+                trk_update(tr, (double)e.x, (double)e.y, P);
+                ++n_upd;
             }
             if (ok) {
                 trk_reset_cov(tr, P);
-                u = last;
-                bool lastc = true;
-                for (int seg = 0; ok && u >= 0 && seg < M.nseg[t]; ++seg) {
-                    const int su = M.sector[u];
-                    const int64_t g0 = (tfb + su) * nr;
+                for (int32_t k = n - 1; k >= 0; --k) {
+                    const float4 e = M.grec[base + k];
+                    const int su = __float_as_int(e.w);
                     if (su != frame) {
                         const int di = step_index(frame, su, S);
                         ++n_rot;
-                        ok = trk_rotate(tr, Q.rc[di], Q.rs[di], P);
+                        if (!trk_rotate(tr, Q.rc[di], Q.rs[di], P)) { ok = false; break; }
                         frame = su;
                     }
-                    for (int64_t j = M.hit_off[u + 1] - 1; ok && j >= M.hit_off[u]; --j) {
-                        const int64_t h = M.hit_ids[j];
-                        if (!lastc) {
-                            ++n_prop;
-                            ok = trk_propagate(tr, (double)P.rx[row_of(M.off, g0, nr, h)], P);
-                            if (!ok) break;
-                        }
-                        lastc = false;
-                        const double my = M.y[h], mz = M.z[h];
-                        chi2 += trk_chi2(tr, my, mz, P);
-                        trk_update(tr, my, mz, P);
-                        ++n_upd;
+                    if (k < n - 1) {
+                        ++n_prop;
+                        if (!trk_propagate(tr, (double)e.z, P)) { ok = false; break; }
                     }
-                    u = (u == t) ? -1 : M.prev[u];
+                    const double my = e.x, mz = e.y;
+                    chi2 += trk_chi2(tr, my, mz, P);
+                    trk_update(tr, my, mz, P);
+                    ++n_upd;
                 }
             }
         }
@@ -465,55 +629,74 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_lead(MergeBatch M)
     }
 }
 
-// 9: merged tracks at their scanned positions
+// 9: merged tracks at their scanned positions: records per lane, then each written
+// track's clusters copied by the whole wave, segment by segment
 __global__ void __launch_bounds__(kMergeThreads) k_m_emit(MergeBatch M, DevParams P)
 {
     if (M.mc->bad) return;
     const int64_t T = M.mc->T;
+    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t0 == 0 && M.cap_merged >= 0) M.o_hit_off[0] = 0;
-    for (int64_t t = t0; t < T; t += stride) {
-        if (M.o_next) {
-            M.o_next[t] = M.next[t];
-            if (M.o_link_chi2) M.o_link_chi2[t] = M.next[t] >= 0 ? M.bestChi[t] : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && M.cap_merged >= 0) M.o_hit_off[0] = 0;
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < T; t0 += stride) {
+        const int64_t t = t0 + lane;
+        bool on = t < T;
+        int64_t m = 0, hp = 0;
+        int32_t nseg = 1;
+        if (on) {
+            if (M.o_next) {
+                M.o_next[t] = M.next[t];
+                if (M.o_link_chi2) M.o_link_chi2[t] = M.next[t] >= 0 ? M.bestChi[t] : 0.0;
+            }
+            on = M.lead[t] != 0;
         }
-        if (!M.lead[t]) continue;
-        const int64_t m = M.m_idx[t], hp = M.m_hpos[t];
-        const int32_t nh = M.nh[t];
-        if (m >= M.cap_merged || hp + nh > M.cap_hits) {
-            atomicOr(&M.ctr->err, kErrOutCap);
-            continue;
+        if (on) {
+            m = M.m_idx[t];
+            hp = M.m_hpos[t];
+            const int32_t nh = M.nh[t];
+            if (m >= M.cap_merged || hp + nh > M.cap_hits) {
+                atomicOr(&M.ctr->err, kErrOutCap);
+                on = false;
+            } else {
+                const bool whole = M.prev[t] < 0 && M.nseg[t] >= 2 && M.fit_ok[t];
+                const double* src_p;
+                if (whole) {
+                    const double* ms = M.mstate + t * 21;
+                    for (int q = 0; q < 5; ++q) M.o_par[m * 5 + q] = ms[q];
+                    for (int q = 0; q < 15; ++q) M.o_cov[m * 15 + q] = ms[5 + q];
+                    M.o_chi2[m] = ms[20];
+                    nseg = M.nseg[t];
+                    src_p = ms;
+                } else {
+                    for (int q = 0; q < 5; ++q) M.o_par[m * 5 + q] = M.par[t * 5 + q];
+                    for (int q = 0; q < 15; ++q) M.o_cov[m * 15 + q] = M.cov[t * 15 + q];
+                    M.o_chi2[m] = M.chi2[t];
+                    src_p = M.par + t * 5;
+                }
+                M.o_nseg[m] = nseg;
+                M.o_xref[m] = M.xref[t];
+                if (M.o_zbeam) M.o_zbeam[m] = trk_beamline_z(P, M.xref[t], src_p);
+                M.o_ndf[m] = 2 * nh - 5;
+                M.o_nhits_trk[m] = nh;
+                M.o_sector[m] = M.sector[t];
+                M.o_tf[m] = M.tf[t];
+                M.o_hit_off[m + 1] = hp + nh;
+            }
         }
-        const bool whole = M.prev[t] < 0 && M.nseg[t] >= 2 && M.fit_ok[t];
-        const double* src_p;
-        if (whole) {
-            const double* ms = M.mstate + t * 21;
-            for (int q = 0; q < 5; ++q) M.o_par[m * 5 + q] = ms[q];
-            for (int q = 0; q < 15; ++q) M.o_cov[m * 15 + q] = ms[5 + q];
-            M.o_chi2[m] = ms[20];
-            M.o_nseg[m] = M.nseg[t];
-            src_p = ms;
-        } else {
-            for (int q = 0; q < 5; ++q) M.o_par[m * 5 + q] = M.par[t * 5 + q];
-            for (int q = 0; q < 15; ++q) M.o_cov[m * 15 + q] = M.cov[t * 15 + q];
-            M.o_chi2[m] = M.chi2[t];
-            M.o_nseg[m] = 1;
-            src_p = M.par + t * 5;
-        }
-        M.o_xref[m] = M.xref[t];
-        if (M.o_zbeam) M.o_zbeam[m] = trk_beamline_z(P, M.xref[t], src_p);
-        M.o_ndf[m] = 2 * nh - 5;
-        M.o_nhits_trk[m] = nh;
-        M.o_sector[m] = M.sector[t];
-        M.o_tf[m] = M.tf[t];
-        M.o_hit_off[m + 1] = hp + nh;
-        int64_t k = hp;
-        const int32_t nseg = whole ? M.nseg[t] : 1;
-        int32_t u = (int32_t)t;
-        for (int seg = 0; u >= 0 && seg < nseg; ++seg, u = M.next[u]) {
-            M.o_track_merged[u] = (int32_t)m;
-            for (int64_t j = M.hit_off[u]; j < M.hit_off[u + 1]; ++j) M.o_hit_ids[k++] = M.hit_ids[j];
+        uint64_t todo = __ballot(on);
+        while (todo) {
+            const int l = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1ull;
+            int32_t u = (int32_t)__shfl(t, l, 64);
+            const int64_t mm = __shfl(m, l, 64);
+            int64_t k = __shfl(hp, l, 64);
+            const int32_t ns_l = __shfl(nseg, l, 64);
+            for (int seg = 0; u >= 0 && seg < ns_l; ++seg, u = M.next[u]) {
+                if (lane == 0) M.o_track_merged[u] = (int32_t)mm;
+                const int64_t hb = M.hit_off[u], n = M.hit_off[u + 1] - hb;
+                for (int64_t j = lane; j < n; j += 64) M.o_hit_ids[k + j] = M.hit_ids[hb + j];
+                k += n;
+            }
         }
     }
 }
@@ -532,10 +715,15 @@ void launch_merge(const MergeBatch& M, const DevParams& P, const MergeParams& Q,
     hipLaunchKernelGGL(k_m_init, g, b, 0, s, M, n_lists);
     hipLaunchKernelGGL(k_m_ends, g, b, 0, s, M, P, Q);
     hipLaunchKernelGGL(k_m_lists, g, b, 0, s, M);
+    {
+        int64_t sb = n_lists < (int64_t)n_cu * 2 ? n_lists : (int64_t)n_cu * 2;
+        hipLaunchKernelGGL(k_m_sort, dim3((unsigned)(sb > 0 ? sb : 1)), dim3(kSortThreads), 0, s, M, n_lists);
+    }
     hipLaunchKernelGGL(k_m_match, g, b, 0, s, M, P, Q);
     hipLaunchKernelGGL(k_m_tie, g, b, 0, s, M);
     hipLaunchKernelGGL(k_m_link, g, b, 0, s, M);
     hipLaunchKernelGGL(k_m_chain, g, b, 0, s, M);
+    hipLaunchKernelGGL(k_m_gather, g, b, 0, s, M, P);
     hipLaunchKernelGGL(k_m_fit, g, b, 0, s, M, P, Q);
     hipLaunchKernelGGL(k_m_lead, g, b, 0, s, M);
     ScanJob J{};
