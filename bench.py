@@ -262,6 +262,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the serving run (Poisson arrivals at 80%% of capacity); 0 skips it")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--reject-steps", type=int, default=20,
+                    help="timed calls of the strategy-B hit removal (0: skip)")
     ap.add_argument("--merge-steps", type=int, default=20,
                     help="timed calls of the merge across sector edges (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -390,6 +392,29 @@ def main():
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
     trk.set_stage_timing(False)
 
+    # hit removal for compression, strategy B: timed calls on the tracks of the last
+    # tracking call (it reuses that call's grids).  Not part of the step above.
+    reject = None
+    if args.reject_steps > 0:
+        trk.track(frame, out=out)
+        keep = torch.empty(N, dtype=torch.uint8, device="cuda:0")
+        n_kept = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+        trk.launch_reject(frame, out, keep, n_kept)
+        trk.sync()
+        kept = int(n_kept.item())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.reject_steps):
+            trk.launch_reject(frame, out, keep, n_kept)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        trk.sync()
+        r_ms = e0.elapsed_time(e1) / args.reject_steps
+        assert int(n_kept.item()) == kept
+        reject = {"ms_per_call": r_ms, "calls": args.reject_steps, "clusters": N, "kept": kept,
+                  "kept_fraction": kept / N, "clusters_per_s": N / (r_ms * 1e-3)}
+        log(f"reject: kept {kept} of {N} ({kept / N:.3f}) in {r_ms:.3f} ms")
+
     # merging across sector edges and refit across sector frames (the stage after sector
     # tracking): timed calls on this frame's sector tracks, tracked with the outer states
     # the merge needs.  Not part of the step above.
@@ -442,6 +467,7 @@ def main():
         "roofline": roofline,
         "kalman_stages": kalman,
         "merge": merge,
+        "reject": reject,
         "path_hbm": {"bytes_per_cluster": path_bytes / N,
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
                      "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

@@ -75,6 +75,7 @@ typedef struct {
     double c0[5];
     int32_t min_chain, min_track_hits, max_miss;
     double merge_edge, merge_window, merge_chi2;   /* tpcsf_merge, see there */
+    double reject_pt_min, reject_window;           /* tpcsf_reject, see there */
 } tpcsf_params;
 
 /* Tuning: changes speed and the grid tables, never links or tracks.
@@ -292,6 +293,24 @@ tpcsf_status tpcsf_merge(tpcsf_ctx* ctx, const tpcsf_frame* frame, const tpcsf_t
 /* Work of the last merge call, after a sync: candidate pairs through the gate, their
  * propagations, chi2 evaluations; refit rotations, propagations, updates. */
 tpcsf_status tpcsf_merge_work(tpcsf_ctx* ctx, int64_t* work6);
+
+/* Hit removal for data compression, strategy B (Sec. 4): only the clusters in the
+ * vicinity of good tracks are kept (the tracks' own clusters are found through their
+ * cluster_track map, which must be the one of these tracks).  Definition: a good track has pT >= reject_pt_min
+ * (|q/pT| * reject_pt_min <= 1); it keeps its own clusters, and at every row from its
+ * innermost to its outermost cluster's row its state at x_ref, propagated in one helix
+ * step to the row plane (no contribution where that step fails, see tpcsf_params), keeps
+ * the clusters of its sector's row with |y - y_p| <= reject_window and
+ * |z - z_p| <= reject_window (binary64).  Defaults: 0.05 GeV/c (the paper's 50 MeV/c
+ * limit for tracks used in physics) and 1 cm.
+ *   frame, tracks: the frame and the sector tracks of this context's LAST tracking call
+ *     (its search grids are reused; TPCSF_E_INVALID if the frame is another one).
+ *   keep:   [device] [n_clusters] written: 1 = kept, 0 = removed, batch input order.
+ *   n_kept: [device] scalar written.
+ * Asynchronous on `stream`; tracks whose clusters lie outside their sector are skipped
+ * and reported by tpcsf_sync as TPCSF_E_INVALID. */
+tpcsf_status tpcsf_reject(tpcsf_ctx* ctx, const tpcsf_frame* frame, const tpcsf_tracks* tracks,
+                          uint8_t* keep, int64_t* n_kept, void* stream);
 
 /* Message of the last error on this context (static storage of the context). */
 const char* tpcsf_last_error(const tpcsf_ctx* ctx);

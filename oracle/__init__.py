@@ -22,6 +22,7 @@ DEFAULT_PARAMS = dict(
     c0=(1.0, 1.0, 1.0, 1.0, 100.0),
     min_chain=5, min_track_hits=20, max_miss=4,
     merge_edge=6.0, merge_window=5.0, merge_chi2=30.0,
+    reject_pt_min=0.05, reject_window=1.0,
 )
 # Grid tuning (changes the grid tables, never links or tracks).
 DEFAULT_GRID = dict(bin_y=2.0, bin_z=2.0, cap_mul=2, cap_add=64)
@@ -37,6 +38,7 @@ class _Cfg(C.Structure):
         ("min_chain", C.c_int32), ("min_track_hits", C.c_int32), ("max_miss", C.c_int32),
         ("bin_y", C.c_float), ("bin_z", C.c_float), ("cap_mul", C.c_int32), ("cap_add", C.c_int32),
         ("merge_edge", C.c_double), ("merge_window", C.c_double), ("merge_chi2", C.c_double),
+        ("reject_pt_min", C.c_double), ("reject_window", C.c_double),
     ]
 
 
@@ -106,6 +108,9 @@ def _lib(mode):
         lib.orc_fit_hits.argtypes = [C.POINTER(_Cfg), C.c_int32, dp, dp, dp, dp, dp, dp, dp]
         lib.orc_rotate.argtypes = [C.POINTER(_Cfg), C.c_double, dp, dp, dp, dp]
         lib.orc_fit_hits_sectors.argtypes = [C.POINTER(_Cfg), C.c_int32, dp, dp, dp, C.c_void_p, dp, dp, dp]
+        lib.orc_reject_frame.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.POINTER(_Tracks), C.c_int, C.c_void_p]
+        lib.orc_reject_frame.restype = C.c_int64
         lib.orc_merge_frame.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.POINTER(_Tracks), C.POINTER(_Merged)]
         _LIBS[mode] = lib
@@ -134,7 +139,8 @@ class Oracle:
                         p["chi2_max"], p["sinphi_max"], p["nsig"], (C.c_double * 5)(*p["c0"]),
                         p["min_chain"], p["min_track_hits"], p["max_miss"],
                         g["bin_y"], g["bin_z"], g["cap_mul"], g["cap_add"],
-                        p["merge_edge"], p["merge_window"], p["merge_chi2"])
+                        p["merge_edge"], p["merge_window"], p["merge_chi2"],
+                        p["reject_pt_min"], p["reject_window"])
 
     # -- whole frame ----------------------------------------------------------------
     def track_frame(self, y, z, row_off, debug=False, shuffle_seed=0):
@@ -237,6 +243,26 @@ class Oracle:
         res.update(n_merged=M, n_hits=Hm, hit_off=o["hit_off"][:M + 1], hit_ids=o["hit_ids"][:Hm],
                    track_merged=o["track_merged"][:T], next=o["next"][:T], link_chi2=o["link_chi2"][:T])
         return res
+
+    def reject_frame(self, y, z, row_off, trk, brute=False):
+        """Hit removal, strategy B (orc_reject_frame): keep flags (uint8) and the kept count."""
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        z = np.ascontiguousarray(z, dtype=np.float32)
+        row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+        n = int(y.shape[0])
+        T = int(trk["n_tracks"])
+        H = int(trk["n_hits"]) if "n_hits" in trk else int(len(trk["hit_ids"]))
+        conv = dict(params=np.float64, x_ref=np.float64, sector=np.int32, hit_off=np.int64, hit_ids=np.int64)
+        keep_arr = {k: np.ascontiguousarray(np.asarray(trk[k]), dtype=t) for k, t in conv.items()}
+        tr = _Tracks(T, H, T, H, *[_ptr(keep_arr[k]) if k in keep_arr else None for k in
+                                   ("params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector", "hit_off",
+                                    "hit_ids", "cluster_track", "z_beam", "params_outer", "cov_outer")])
+        keep = np.zeros(max(n, 1), np.uint8)
+        k = self.lib.orc_reject_frame(C.byref(self.cfg), n, _ptr(y), _ptr(z), _ptr(row_off), C.byref(tr),
+                                      int(bool(brute)), _ptr(keep))
+        if k < 0:
+            raise RuntimeError("orc_reject_frame failed")
+        return keep[:n], int(k)
 
     # -- single steps ----------------------------------------------------------------
     def grid_row(self, y, z):

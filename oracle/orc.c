@@ -17,6 +17,8 @@
  *   7. final fit   two-pass Kalman refit of each accepted track's kept clusters
  *   8. merging     links of sector tracks across azimuthal sector edges, refit of the
  *                  merged tracks across sector frames (orc_merge_frame)
+ *   9. hit removal keep only the clusters near good tracks, compression strategy B
+ *                  (orc_reject_frame)
  */
 #include "orc.h"
 
@@ -1210,4 +1212,64 @@ int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
     free(dissolved); free(fitted); free(fit); free(fit_c2); free(chain_hits); free(chain_seg);
     free(fx); free(fs);
     return rc;
+}
+
+/* ---------------------------------------------------------------------------------- */
+/* Step 9: hit removal for data compression, strategy B (Sec. 4): the clusters that are  */
+/* not in the vicinity of a good track are removed.  See orc.h for the definition.       */
+/* ---------------------------------------------------------------------------------- */
+int64_t orc_reject_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
+                         const int64_t* row_off, const orc_tracks* trk, int brute, uint8_t* keep)
+{
+    const int nr = cfg->n_rows, ns = cfg->n_sectors;
+    if (row_off[0] != 0 || row_off[(int64_t)ns * nr] != n) return -1;
+    const double w = cfg->reject_window, pmin = cfg->reject_pt_min;
+    int32_t* row = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t g = 0; g < (int64_t)ns * nr; ++g)
+        for (int64_t i = row_off[g]; i < row_off[g + 1]; ++i) row[i] = (int32_t)(g % nr);
+    /* each row's clusters ordered by y (ties: in-row index) for the window scan */
+    int32_t* sidx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!brute)
+        for (int64_t g = 0; g < (int64_t)ns * nr; ++g)
+            sort_row_by_y(y + row_off[g], row_off[g + 1] - row_off[g], sidx + row_off[g]);
+    for (int64_t i = 0; i < n; ++i) keep[i] = 0;
+    for (int64_t t = 0; t < trk->n_tracks; ++t) {
+        const double* p = trk->params + t * 5;
+        if (!(fabs(p[4]) * pmin <= 1.0)) continue;
+        const int s = trk->sector[t];
+        const int64_t hb = trk->hit_off[t], he = trk->hit_off[t + 1];
+        if (s < 0 || s >= ns || he <= hb) { free(row); free(sidx); return -1; }
+        for (int64_t j = hb; j < he; ++j) keep[trk->hit_ids[j]] = 1;
+        const int r0 = row[trk->hit_ids[hb]], r1 = row[trk->hit_ids[he - 1]];
+        for (int r = r0; r <= r1; ++r) {
+            kstate st;
+            st.x = (orc_real)trk->x_ref[t];
+            for (int i = 0; i < 5; ++i) st.p[i] = (orc_real)p[i];
+            for (int i = 0; i < 15; ++i) st.C[i] = 0;
+            if (kprop(cfg, &st, (orc_real)cfg->row_x[r], NULL) != 0) continue;
+            const double yp = (double)st.p[0], zp = (double)st.p[1];
+            const int64_t g = (int64_t)s * nr + r, b = row_off[g], m = row_off[g + 1] - b;
+            if (brute) {
+                for (int64_t i = b; i < b + m; ++i)
+                    if (fabs((double)y[i] - yp) <= w && fabs((double)z[i] - zp) <= w) keep[i] = 1;
+            } else {
+                /* first cluster with y >= yp - w (generous by 1e-6 cm; the test decides) */
+                int64_t lo = 0, hi = m;
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) / 2;
+                    if ((double)y[b + sidx[b + mid]] < yp - w - 1e-6) lo = mid + 1; else hi = mid;
+                }
+                for (int64_t k = lo; k < m; ++k) {
+                    const int64_t i = b + sidx[b + k];
+                    if ((double)y[i] > yp + w + 1e-6) break;
+                    if (fabs((double)y[i] - yp) <= w && fabs((double)z[i] - zp) <= w) keep[i] = 1;
+                }
+            }
+        }
+    }
+    int64_t kept = 0;
+    for (int64_t i = 0; i < n; ++i) kept += keep[i];
+    free(row);
+    free(sidx);
+    return kept;
 }

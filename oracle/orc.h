@@ -50,6 +50,9 @@ typedef struct {
     double merge_edge;        /* a track end within this distance of a sector edge (cm) */
     double merge_window;      /* linear-prediction gate on y and z (cm)              */
     double merge_chi2;        /* largest accepted 5-parameter chi2 of a match        */
+    /* hit removal, strategy B (orc_reject_frame) */
+    double reject_pt_min;     /* good tracks have pT >= this (GeV/c)                 */
+    double reject_window;     /* half-width in y and z of a good track's vicinity (cm) */
 } orc_cfg;
 
 typedef struct {
@@ -178,6 +181,18 @@ typedef struct {
  * small (sizes are still written). */
 int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
                     const int64_t* row_off, const orc_tracks* trk, orc_merged* out);
+
+/* Hit removal for data compression, strategy B (Sec. 4): keep only the clusters in the
+ * vicinity of good tracks.  A good track has pT >= reject_pt_min (|q/pT| * pT_min <= 1).
+ * Its own clusters are kept, and at every row from its innermost to its outermost
+ * cluster's row its state at x_ref, propagated in one helix step to the row plane,
+ * keeps the clusters of its sector's row with |y - y_p| <= reject_window and
+ * |z - z_p| <= reject_window (a row where the step fails keeps none by this rule).
+ * keep: [n] 1 = kept.  brute != 0 compares every cluster of the row, else a y-sorted
+ * window scan (same result).  Returns the number of kept clusters, or -1 on invalid
+ * input. */
+int64_t orc_reject_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
+                         const int64_t* row_off, const orc_tracks* trk, int brute, uint8_t* keep);
 
 #ifdef __cplusplus
 }

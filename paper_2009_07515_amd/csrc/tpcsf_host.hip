@@ -27,7 +27,7 @@ struct Layout {
     size_t keep_n, fit_pos, cand_off, kept_list, keep_mask, fit_list;
     size_t trk_flag, hit_cnt, trk_idx, hit_pos, trk_out;
     size_t f_par, f_cov, f_chi2, f_xref, f_pout, f_cout, scan_part;
-    size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n;
+    size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n, rmark;
 };
 
 constexpr int kStages = 13;
@@ -75,6 +75,7 @@ struct tpcsf_ctx {
     hipEvent_t ev[kStages + 1] = {};
     bool timed_last = false;
     Batch last{};
+    DevParams last_P{};             // the method constants and tuning of that call
     bool have_last = false;
     std::string err;
 };
@@ -160,6 +161,7 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.d_start_row = take(S * 4);
     L.d_start_idx = take(S * 4);
     L.d_tl_n = take(S * 4);
+    L.rmark = take(N);
     L.total = o;
     return L;
 }
@@ -215,6 +217,7 @@ bool params_ok(const tpcsf_params* p)
     for (int i = 0; i < 5; ++i)
         if (!(p->c0[i] > 0)) return false;
     if (!(p->merge_edge >= 0 && p->merge_window >= 0 && p->merge_chi2 >= 0)) return false;
+    if (!(p->reject_pt_min >= 0 && p->reject_window >= 0 && p->reject_window < 1e4)) return false;
     return p->min_chain >= 3 && p->min_track_hits >= 3 && p->max_miss >= 0;
 }
 
@@ -532,6 +535,37 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     return TPCSF_OK;
 }
 
+extern "C" tpcsf_status tpcsf_reject(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks* t, uint8_t* keep,
+                                     int64_t* n_kept, void* stream)
+{
+    if (!c) return TPCSF_E_INVALID;
+    if (!f || !t || !n_kept || (f->n_clusters > 0 && !keep)) return fail(c, TPCSF_E_INVALID, "null argument");
+    const int64_t R = (int64_t)f->n_tf * c->n_sectors * c->n_rows;
+    if (!c->have_last || c->last.y != f->y || c->last.z != f->z || c->last.off != f->row_offsets ||
+        (int64_t)c->last.n_rows_total != R)
+        return fail(c, TPCSF_E_INVALID, "tpcsf_reject needs the frame of the context's last tracking call");
+    if (t->cap_tracks < 0 || !t->n_tracks || !t->hit_off) return fail(c, TPCSF_E_INVALID, "track input incomplete");
+    if (t->cap_tracks > 0 && (!t->params || !t->x_ref || !t->sector || !t->tf || !t->hit_ids))
+        return fail(c, TPCSF_E_INVALID, "track input arrays missing");
+    if (f->n_clusters > 0 && !t->cluster_track) return fail(c, TPCSF_E_INVALID, "cluster_track missing");
+    RejectArgs A{};
+    A.n_tracks = t->n_tracks; A.cap_tracks = t->cap_tracks; A.cap_hits = t->cap_hits;
+    A.par = t->params; A.xref = t->x_ref; A.sector = t->sector; A.tf = t->tf;
+    A.hit_off = t->hit_off; A.hit_ids = t->hit_ids; A.cluster_track = t->cluster_track;
+    A.n_tf = f->n_tf;
+    A.mark = (uint8_t*)c->arena + c->lay.rmark;
+    A.pt_min = c->params.reject_pt_min;
+    A.window = c->params.reject_window;
+    A.keep = keep;
+    A.n_kept = n_kept;
+    Batch B = c->last;
+    B.n = f->n_clusters;
+    launch_reject(B, c->last_P, A, launch_cfg(c), (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "reject kernel launch");
+    return TPCSF_OK;
+}
+
 extern "C" tpcsf_status tpcsf_merge_work(tpcsf_ctx* c, int64_t* work6)
 {
     if (!c || !work6) return TPCSF_E_INVALID;
@@ -563,6 +597,8 @@ void tpcsf_default_params(tpcsf_params* p)
     p->merge_edge = 6.0;
     p->merge_window = 5.0;
     p->merge_chi2 = 30.0;
+    p->reject_pt_min = 0.05;
+    p->reject_window = 1.0;
 }
 
 void tpcsf_default_tuning(tpcsf_tuning* t)
@@ -689,6 +725,7 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
             launch_assign(B, P, g0, g1, LC, s);
         }
     c->last = B;
+    c->last_P = dev_params(c);
     c->have_last = true;
     c->timed_last = false;
     hipError_t e = hipGetLastError();
@@ -721,6 +758,7 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "kernel launch");
         c->timed_last = true;
         c->last = B;
+        c->last_P = dev_params(c);
         c->have_last = true;
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "kernel launch");
         return TPCSF_OK;
@@ -750,6 +788,7 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
     if ((e = hipGraphLaunch(c->gexec, (hipStream_t)stream)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
     c->timed_last = false;
     c->last = B;
+    c->last_P = dev_params(c);
     c->have_last = true;
     return TPCSF_OK;
 }

@@ -233,6 +233,22 @@ struct MergeBatch {
 
 void launch_merge(const MergeBatch& b, const DevParams& p, const MergeParams& m, int n_cu, hipStream_t s);
 
+// Hit removal, strategy B (tpcsf_reject): the sector tracks of the context's last call and
+// the keep flags to write.
+struct RejectArgs {
+    const int64_t* n_tracks; int64_t cap_tracks, cap_hits;
+    const double* par; const double* xref;
+    const int32_t* sector; const int32_t* tf;
+    const int64_t* hit_off; const int32_t* hit_ids;
+    const int32_t* cluster_track;   // [n_clusters] the tracks' cluster -> track map
+    int32_t n_tf;
+    double pt_min, window;
+    uint8_t* mark;                  // [arena, N] vicinity flags in sorted (bin) order
+    uint8_t* keep;                  // [n_clusters]
+    int64_t* n_kept;
+};
+void launch_reject(const Batch& b, const DevParams& p, const RejectArgs& r, const LaunchCfg& c, hipStream_t s);
+
 // Stage launchers (all asynchronous on `stream`).  Row ranges are [g0, g1).
 // Allows the grid kernel the device's LDS per block; returns the dynamic LDS bytes to use.
 int grid_lds_setup(int max_lds_per_block);

@@ -103,6 +103,33 @@ static __device__ bool trk_propagate(Trk& t, double x1, const DevParams& P)
     return true;
 }
 
+// Position (y, z) of the helix of state p at plane x0 on the plane x1: the parameter part
+// of trk_propagate, same arithmetic.  False where that step would fail.
+__device__ __forceinline__ bool trk_predict(const double* p, double x0, double x1, const DevParams& P, double& y,
+                                            double& z)
+{
+    const double dx = x1 - x0;
+    const double s0 = p[2];
+    const double kap = P.a * p[4];
+    const double s1 = s0 + kap * dx;
+    if (!(fabs(s0) < P.sinphi_max) || !(fabs(s1) < P.sinphi_max)) return false;
+    const double u0 = (1.0 - s0) * (1.0 + s0), u1 = (1.0 - s1) * (1.0 + s1);
+    const double ic0 = rsqrt(u0), ic1 = rsqrt(u1);
+    const double c0 = u0 * ic0, c1 = u1 * ic1;
+    const double ics = 1.0 / (c0 + c1);
+    const double tb = (s0 + s1) * ics;
+    const double sec2 = 1.0 + tb * tb;
+    const double sec = sqrt(sec2);
+    const double chord = dx * sec;
+    const double h = 0.5 * kap * chord;
+    if (!(fabs(h) < 1.0)) return false;
+    double A, Ap;
+    arc_factor(h, A, Ap);
+    y = p[0] + dx * tb;
+    z = p[1] + p[3] * (chord * A);
+    return true;
+}
+
 __device__ __forceinline__ double trk_chi2(const Trk& t, double my, double mz, const DevParams& P)
 {
     const double r0 = my - t.p[0], r1 = mz - t.p[1];

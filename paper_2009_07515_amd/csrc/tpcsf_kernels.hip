@@ -1859,6 +1859,152 @@ void launch_assign(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, c
     hipLaunchKernelGGL(k_assign, dim3(grid_for(g1 - g0, 1, 1 << 16)), dim3(256), 0, s, b, p, g0, g1);
 }
 
+// ------------------------------------------------------------------------------------
+// Hit removal for data compression, strategy B (Sec. 4): keep only the clusters in the
+// vicinity of good tracks (pT >= pt_min).  A good track keeps its own clusters and, at
+// every row from its innermost to its outermost cluster's row, the clusters of its
+// sector's row within `window` in y and z of its state at x_ref propagated in one helix
+// step to the row.  The rows are searched with the grids of the same call.  Wave per
+// track; the flags are bytes in input order (concurrent stores all write 1).
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_r_clear(RejectArgs A, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) *A.n_kept = 0;
+    for (int64_t i = i0; i < n; i += stride) A.mark[i] = 0;
+}
+
+// row of cluster h among the rows [g0, g0 + nr): the lanes test 64 rows per pass
+__device__ __forceinline__ int wave_row_of(const int64_t* off, int64_t g0, int nr, int64_t h)
+{
+    for (int r0 = 0; r0 < nr; r0 += 64) {
+        const int r = r0 + lane_id();
+        const bool in = r < nr && off[g0 + r] <= h && h < off[g0 + r + 1];
+        const uint64_t m = __ballot(in);
+        if (m != 0ull) return r0 + __ffsll((unsigned long long)m) - 1;
+    }
+    return 0;
+}
+
+// vicinity of the good tracks, marked in sorted order.  A wave takes 64 neighbouring
+// tracks (lane per track) and sweeps their rows together, all lanes on the same row, so
+// that they share the row's record and nearby parts of its bin table; the input checks
+// are done by the whole wave, 64 clusters of one track per pass.
+__global__ void __launch_bounds__(256) k_r_mark(Batch B, DevParams P, RejectArgs A)
+{
+    const int nr = P.n_rows, ns = P.n_sectors;
+    const int lane = lane_id();
+    int64_t T = *A.n_tracks;
+    if (T > A.cap_tracks) T = A.cap_tracks;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; w0 < T; w0 += nw * 64) {
+        const int64_t t = w0 + lane;
+        bool on = false;
+        int64_t g0 = 0, hb = 0, he = 0, lo = 0, hi = 0;
+        double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, x0 = 0.0;
+        if (t < T) {
+            for (int q = 0; q < 5; ++q) p[q] = A.par[t * 5 + q];
+            x0 = A.xref[t];
+            const int s = A.sector[t], f = A.tf[t];
+            hb = A.hit_off[t];
+            he = A.hit_off[t + 1];
+            if (!(s >= 0 && s < ns && f >= 0 && f < A.n_tf && hb >= 0 && he > hb && he <= A.cap_hits)) {
+                atomicOr(&B.ctr->err, kErrInvalid);
+            } else if (fabs(p[4]) * A.pt_min <= 1.0) {
+                g0 = ((int64_t)f * ns + s) * nr;
+                lo = B.off[g0];
+                hi = B.off[g0 + nr];
+                on = true;
+            }
+        }
+        // every cluster inside the track's own sector
+        uint64_t todo = __ballot(on);
+        while (todo) {
+            const int l = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1ull;
+            const int64_t b0 = __shfl(hb, l, 64), b1 = __shfl(he, l, 64);
+            const int64_t c0 = __shfl(lo, l, 64), c1 = __shfl(hi, l, 64);
+            bool out = false;
+            for (int64_t j = b0 + lane; j < b1; j += 64) {
+                const int64_t h = A.hit_ids[j];
+                out = out || h < c0 || h >= c1;
+            }
+            if (__ballot(out) != 0ull && lane == l) {
+                on = false;
+                atomicOr(&B.ctr->err, kErrInvalid);
+            }
+        }
+        int r0 = 0, r1 = -1;
+        if (on) {
+            const int64_t hs[2] = {A.hit_ids[hb], A.hit_ids[he - 1]};
+            int rr[2];
+            for (int q = 0; q < 2; ++q) {
+                int a = 0, b = nr - 1;
+                while (a < b) {
+                    const int mid = (a + b + 1) >> 1;
+                    if (B.off[g0 + mid] <= hs[q]) a = mid; else b = mid - 1;
+                }
+                rr[q] = a;
+            }
+            r0 = rr[0];
+            r1 = rr[1];
+        }
+        const int rlo = wave_min_i(on ? r0 : nr), rhi = wave_max_i(on ? r1 : -1);
+        const double w = A.window;
+        for (int r = rlo; r <= rhi; ++r) {
+            if (!(on && r >= r0 && r <= r1)) continue;
+            double yp, zp;
+            if (!trk_predict(p, x0, (double)P.rx[r], P, yp, zp)) continue;
+            if (!(fabs(yp) < 1.0e6) || !(fabs(zp) < 1.0e6)) continue;
+            const int64_t g = g0 + r;
+            const RowView v = row_view(B, P, g);
+            if (v.n == 0) continue;
+            int iy0, iy1, iz0, iz1;
+            bin_span((float)yp, (float)w, v.ylo, v.iby, v.ny, iy0, iy1);
+            bin_span((float)zp, (float)w, v.zlo, v.ibz, v.nz, iz0, iz1);
+            const float2* yz = B.yz + v.first;
+            for (int iz = iz0; iz <= iz1; ++iz) {
+                const uint32_t a0 = v.bs[iz * v.ny + iy0], a1 = v.bs[iz * v.ny + iy1 + 1];
+                for (uint32_t k = a0; k < a1; ++k) {
+                    const float2 c = yz[k];
+                    if (fabs((double)c.x - yp) <= w && fabs((double)c.y - zp) <= w) A.mark[v.first + k] = 1;
+                }
+            }
+        }
+    }
+}
+
+// keep flags in input order, per row: in the vicinity of a good track, or a cluster of one
+__global__ void __launch_bounds__(256) k_r_final(Batch B, RejectArgs A, int64_t g0, int64_t g1)
+{
+    int64_t T = *A.n_tracks;
+    if (T > A.cap_tracks) T = A.cap_tracks;
+    int64_t c = 0;
+    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
+        const int64_t base = B.off[g];
+        const int n = (int)(B.off[g + 1] - base);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int32_t t = A.cluster_track[base + i];
+            bool k = A.mark[base + B.iperm[base + i]] != 0;
+            if (!k && t >= 0 && t < T) k = fabs(A.par[(int64_t)t * 5 + 4]) * A.pt_min <= 1.0;
+            A.keep[base + i] = k ? 1 : 0;
+            c += k;
+        }
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd((unsigned long long*)A.n_kept, (unsigned long long)c);
+}
+
+void launch_reject(const Batch& b, const DevParams& p, const RejectArgs& r, const LaunchCfg& c, hipStream_t s)
+{
+    const unsigned g = (unsigned)(c.n_cu * 4);
+    hipLaunchKernelGGL(k_r_clear, dim3(g), dim3(256), 0, s, r, b.n);
+    hipLaunchKernelGGL(k_r_mark, dim3(c.n_cu * 8), dim3(256), 0, s, b, p, r);
+    hipLaunchKernelGGL(k_r_final, dim3(grid_for(b.n_rows_total, 1, 1 << 16)), dim3(256), 0, s, b, r, (int64_t)0,
+                       (int64_t)b.n_rows_total);
+}
+
 void launch_hash(const Batch& b, int64_t n_clusters, const LaunchCfg& c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_hash_clear, dim3(1), dim3(64), 0, s, b);

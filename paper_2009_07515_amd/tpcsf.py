@@ -37,7 +37,8 @@ class Params(C.Structure):
                 ("sigma_y", C.c_double), ("sigma_z", C.c_double), ("chi2_max", C.c_double),
                 ("sinphi_max", C.c_double), ("nsig", C.c_double), ("c0", C.c_double * 5),
                 ("min_chain", C.c_int32), ("min_track_hits", C.c_int32), ("max_miss", C.c_int32),
-                ("merge_edge", C.c_double), ("merge_window", C.c_double), ("merge_chi2", C.c_double)]
+                ("merge_edge", C.c_double), ("merge_window", C.c_double), ("merge_chi2", C.c_double),
+                ("reject_pt_min", C.c_double), ("reject_window", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -122,6 +123,8 @@ def load():
     lib.tpcsf_merge.argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), C.POINTER(MergedDesc), vp]
     lib.tpcsf_merge.restype = C.c_int
     lib.tpcsf_merge_work.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.tpcsf_reject.argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), vp, vp, vp]
+    lib.tpcsf_reject.restype = C.c_int
     lib.tpcsf_merge_work.restype = C.c_int
     lib.tpcsf_sync.argtypes = [vp, vp]
     lib.tpcsf_sync.restype = C.c_int
@@ -404,6 +407,22 @@ class Tracker:
         self.launch_merge(frame, tracks, out, stream)
         self.sync(stream)
         return out.result(int(tracks.n_tracks.item()))
+
+    def launch_reject(self, frame: DeviceFrame, tracks: TrackBuffers, keep, n_kept, stream=None):
+        """Enqueue the strategy-B hit removal for the last tracking call (no sync)."""
+        fd, td = frame.desc(), tracks.desc()
+        self._check(self.lib.tpcsf_reject(self.h, C.byref(fd), C.byref(td), _ptr(keep), _ptr(n_kept),
+                                          self._stream(stream)))
+
+    def reject(self, frame: DeviceFrame, tracks: TrackBuffers, stream=None):
+        """Keep flags (uint8, input order) and kept count of the strategy-B hit removal for
+        the sector tracks of the last tracking call on `frame` (synchronises)."""
+        import torch
+        keep = torch.empty(max(frame.n_clusters, 1), dtype=torch.uint8, device=frame.y.device)
+        n_kept = torch.zeros(1, dtype=torch.int64, device=frame.y.device)
+        self.launch_reject(frame, tracks, keep, n_kept, stream)
+        self.sync(stream)
+        return keep[:frame.n_clusters], int(n_kept.item())
 
     def merge_work(self):
         w = (C.c_int64 * 6)()
