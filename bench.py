@@ -262,6 +262,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the serving run (Poisson arrivals at 80%% of capacity); 0 skips it")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--compress-steps", type=int, default=20,
+                    help="timed calls of the track-model compression (0: skip)")
     ap.add_argument("--reject-steps", type=int, default=20,
                     help="timed calls of the strategy-B hit removal (0: skip)")
     ap.add_argument("--merge-steps", type=int, default=20,
@@ -392,6 +394,48 @@ def main():
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
     trk.set_stage_timing(False)
 
+    # track-model compression of the attached clusters: timed encode calls, one decode,
+    # and the bits per coordinate of the codes against absolute coordinates at the same step
+    compress = None
+    if args.compress_steps > 0:
+        trk.track(frame, out=out)
+        H = int(out.n_hits.item())
+        codes = torch.empty((max(out.cap_hits, 1), 2), dtype=torch.int32, device="cuda:0")
+        rows = torch.empty(max(out.cap_hits, 1), dtype=torch.uint8, device="cuda:0")
+        yz = torch.empty((max(out.cap_hits, 1), 2), dtype=torch.float64, device="cuda:0")
+        trk.launch_compress(frame, out, codes, rows)
+        trk.launch_decompress(out, codes, rows, yz)
+        trk.sync()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        for _ in range(args.compress_steps):
+            trk.launch_compress(frame, out, codes, rows)
+        e1.record(stream)
+        for _ in range(args.compress_steps):
+            trk.launch_decompress(out, codes, rows, yz)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        trk.sync()
+        c_ms, d_ms = e0.elapsed_time(e1) / args.compress_steps, e1.elapsed_time(e2) / args.compress_steps
+        step = trk.params.resid_step
+        q = codes[:H].cpu().numpy()
+        hid = out.hit_ids[:H].cpu().numpy()
+        dec = yz[:H].cpu().numpy()
+        err = max(float(np.abs(dec[:, 0] - f.y[hid]).max()), float(np.abs(dec[:, 1] - f.z[hid]).max()))
+
+        def entropy(v):
+            _, k = np.unique(v, return_counts=True)
+            pr = k / k.sum()
+            return float(-(pr * np.log2(pr)).sum())
+
+        compress = {"encode_ms": c_ms, "decode_ms": d_ms, "calls": args.compress_steps, "clusters": H,
+                    "clusters_per_s": H / (c_ms * 1e-3), "step_cm": step, "max_decode_error_cm": err,
+                    "bits_residual": [entropy(q[:, 0]), entropy(q[:, 1])],
+                    "bits_absolute": [entropy(np.floor(f.y[hid] / step)), entropy(np.floor(f.z[hid] / step))]}
+        log(f"compress: {H} clusters, encode {c_ms:.3f} ms, decode {d_ms:.3f} ms, bits/coordinate "
+            f"{compress['bits_residual'][0]:.2f}/{compress['bits_residual'][1]:.2f} vs absolute "
+            f"{compress['bits_absolute'][0]:.2f}/{compress['bits_absolute'][1]:.2f}, max error {err:.4f} cm")
+
     # hit removal for compression, strategy B: timed calls on the tracks of the last
     # tracking call (it reuses that call's grids).  Not part of the step above.
     reject = None
@@ -468,6 +512,7 @@ def main():
         "kalman_stages": kalman,
         "merge": merge,
         "reject": reject,
+        "compress": compress,
         "path_hbm": {"bytes_per_cluster": path_bytes / N,
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
                      "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

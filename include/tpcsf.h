@@ -76,6 +76,7 @@ typedef struct {
     int32_t min_chain, min_track_hits, max_miss;
     double merge_edge, merge_window, merge_chi2;   /* tpcsf_merge, see there */
     double reject_pt_min, reject_window;           /* tpcsf_reject, see there */
+    double resid_step;                             /* tpcsf_compress, see there */
 } tpcsf_params;
 
 /* Tuning: changes speed and the grid tables, never links or tracks.
@@ -311,6 +312,27 @@ tpcsf_status tpcsf_merge_work(tpcsf_ctx* ctx, int64_t* work6);
  * and reported by tpcsf_sync as TPCSF_E_INVALID. */
 tpcsf_status tpcsf_reject(tpcsf_ctx* ctx, const tpcsf_frame* frame, const tpcsf_tracks* tracks,
                           uint8_t* keep, int64_t* n_kept, void* stream);
+
+/* Track-model compression of the attached clusters (Sec. 4, entropy reduction): each
+ * cluster of a track is stored as its row and its residual to the track's position on
+ * that row plane.  Definition: the position (y_p, z_p) is the track's state at x_ref
+ * propagated in one helix step to the row plane (the state at x_ref itself where that
+ * step fails); the codes are q = floor(r / resid_step + 1/2) for r = y - y_p and
+ * r = z - z_p (binary64), clamped to [-2^30, 2^30].  The state at x_ref (params, x_ref,
+ * sector) travels with the codes; tpcsf_decompress rebuilds y_p + q_y * resid_step and
+ * z_p + q_z * resid_step, within half a step of the clusters.  Default step 0.01 cm.
+ *   tracks: [device] any tracks of the batch (e.g. tpcsf_track_* output): n_tracks,
+ *           params, x_ref, sector, tf, hit_off, hit_ids.
+ *   codes:  [device] [cap_hits][2] written, in hit-list order (y, z).
+ *   rows:   [device] [cap_hits] written: row of each cluster in its sector.
+ * Clusters outside their track's sector get code 0 and row 0.  Asynchronous. */
+tpcsf_status tpcsf_compress(tpcsf_ctx* ctx, const tpcsf_frame* frame, const tpcsf_tracks* tracks,
+                            int32_t* codes, uint8_t* rows, void* stream);
+
+/* Decoding of tpcsf_compress: yz [device] [cap_hits][2] (binary64) from the tracks'
+ * n_tracks, params, x_ref and hit_off, the codes and the rows.  Asynchronous. */
+tpcsf_status tpcsf_decompress(tpcsf_ctx* ctx, const tpcsf_tracks* tracks, const int32_t* codes,
+                              const uint8_t* rows, double* yz, void* stream);
 
 /* Message of the last error on this context (static storage of the context). */
 const char* tpcsf_last_error(const tpcsf_ctx* ctx);

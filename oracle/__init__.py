@@ -23,6 +23,7 @@ DEFAULT_PARAMS = dict(
     min_chain=5, min_track_hits=20, max_miss=4,
     merge_edge=6.0, merge_window=5.0, merge_chi2=30.0,
     reject_pt_min=0.05, reject_window=1.0,
+    resid_step=0.01,
 )
 # Grid tuning (changes the grid tables, never links or tracks).
 DEFAULT_GRID = dict(bin_y=2.0, bin_z=2.0, cap_mul=2, cap_add=64)
@@ -39,6 +40,7 @@ class _Cfg(C.Structure):
         ("bin_y", C.c_float), ("bin_z", C.c_float), ("cap_mul", C.c_int32), ("cap_add", C.c_int32),
         ("merge_edge", C.c_double), ("merge_window", C.c_double), ("merge_chi2", C.c_double),
         ("reject_pt_min", C.c_double), ("reject_window", C.c_double),
+        ("resid_step", C.c_double),
     ]
 
 
@@ -111,6 +113,8 @@ def _lib(mode):
         lib.orc_reject_frame.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.POINTER(_Tracks), C.c_int, C.c_void_p]
         lib.orc_reject_frame.restype = C.c_int64
+        lib.orc_compress_frame.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.POINTER(_Tracks), C.c_void_p, C.c_void_p, C.c_void_p]
         lib.orc_merge_frame.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.POINTER(_Tracks), C.POINTER(_Merged)]
         _LIBS[mode] = lib
@@ -140,7 +144,7 @@ class Oracle:
                         p["min_chain"], p["min_track_hits"], p["max_miss"],
                         g["bin_y"], g["bin_z"], g["cap_mul"], g["cap_add"],
                         p["merge_edge"], p["merge_window"], p["merge_chi2"],
-                        p["reject_pt_min"], p["reject_window"])
+                        p["reject_pt_min"], p["reject_window"], p["resid_step"])
 
     # -- whole frame ----------------------------------------------------------------
     def track_frame(self, y, z, row_off, debug=False, shuffle_seed=0):
@@ -263,6 +267,29 @@ class Oracle:
         if k < 0:
             raise RuntimeError("orc_reject_frame failed")
         return keep[:n], int(k)
+
+    def compress_frame(self, y, z, row_off, trk):
+        """Track-model compression (orc_compress_frame): residual codes [H, 2] (int32),
+        unrounded residuals in steps [H, 2] and predicted positions [H, 2]."""
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        z = np.ascontiguousarray(z, dtype=np.float32)
+        row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+        n = int(y.shape[0])
+        T = int(trk["n_tracks"])
+        H = int(trk["n_hits"]) if "n_hits" in trk else int(len(trk["hit_ids"]))
+        conv = dict(params=np.float64, x_ref=np.float64, sector=np.int32, hit_off=np.int64, hit_ids=np.int64)
+        a = {k: np.ascontiguousarray(np.asarray(trk[k]), dtype=t) for k, t in conv.items()}
+        tr = _Tracks(T, H, T, H, *[_ptr(a[k]) if k in a else None for k in
+                                   ("params", "cov", "x_ref", "chi2", "ndf", "nhits", "sector", "hit_off",
+                                    "hit_ids", "cluster_track", "z_beam", "params_outer", "cov_outer")])
+        codes = np.zeros((max(H, 1), 2), np.int32)
+        resid = np.zeros((max(H, 1), 2))
+        pred = np.zeros((max(H, 1), 2))
+        rc = self.lib.orc_compress_frame(C.byref(self.cfg), n, _ptr(y), _ptr(z), _ptr(row_off), C.byref(tr),
+                                         _ptr(codes), _ptr(resid), _ptr(pred))
+        if rc != 0:
+            raise RuntimeError("orc_compress_frame failed")
+        return codes[:H], resid[:H], pred[:H]
 
     # -- single steps ----------------------------------------------------------------
     def grid_row(self, y, z):

@@ -19,6 +19,7 @@
  *                  merged tracks across sector frames (orc_merge_frame)
  *   9. hit removal keep only the clusters near good tracks, compression strategy B
  *                  (orc_reject_frame)
+ *  10. residuals   track-model compression of the attached clusters (orc_compress_frame)
  */
 #include "orc.h"
 
@@ -1272,4 +1273,47 @@ int64_t orc_reject_frame(const orc_cfg* cfg, int64_t n, const float* y, const fl
     free(row);
     free(sidx);
     return kept;
+}
+
+/* ---------------------------------------------------------------------------------- */
+/* Step 10: track-model compression (Sec. 4): residuals of the attached clusters to the  */
+/* track's helix, quantised.  See orc.h for the definition.                               */
+/* ---------------------------------------------------------------------------------- */
+int orc_compress_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
+                       const int64_t* row_off, const orc_tracks* trk, int32_t* codes, double* resid,
+                       double* pred)
+{
+    const int nr = cfg->n_rows, ns = cfg->n_sectors;
+    if (row_off[0] != 0 || row_off[(int64_t)ns * nr] != n || !(cfg->resid_step > 0)) return -1;
+    const double step = cfg->resid_step, lim = 1073741824.0;   /* 2^30 */
+    for (int64_t t = 0; t < trk->n_tracks; ++t) {
+        const int s = trk->sector[t];
+        if (s < 0 || s >= ns) return -1;
+        for (int64_t j = trk->hit_off[t]; j < trk->hit_off[t + 1]; ++j) {
+            const int64_t h = trk->hit_ids[j];
+            if (h < row_off[(int64_t)s * nr] || h >= row_off[(int64_t)(s + 1) * nr]) return -1;
+            int r = 0;
+            while (row_off[(int64_t)s * nr + r + 1] <= h) ++r;
+            kstate st;
+            st.x = (orc_real)trk->x_ref[t];
+            for (int i = 0; i < 5; ++i) st.p[i] = (orc_real)trk->params[t * 5 + i];
+            for (int i = 0; i < 15; ++i) st.C[i] = 0;
+            double yp = (double)st.p[0], zp = (double)st.p[1];
+            if (kprop(cfg, &st, (orc_real)cfg->row_x[r], NULL) == 0) {
+                yp = (double)st.p[0];
+                zp = (double)st.p[1];
+            }
+            const double ry = ((double)y[h] - yp) / step, rz = ((double)z[h] - zp) / step;
+            double qy = floor(ry + 0.5), qz = floor(rz + 0.5);
+            if (qy > lim) qy = lim;
+            if (qy < -lim) qy = -lim;
+            if (qz > lim) qz = lim;
+            if (qz < -lim) qz = -lim;
+            codes[2 * j] = (int32_t)qy;
+            codes[2 * j + 1] = (int32_t)qz;
+            if (resid) { resid[2 * j] = ry; resid[2 * j + 1] = rz; }
+            if (pred) { pred[2 * j] = yp; pred[2 * j + 1] = zp; }
+        }
+    }
+    return 0;
 }

@@ -53,6 +53,8 @@ typedef struct {
     /* hit removal, strategy B (orc_reject_frame) */
     double reject_pt_min;     /* good tracks have pT >= this (GeV/c)                 */
     double reject_window;     /* half-width in y and z of a good track's vicinity (cm) */
+    /* track-model compression (orc_compress_frame) */
+    double resid_step;        /* quantisation step of the residuals (cm)             */
 } orc_cfg;
 
 typedef struct {
@@ -193,6 +195,18 @@ int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
  * input. */
 int64_t orc_reject_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
                          const int64_t* row_off, const orc_tracks* trk, int brute, uint8_t* keep);
+
+/* Track-model compression (Sec. 4, entropy reduction): every cluster attached to a track
+ * is stored as its residual to the track's position on the cluster's row plane, the
+ * position being the track's state at x_ref (which the compressed stream keeps with the
+ * track) propagated in one helix step to the row (or the state at x_ref itself where that
+ * step fails).  Codes: q = floor(r / resid_step + 1/2) for r = y - y_p and r = z - z_p,
+ * clamped to [-2^30, 2^30].  codes: [n_hits][2] in hit-list order; resid (or NULL):
+ * [n_hits][2] the unrounded r / resid_step.  Decoding: y = y_p + q_y * resid_step.
+ * pred (or NULL): [n_hits][2] the positions y_p, z_p.  Returns 0 or -1. */
+int orc_compress_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
+                       const int64_t* row_off, const orc_tracks* trk, int32_t* codes, double* resid,
+                       double* pred);
 
 #ifdef __cplusplus
 }

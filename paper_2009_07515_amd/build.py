@@ -11,7 +11,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = [os.path.join(PKG, "csrc", f) for f in ("tpcsf_kernels.hip", "tpcsf_merge.hip", "tpcsf_host.hip",
+SRC = [os.path.join(PKG, "csrc", f) for f in ("tpcsf_kernels.hip", "tpcsf_merge.hip", "tpcsf_compress.hip", "tpcsf_host.hip",
                                                         "tpcsf_server.hip")]
 LIB = os.path.join(PKG, "libtpcsf.so")
 ARCH = os.environ.get("TPCSF_OFFLOAD_ARCH", "gfx950")

@@ -218,6 +218,7 @@ bool params_ok(const tpcsf_params* p)
         if (!(p->c0[i] > 0)) return false;
     if (!(p->merge_edge >= 0 && p->merge_window >= 0 && p->merge_chi2 >= 0)) return false;
     if (!(p->reject_pt_min >= 0 && p->reject_window >= 0 && p->reject_window < 1e4)) return false;
+    if (!(p->resid_step > 1e-9 && p->resid_step < 1e4)) return false;
     return p->min_chain >= 3 && p->min_track_hits >= 3 && p->max_miss >= 0;
 }
 
@@ -566,6 +567,52 @@ extern "C" tpcsf_status tpcsf_reject(tpcsf_ctx* c, const tpcsf_frame* f, const t
     return TPCSF_OK;
 }
 
+extern "C" tpcsf_status tpcsf_compress(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks* t, int32_t* codes,
+                                       uint8_t* rows, void* stream)
+{
+    if (!c) return TPCSF_E_INVALID;
+    if (!f || !t) return fail(c, TPCSF_E_INVALID, "null frame or tracks");
+    if (f->n_tf < 1 || !f->row_offsets || f->n_clusters < 0 || (f->n_clusters > 0 && (!f->y || !f->z)))
+        return fail(c, TPCSF_E_INVALID, "frame incomplete");
+    if (t->cap_tracks < 0 || t->cap_hits < 0 || !t->n_tracks || !t->hit_off)
+        return fail(c, TPCSF_E_INVALID, "track input incomplete");
+    if (t->cap_tracks > 0 && (!t->params || !t->x_ref || !t->sector || !t->tf || !t->hit_ids))
+        return fail(c, TPCSF_E_INVALID, "track input arrays missing");
+    if (t->cap_hits > 0 && (!codes || !rows)) return fail(c, TPCSF_E_INVALID, "code outputs missing");
+    CompressArgs A{};
+    A.n_tracks = t->n_tracks; A.cap_tracks = t->cap_tracks; A.cap_hits = t->cap_hits;
+    A.par = t->params; A.xref = t->x_ref; A.sector = t->sector; A.tf = t->tf;
+    A.hit_off = t->hit_off; A.hit_ids = t->hit_ids;
+    A.y = f->y; A.z = f->z; A.off = f->row_offsets; A.n_tf = f->n_tf;
+    A.step = c->params.resid_step;
+    A.codes = codes; A.rows = rows;
+    launch_compress(A, dev_params(c), c->n_cu, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "compress kernel launch");
+    return TPCSF_OK;
+}
+
+extern "C" tpcsf_status tpcsf_decompress(tpcsf_ctx* c, const tpcsf_tracks* t, const int32_t* codes,
+                                         const uint8_t* rows, double* yz, void* stream)
+{
+    if (!c) return TPCSF_E_INVALID;
+    if (!t || t->cap_tracks < 0 || t->cap_hits < 0 || !t->n_tracks || !t->hit_off)
+        return fail(c, TPCSF_E_INVALID, "track input incomplete");
+    if (t->cap_tracks > 0 && (!t->params || !t->x_ref)) return fail(c, TPCSF_E_INVALID, "track input arrays missing");
+    if (t->cap_hits > 0 && (!codes || !rows || !yz)) return fail(c, TPCSF_E_INVALID, "code arrays missing");
+    CompressArgs A{};
+    A.n_tracks = t->n_tracks; A.cap_tracks = t->cap_tracks; A.cap_hits = t->cap_hits;
+    A.par = t->params; A.xref = t->x_ref; A.hit_off = t->hit_off;
+    A.step = c->params.resid_step;
+    A.codes = const_cast<int32_t*>(codes);
+    A.rows = const_cast<uint8_t*>(rows);
+    A.yz = yz;
+    launch_decompress(A, dev_params(c), c->n_cu, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "decompress kernel launch");
+    return TPCSF_OK;
+}
+
 extern "C" tpcsf_status tpcsf_merge_work(tpcsf_ctx* c, int64_t* work6)
 {
     if (!c || !work6) return TPCSF_E_INVALID;
@@ -599,6 +646,7 @@ void tpcsf_default_params(tpcsf_params* p)
     p->merge_chi2 = 30.0;
     p->reject_pt_min = 0.05;
     p->reject_window = 1.0;
+    p->resid_step = 0.01;
 }
 
 void tpcsf_default_tuning(tpcsf_tuning* t)

@@ -249,6 +249,22 @@ struct RejectArgs {
 };
 void launch_reject(const Batch& b, const DevParams& p, const RejectArgs& r, const LaunchCfg& c, hipStream_t s);
 
+// Track-model compression (tpcsf_compress / tpcsf_decompress).
+struct CompressArgs {
+    const int64_t* n_tracks; int64_t cap_tracks, cap_hits;
+    const double* par; const double* xref;
+    const int32_t* sector; const int32_t* tf;
+    const int64_t* hit_off; const int32_t* hit_ids;   // encode only
+    const float* y; const float* z; const int64_t* off; // encode only
+    int32_t n_tf;
+    double step;
+    int32_t* codes;                 // [cap_hits][2]: written by encode, read by decode
+    uint8_t* rows;                  // [cap_hits]: written by encode, read by decode
+    double* yz;                     // [cap_hits][2]: written by decode
+};
+void launch_compress(const CompressArgs& a, const DevParams& p, int n_cu, hipStream_t s);
+void launch_decompress(const CompressArgs& a, const DevParams& p, int n_cu, hipStream_t s);
+
 // Stage launchers (all asynchronous on `stream`).  Row ranges are [g0, g1).
 // Allows the grid kernel the device's LDS per block; returns the dynamic LDS bytes to use.
 int grid_lds_setup(int max_lds_per_block);

@@ -38,7 +38,7 @@ class Params(C.Structure):
                 ("sinphi_max", C.c_double), ("nsig", C.c_double), ("c0", C.c_double * 5),
                 ("min_chain", C.c_int32), ("min_track_hits", C.c_int32), ("max_miss", C.c_int32),
                 ("merge_edge", C.c_double), ("merge_window", C.c_double), ("merge_chi2", C.c_double),
-                ("reject_pt_min", C.c_double), ("reject_window", C.c_double)]
+                ("reject_pt_min", C.c_double), ("reject_window", C.c_double), ("resid_step", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -125,6 +125,10 @@ def load():
     lib.tpcsf_merge_work.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.tpcsf_reject.argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), vp, vp, vp]
     lib.tpcsf_reject.restype = C.c_int
+    lib.tpcsf_compress.argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), vp, vp, vp]
+    lib.tpcsf_compress.restype = C.c_int
+    lib.tpcsf_decompress.argtypes = [vp, C.POINTER(TracksDesc), vp, vp, vp, vp]
+    lib.tpcsf_decompress.restype = C.c_int
     lib.tpcsf_merge_work.restype = C.c_int
     lib.tpcsf_sync.argtypes = [vp, vp]
     lib.tpcsf_sync.restype = C.c_int
@@ -423,6 +427,41 @@ class Tracker:
         self.launch_reject(frame, tracks, keep, n_kept, stream)
         self.sync(stream)
         return keep[:frame.n_clusters], int(n_kept.item())
+
+    def launch_compress(self, frame: DeviceFrame, tracks: TrackBuffers, codes, rows, stream=None):
+        fd, td = frame.desc(), tracks.desc()
+        self._check(self.lib.tpcsf_compress(self.h, C.byref(fd), C.byref(td), _ptr(codes), _ptr(rows),
+                                            self._stream(stream)))
+
+    def launch_decompress(self, tracks: TrackBuffers, codes, rows, yz, stream=None):
+        td = tracks.desc()
+        self._check(self.lib.tpcsf_decompress(self.h, C.byref(td), _ptr(codes), _ptr(rows), _ptr(yz),
+                                              self._stream(stream)))
+
+    def compress(self, frame: DeviceFrame, tracks: TrackBuffers, stream=None):
+        """Residual codes [H, 2] (int32) and rows [H] (uint8) of the tracks' clusters, in
+        hit-list order (synchronises)."""
+        import torch
+        H = max(tracks.cap_hits, 1)
+        codes = torch.empty((H, 2), dtype=torch.int32, device=frame.y.device)
+        rows = torch.empty(H, dtype=torch.uint8, device=frame.y.device)
+        self.launch_compress(frame, tracks, codes, rows, stream)
+        self.sync(stream)
+        n = int(tracks.n_hits.item())
+        return codes[:n], rows[:n]
+
+    def decompress(self, tracks: TrackBuffers, codes, rows, stream=None):
+        """Decoded cluster positions [H, 2] (float64) from the codes and rows (synchronises)."""
+        import torch
+        H = max(tracks.cap_hits, 1)
+        c = torch.zeros((H, 2), dtype=torch.int32, device=codes.device)
+        r = torch.zeros(H, dtype=torch.uint8, device=codes.device)
+        c[:codes.shape[0]] = codes
+        r[:rows.shape[0]] = rows
+        yz = torch.empty((H, 2), dtype=torch.float64, device=codes.device)
+        self.launch_decompress(tracks, c, r, yz, stream)
+        self.sync(stream)
+        return yz[:codes.shape[0]]
 
     def merge_work(self):
         w = (C.c_int64 * 6)()
