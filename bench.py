@@ -103,15 +103,23 @@ def stage_flops(c):
             + FLOPS_CHI2 * w["fit_chi2"]}
 
 
+def kernel_source_sha():
+    """sha256 over the tracking kernels' sources (kernels, then the shared Kalman code)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("tpcsf_kernels.hip", "tpcsf_kalman.h"):
+        h.update(open(os.path.join(ROOT, "paper_2009_07515_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def profiled_traffic(kernel):
     """HBM bytes per launch of `kernel` (calibrated FETCH_SIZE + WRITE_SIZE) from the
     committed rocprofv3 summary, or None if the kernels changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "tpcsf_cfg3_counters.txt")
-    src = os.path.join(ROOT, "paper_2009_07515_amd", "csrc", "tpcsf_kernels.hip")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_sha()
     rec = {}
     for ln in open(path):
         f = ln.split()
