@@ -158,6 +158,44 @@ def cpu_baseline(f, budget_s, max_sectors):
                        f"({done_cl} clusters, {done_t:.1f} s)")
 
 
+def cpu_next_stages(f):
+    """The oracle's merge, hit removal and compression timed on sectors 0 and 1 of the same
+    frame (two neighbours, so that tracks cross their shared edge), after its tracking."""
+    import oracle
+    from paper_2009_07515_amd import synth
+    o = oracle.Oracle(synth.row_x())
+    R = 36 * 152
+    counts = np.diff(f.row_off)
+    sub = np.zeros(R, np.int64)
+    sub[:2 * 152] = counts[:2 * 152]
+    b = int(f.row_off[2 * 152])
+    ro = np.concatenate([[0], np.cumsum(sub)]).astype(np.int64)
+    y, z = f.y[:b], f.z[:b]
+    t0 = time.perf_counter()
+    r = o.track_frame(y, z, ro)
+    t_track = time.perf_counter() - t0
+    out = {}
+    t0 = time.perf_counter()
+    m = o.merge_frame(y, z, ro, r)
+    t = time.perf_counter() - t0
+    out["merge"] = {"value": r["n_tracks"] / t, "unit": "sector tracks/s", "seconds": t,
+                    "merged_of_several": int((m["n_segments"] >= 2).sum())}
+    t0 = time.perf_counter()
+    o.reject_frame(y, z, ro, r)
+    t = time.perf_counter() - t0
+    out["reject"] = {"value": b / t, "unit": "clusters/s", "seconds": t}
+    t0 = time.perf_counter()
+    o.compress_frame(y, z, ro, r)
+    t = time.perf_counter() - t0
+    out["compress"] = {"value": r["n_hits"] / t, "unit": "attached clusters/s", "seconds": t}
+    out["sample"] = (f"FP64 oracle, 1 thread, sectors 0 and 1 of the same time frame ({b} clusters, "
+                     f"{r['n_tracks']} tracks; tracking them took {t_track:.1f} s, not counted)")
+    out["cores"] = 1
+    log(f"oracle next stages on sectors 0-1: merge {out['merge']['seconds']:.2f} s, reject "
+        f"{out['reject']['seconds']:.2f} s, compress {out['compress']['seconds']:.2f} s")
+    return out
+
+
 def serve(f_main, tuning, batched_rate, seconds, n_slots):
     """Serving run over a pool of frames (this time frame and three frames of the uneven
     pp / Pb-Pb mix).  The server's capacity is measured first with every slot kept busy;
@@ -436,7 +474,14 @@ def main():
             pr = k / k.sum()
             return float(-(pr * np.log2(pr)).sum())
 
-        compress = {"encode_ms": c_ms, "decode_ms": d_ms, "calls": args.compress_steps, "clusters": H,
+        # encode, per launch: per cluster the hit index (4 B), y and z (8 B), the codes (8 B)
+        # and the row (1 B); per track its state, x_ref, sector, time frame, hit range (72 B)
+        enc_bytes = 21 * H + 72 * T0
+        enc_gbs = enc_bytes / (c_ms * 1e-3) / 1e9
+        compress = {"roofline": {"bound": "hbm", "kernel": "c_encode", "achieved": enc_gbs, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": enc_gbs / HBM_PEAK_GBS, "traffic": profiled_traffic("c_encode"),
+                                 "algorithmic_bytes_per_launch": enc_bytes, "launch_ms": c_ms},
+                    "encode_ms": c_ms, "decode_ms": d_ms, "calls": args.compress_steps, "clusters": H,
                     "clusters_per_s": H / (c_ms * 1e-3), "step_cm": step, "max_decode_error_cm": err,
                     "bits_residual": [entropy(q[:, 0]), entropy(q[:, 1])],
                     "bits_absolute": [entropy(np.floor(f.y[hid] / step)), entropy(np.floor(f.z[hid] / step))]}
@@ -463,7 +508,14 @@ def main():
         trk.sync()
         r_ms = e0.elapsed_time(e1) / args.reject_steps
         assert int(n_kept.item()) == kept
-        reject = {"ms_per_call": r_ms, "calls": args.reject_steps, "clusters": N, "kept": kept,
+        # per call: y, z, cluster->track map, keep flag and the bin-order mark of every
+        # cluster (15 B); per track its state and hit range (64 B)
+        rej_bytes = 15 * N + 64 * T0
+        rej_gbs = rej_bytes / (r_ms * 1e-3) / 1e9
+        reject = {"roofline": {"bound": "hbm", "kernel": "r_mark + r_final", "achieved": rej_gbs,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rej_gbs / HBM_PEAK_GBS,
+                               "traffic": None, "algorithmic_bytes_per_launch": rej_bytes, "launch_ms": r_ms},
+                  "ms_per_call": r_ms, "calls": args.reject_steps, "clusters": N, "kept": kept,
                   "kept_fraction": kept / N, "clusters_per_s": N / (r_ms * 1e-3)}
         log(f"reject: kept {kept} of {N} ({kept / N:.3f}) in {r_ms:.3f} ms")
 
@@ -489,7 +541,14 @@ def main():
         m_ms = e0.elapsed_time(e1) / args.merge_steps
         assert int(mb.n_merged.item()) == M
         w = trk.merge_work()
-        merge = {"ms_per_call": m_ms, "calls": args.merge_steps, "sector_tracks": T0, "merged_tracks": M,
+        # binary64 operations: per gate pair a propagation (182) and a 5x5 chi2 (155); per
+        # refit rotation 60, propagation 182, update 121
+        m_flops = 337 * int(w[0]) + 60 * int(w[3]) + 182 * int(w[4]) + 121 * int(w[5])
+        m_tfs = m_flops / (m_ms * 1e-3) / 1e12
+        merge = {"roofline": {"bound": "alu", "kernel": "merge (all kernels)", "achieved": m_tfs,
+                              "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": m_tfs / FP64_PEAK_TFS,
+                              "traffic": None, "algorithmic_flops_per_launch": m_flops, "launch_ms": m_ms},
+                 "ms_per_call": m_ms, "calls": args.merge_steps, "sector_tracks": T0, "merged_tracks": M,
                  "merged_of_several": n_multi, "tracks_per_s": T0 / (m_ms * 1e-3),
                  "work": {"gate_pairs": int(w[0]), "match_propagations": int(w[1]), "match_chi2": int(w[2]),
                           "fit_rotations": int(w[3]), "fit_propagations": int(w[4]), "fit_updates": int(w[5])}}
@@ -530,6 +589,7 @@ def main():
         line["serving"] = serve(f, trk.tuning.as_dict(), value, args.serve_seconds, args.serve_slots)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f, args.cpu_budget, args.cpu_sectors)
+        line["cpu_baseline"]["next_stages"] = cpu_next_stages(f)
     print(json.dumps(line), flush=True)
 
 
