@@ -444,7 +444,10 @@ def main():
     # and the bits per coordinate of the codes against absolute coordinates at the same step
     compress = None
     if args.compress_steps > 0:
-        trk.track(frame, out=out)
+        # the tracks with their per-hit records, which the encoder reads
+        out_r = tpcsf.TrackBuffers(N, hit_rec=True)
+        trk.track(frame, out=out_r)
+        out = out_r
         H = int(out.n_hits.item())
         codes = torch.empty((max(out.cap_hits, 1), 2), dtype=torch.int32, device="cuda:0")
         rows = torch.empty(max(out.cap_hits, 1), dtype=torch.uint8, device="cuda:0")
@@ -524,7 +527,7 @@ def main():
     # the merge needs.  Not part of the step above.
     merge = None
     if args.merge_steps > 0:
-        tb = tpcsf.TrackBuffers(N, outer=True)
+        tb = tpcsf.TrackBuffers(N, outer=True, hit_rec=True)
         trk.track(frame, out=tb)
         mb = tpcsf.MergedBuffers(tb)
         mres = trk.merge(frame, tb, out=mb)

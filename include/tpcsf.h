@@ -134,6 +134,10 @@ typedef struct {
                                            cluster's row (input of tpcsf_merge)            */
     double* cov_outer;                  /* [device] [cap_tracks][15] or NULL: its
                                            covariance                                      */
+    float* hit_rec;                     /* [device] [cap_hits][4] or NULL: per hit, in
+                                           hit_ids order, the cluster's y, z, its row
+                                           plane x and its batch index (int32 bits); read
+                                           by tpcsf_merge and tpcsf_compress when given    */
 } tpcsf_tracks;
 
 /* Defaults of the method constants and of the tuning. */

@@ -336,6 +336,7 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.o_zbeam = o->z_beam;
     B.o_par_out = outer ? o->params_outer : nullptr;
     B.o_cov_out = outer ? o->cov_outer : nullptr;
+    B.o_hit_rec = (float4*)o->hit_rec;
     B.d_up = (int32_t*)(a + L.d_up); B.d_dn = (int32_t*)(a + L.d_dn);
     B.d_cup = (int32_t*)(a + L.d_cup); B.d_cdn = (int32_t*)(a + L.d_cdn);
     B.d_start_row = (int32_t*)(a + L.d_start_row);
@@ -379,7 +380,8 @@ struct MergeLayout {
     size_t total = 0;
     size_t ends, a_list, b_list, sec_first, cnt, brec, bidx, brec_s, bidx_s, zs, lsorted, mstate, bestB, bestChi,
         keepChi, keepA;
-    size_t next, prev, nseg, chain_hits, fit_ok, diss, lead, nh, fit_list, fit_off, grec, m_idx, m_hpos, scan_part;
+    size_t next, prev, nseg, chain_hits, fit_ok, diss, lead, nh, fit_list, seg_head, seg_pre, fit_off, grec, m_idx,
+        m_hpos, scan_part;
 };
 
 MergeLayout make_merge_layout(int64_t T, int64_t K, int64_t H)
@@ -413,6 +415,8 @@ MergeLayout make_merge_layout(int64_t T, int64_t K, int64_t H)
     L.lead = take(t * 4);
     L.nh = take(t * 4);
     L.fit_list = take(t * 4);
+    L.seg_head = take(t * 4);
+    L.seg_pre = take(t * 4);
     L.fit_off = take(t * 8);
     L.grec = take((size_t)(H > 0 ? H : 1) * 16);
     L.m_idx = take(t * 8);
@@ -480,6 +484,7 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     M.par = t->params; M.cov = t->cov; M.xref = t->x_ref; M.chi2 = t->chi2;
     M.sector = t->sector; M.tf = t->tf;
     M.par_out = t->params_outer; M.cov_out = t->cov_outer;
+    M.hit_rec = (const float4*)t->hit_rec;
     M.n_tf = f->n_tf;
     M.ends = (float4*)(a + L.ends);
     M.a_list = (int32_t*)(a + L.a_list);
@@ -506,6 +511,8 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     M.lead = (int32_t*)(a + L.lead);
     M.nh = (int32_t*)(a + L.nh);
     M.fit_list = (int32_t*)(a + L.fit_list);
+    M.seg_head = (int32_t*)(a + L.seg_head);
+    M.seg_pre = (int32_t*)(a + L.seg_pre);
     M.fit_off = (int64_t*)(a + L.fit_off);
     M.grec = (float4*)(a + L.grec);
     M.m_idx = (int64_t*)(a + L.m_idx);
@@ -584,6 +591,7 @@ extern "C" tpcsf_status tpcsf_compress(tpcsf_ctx* c, const tpcsf_frame* f, const
     A.par = t->params; A.xref = t->x_ref; A.sector = t->sector; A.tf = t->tf;
     A.hit_off = t->hit_off; A.hit_ids = t->hit_ids;
     A.y = f->y; A.z = f->z; A.off = f->row_offsets; A.n_tf = f->n_tf;
+    A.hit_rec = (const float4*)t->hit_rec;
     A.step = c->params.resid_step;
     A.codes = codes; A.rows = rows;
     launch_compress(A, dev_params(c), c->n_cu, (hipStream_t)stream);

@@ -125,6 +125,7 @@ struct Batch {
     double* o_zbeam;                // may be null
     double* o_par_out;              // may be null
     double* o_cov_out;              // may be null
+    float4* o_hit_rec;              // may be null
     // verification views in input order (filled only by launch_debug_views)
     int32_t* d_up; int32_t* d_dn; int32_t* d_cup; int32_t* d_cdn;   // [N]
     int32_t* d_start_row; int32_t* d_start_idx; int32_t* d_tl_n;     // [cap_starts] by rank
@@ -193,6 +194,7 @@ struct MergeBatch {
     const double* par; const double* cov; const double* xref; const double* chi2;
     const int32_t* sector; const int32_t* tf;
     const double* par_out; const double* cov_out;
+    const float4* hit_rec;          // per hit (y, z, row plane x, index), or null
     int32_t n_tf;
     // scratch
     float4* ends;                   // [T] innermost (x, y) and outermost (x, y) cluster
@@ -215,6 +217,8 @@ struct MergeBatch {
     int32_t* nseg; int32_t* chain_hits; int32_t* fit_ok; int32_t* diss;
     int32_t* lead; int32_t* nh;     // scan inputs
     int32_t* fit_list;
+    int32_t* seg_head;              // [T] head of the chain a track belongs to, or -1
+    int32_t* seg_pre;               // [T] clusters of the chain before this track
     int64_t* fit_off;               // [T] first gathered record of a chain head
     float4* grec;                   // [input cap_hits] clusters of the chains to refit, in
                                     //     chain order: y, z, row plane x, sector (as bits)
@@ -256,6 +260,7 @@ struct CompressArgs {
     const int32_t* sector; const int32_t* tf;
     const int64_t* hit_off; const int32_t* hit_ids;   // encode only
     const float* y; const float* z; const int64_t* off; // encode only
+    const float4* hit_rec;          // encode: per hit (y, z, row plane x, index), or null
     int32_t n_tf;
     double step;
     int32_t* codes;                 // [cap_hits][2]: written by encode, read by decode

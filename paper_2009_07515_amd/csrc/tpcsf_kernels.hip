@@ -1607,7 +1607,11 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
             todo &= todo - 1ull;
             const int64_t d = __shfl(hp, l, 64), sj = __shfl(src, l, 64);
             const int m = __shfl(nk, l, 64);
-            for (int q = lane; q < m; q += 64) B.o_hit_ids[d + q] = __float_as_int(B.kept_list[sj + q].w);
+            for (int q = lane; q < m; q += 64) {
+                const float4 e = B.kept_list[sj + q];
+                B.o_hit_ids[d + q] = __float_as_int(e.w);
+                if (B.o_hit_rec) B.o_hit_rec[d + q] = e;
+            }
         }
     }
 }

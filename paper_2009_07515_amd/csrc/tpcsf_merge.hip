@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_init(MergeBatch M, int64_t 
         M.diss[i] = 0;
         M.fit_ok[i] = 0;
         M.nseg[i] = 0;
+        M.seg_head[i] = -1;
     }
     for (int64_t i = i0; i < n_lists; i += stride) M.cnt[i] = 0;
 }
@@ -448,40 +449,52 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_chain(MergeBatch M)
             M.fit_list[atomicAdd(&M.mc->n_fit, 1)] = (int32_t)t;
             M.fit_off[t] = (int64_t)atomicAdd(&M.mc->fit_hits, (unsigned long long)nh);
         }
+        // every segment's chain head and the clusters before it in the chain
+        int32_t pre = 0;
+        u = (int32_t)t;
+        for (int k = 0; k < ns; ++k, u = M.next[u]) {
+            M.seg_head[u] = (int32_t)t;
+            M.seg_pre[u] = pre;
+            pre += (int32_t)(M.hit_off[u + 1] - M.hit_off[u]);
+        }
     }
 }
 
 // ------------------------------------------------------------------------------------
 // 7a: the clusters of every chain to refit, in chain order, as records (y, z, row plane x,
-// sector); one wave per chain, 64 clusters per pass
+// sector); one wave per track of such a chain, 64 clusters per pass, the rows found in
+// the sector's row offsets staged in the wave's LDS
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kMergeThreads) k_m_gather(MergeBatch M, DevParams P)
 {
-    if (M.mc->bad) return;
     __shared__ int64_t offs[kMergeThreads / 64][kMaxRows + 1];
+    if (M.mc->bad) return;
     const int nr = P.n_rows, ns = P.n_sectors;
-    const int64_t nf = M.mc->n_fit;
+    const int64_t T = M.mc->T;
     const int lane = threadIdx.x & 63;
     int64_t* o = offs[threadIdx.x >> 6];
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < nf; i += nw) {
-        const int32_t t = M.fit_list[i];
-        const int64_t tfb = (int64_t)M.tf[t] * ns;
-        int64_t k = M.fit_off[t];
-        int32_t u = t;
-        for (int seg = 0; u >= 0 && seg < M.nseg[t]; ++seg, u = M.next[u]) {
-            const int su = M.sector[u];
-            const int64_t g0 = (tfb + su) * nr;
-            // the sector's row offsets in this wave's LDS slot
-            wave_lds_sync();
-            for (int r = lane; r <= nr; r += 64) o[r] = M.off[g0 + r];
-            wave_lds_sync();
-            const int64_t hb = M.hit_off[u], n = M.hit_off[u + 1] - hb;
+    for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < T; u += nw) {
+        const int32_t head = M.seg_head[u];
+        if (head < 0 || M.nseg[head] < 2) continue;
+        const int su = M.sector[u];
+        const int64_t k = M.fit_off[head] + M.seg_pre[u];
+        const int64_t hb = M.hit_off[u], n = M.hit_off[u + 1] - hb;
+        if (M.hit_rec) {
+            // the tracking call's own records of these clusters, contiguous
             for (int64_t j = lane; j < n; j += 64) {
-                const int64_t h = M.hit_ids[hb + j];
-                M.grec[k + j] = make_float4(M.y[h], M.z[h], P.rx[row_of(o, 0, nr, h)], __int_as_float(su));
+                const float4 e = M.hit_rec[hb + j];
+                M.grec[k + j] = make_float4(e.x, e.y, e.z, __int_as_float(su));
             }
-            k += n;
+            continue;
+        }
+        const int64_t g0 = ((int64_t)M.tf[u] * ns + su) * nr;
+        wave_lds_sync();
+        for (int r = lane; r <= nr; r += 64) o[r] = M.off[g0 + r];
+        wave_lds_sync();
+        for (int64_t j = lane; j < n; j += 64) {
+            const int64_t h = M.hit_ids[hb + j];
+            M.grec[k + j] = make_float4(M.y[h], M.z[h], P.rx[row_of(o, 0, nr, h)], __int_as_float(su));
         }
     }
 }
@@ -629,75 +642,75 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_lead(MergeBatch M)
     }
 }
 
-// 9: merged tracks at their scanned positions: records per lane, then each written
-// track's clusters copied by the whole wave, segment by segment
+// 9: merged tracks at their scanned positions (lane per merged track)
 __global__ void __launch_bounds__(kMergeThreads) k_m_emit(MergeBatch M, DevParams P)
 {
     if (M.mc->bad) return;
     const int64_t T = M.mc->T;
-    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (blockIdx.x == 0 && threadIdx.x == 0 && M.cap_merged >= 0) M.o_hit_off[0] = 0;
-    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < T; t0 += stride) {
-        const int64_t t = t0 + lane;
-        bool on = t < T;
-        int64_t m = 0, hp = 0;
-        int32_t nseg = 1;
-        if (on) {
-            if (M.o_next) {
-                M.o_next[t] = M.next[t];
-                if (M.o_link_chi2) M.o_link_chi2[t] = M.next[t] >= 0 ? M.bestChi[t] : 0.0;
-            }
-            on = M.lead[t] != 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += stride) {
+        if (M.o_next) {
+            M.o_next[t] = M.next[t];
+            if (M.o_link_chi2) M.o_link_chi2[t] = M.next[t] >= 0 ? M.bestChi[t] : 0.0;
         }
-        if (on) {
-            m = M.m_idx[t];
-            hp = M.m_hpos[t];
-            const int32_t nh = M.nh[t];
-            if (m >= M.cap_merged || hp + nh > M.cap_hits) {
-                atomicOr(&M.ctr->err, kErrOutCap);
-                on = false;
-            } else {
-                const bool whole = M.prev[t] < 0 && M.nseg[t] >= 2 && M.fit_ok[t];
-                const double* src_p;
-                if (whole) {
-                    const double* ms = M.mstate + t * 21;
-                    for (int q = 0; q < 5; ++q) M.o_par[m * 5 + q] = ms[q];
-                    for (int q = 0; q < 15; ++q) M.o_cov[m * 15 + q] = ms[5 + q];
-                    M.o_chi2[m] = ms[20];
-                    nseg = M.nseg[t];
-                    src_p = ms;
-                } else {
-                    for (int q = 0; q < 5; ++q) M.o_par[m * 5 + q] = M.par[t * 5 + q];
-                    for (int q = 0; q < 15; ++q) M.o_cov[m * 15 + q] = M.cov[t * 15 + q];
-                    M.o_chi2[m] = M.chi2[t];
-                    src_p = M.par + t * 5;
-                }
-                M.o_nseg[m] = nseg;
-                M.o_xref[m] = M.xref[t];
-                if (M.o_zbeam) M.o_zbeam[m] = trk_beamline_z(P, M.xref[t], src_p);
-                M.o_ndf[m] = 2 * nh - 5;
-                M.o_nhits_trk[m] = nh;
-                M.o_sector[m] = M.sector[t];
-                M.o_tf[m] = M.tf[t];
-                M.o_hit_off[m + 1] = hp + nh;
-            }
+        if (!M.lead[t]) continue;
+        const int64_t m = M.m_idx[t], hp = M.m_hpos[t];
+        const int32_t nh = M.nh[t];
+        if (m >= M.cap_merged || hp + nh > M.cap_hits) {
+            atomicOr(&M.ctr->err, kErrOutCap);
+            continue;
         }
-        uint64_t todo = __ballot(on);
-        while (todo) {
-            const int l = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1ull;
-            int32_t u = (int32_t)__shfl(t, l, 64);
-            const int64_t mm = __shfl(m, l, 64);
-            int64_t k = __shfl(hp, l, 64);
-            const int32_t ns_l = __shfl(nseg, l, 64);
-            for (int seg = 0; u >= 0 && seg < ns_l; ++seg, u = M.next[u]) {
-                if (lane == 0) M.o_track_merged[u] = (int32_t)mm;
-                const int64_t hb = M.hit_off[u], n = M.hit_off[u + 1] - hb;
-                for (int64_t j = lane; j < n; j += 64) M.o_hit_ids[k + j] = M.hit_ids[hb + j];
-                k += n;
-            }
+        const bool whole = M.prev[t] < 0 && M.nseg[t] >= 2 && M.fit_ok[t];
+        const double* src_p;
+        if (whole) {
+            const double* ms = M.mstate + t * 21;
+            for (int q = 0; q < 5; ++q) M.o_par[m * 5 + q] = ms[q];
+            for (int q = 0; q < 15; ++q) M.o_cov[m * 15 + q] = ms[5 + q];
+            M.o_chi2[m] = ms[20];
+            src_p = ms;
+        } else {
+            for (int q = 0; q < 5; ++q) M.o_par[m * 5 + q] = M.par[t * 5 + q];
+            for (int q = 0; q < 15; ++q) M.o_cov[m * 15 + q] = M.cov[t * 15 + q];
+            M.o_chi2[m] = M.chi2[t];
+            src_p = M.par + t * 5;
         }
+        M.o_nseg[m] = whole ? M.nseg[t] : 1;
+        M.o_xref[m] = M.xref[t];
+        if (M.o_zbeam) M.o_zbeam[m] = trk_beamline_z(P, M.xref[t], src_p);
+        M.o_ndf[m] = 2 * nh - 5;
+        M.o_nhits_trk[m] = nh;
+        M.o_sector[m] = M.sector[t];
+        M.o_tf[m] = M.tf[t];
+        M.o_hit_off[m + 1] = hp + nh;
+    }
+}
+
+// 10: every input track's clusters into its merged track's hit list, and its entry in the
+// input-to-merged map; one wave per input track
+__global__ void __launch_bounds__(kMergeThreads) k_m_copy(MergeBatch M)
+{
+    if (M.mc->bad) return;
+    const int64_t T = M.mc->T;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < T; u += nw) {
+        const int32_t head = M.seg_head[u];
+        if (head < 0) continue;
+        const bool whole = M.prev[head] < 0 && M.nseg[head] >= 2 && M.fit_ok[head];
+        int64_t m, dst;
+        if (whole) {
+            m = M.m_idx[head];
+            dst = M.m_hpos[head] + M.seg_pre[u];
+        } else {
+            if (!M.lead[u]) continue;
+            m = M.m_idx[u];
+            dst = M.m_hpos[u];
+        }
+        const int64_t hb = M.hit_off[u], n = M.hit_off[u + 1] - hb;
+        if (m >= M.cap_merged || dst + n > M.cap_hits) continue;
+        if (lane == 0) M.o_track_merged[u] = (int32_t)m;
+        for (int64_t j = lane; j < n; j += 64) M.o_hit_ids[dst + j] = M.hit_ids[hb + j];
     }
 }
 
@@ -723,7 +736,7 @@ void launch_merge(const MergeBatch& M, const DevParams& P, const MergeParams& Q,
     hipLaunchKernelGGL(k_m_tie, g, b, 0, s, M);
     hipLaunchKernelGGL(k_m_link, g, b, 0, s, M);
     hipLaunchKernelGGL(k_m_chain, g, b, 0, s, M);
-    hipLaunchKernelGGL(k_m_gather, g, b, 0, s, M, P);
+    hipLaunchKernelGGL(k_m_gather, dim3((unsigned)(n_cu * 16)), b, 0, s, M, P);
     hipLaunchKernelGGL(k_m_fit, g, b, 0, s, M, P, Q);
     hipLaunchKernelGGL(k_m_lead, g, b, 0, s, M);
     ScanJob J{};
@@ -739,6 +752,7 @@ void launch_merge(const MergeBatch& M, const DevParams& P, const MergeParams& Q,
     J.part = M.scan_part;
     launch_scan(J, s);
     hipLaunchKernelGGL(k_m_emit, g, b, 0, s, M, P);
+    hipLaunchKernelGGL(k_m_copy, dim3((unsigned)(n_cu * 16)), b, 0, s, M);
 }
 
 }  // namespace tpcsf

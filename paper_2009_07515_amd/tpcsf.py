@@ -65,7 +65,7 @@ class TracksDesc(C.Structure):
                 ("chi2", C.c_void_p), ("ndf", C.c_void_p), ("nhits", C.c_void_p), ("sector", C.c_void_p),
                 ("tf", C.c_void_p), ("hit_off", C.c_void_p), ("hit_ids", C.c_void_p),
                 ("cluster_track", C.c_void_p), ("z_beam", C.c_void_p), ("params_outer", C.c_void_p),
-                ("cov_outer", C.c_void_p)]
+                ("cov_outer", C.c_void_p), ("hit_rec", C.c_void_p)]
 
 
 class MergedDesc(C.Structure):
@@ -229,7 +229,7 @@ class TrackBuffers:
     a track keeps >= min_track_hits clusters and no cluster is in two tracks."""
 
     def __init__(self, n_clusters, cap_tracks=None, cap_hits=None, min_track_hits=20, device="cuda",
-                 outer=False):
+                 outer=False, hit_rec=False):
         import torch
         n = int(n_clusters)
         self.cap_tracks = int(cap_tracks if cap_tracks is not None else n // max(1, min_track_hits) + 1)
@@ -253,6 +253,8 @@ class TrackBuffers:
         # outer states (input of the merge) only on request
         self.params_outer = torch.empty((max(T, 1), 5), dtype=torch.float64, **kw) if outer else None
         self.cov_outer = torch.empty((max(T, 1), 15), dtype=torch.float64, **kw) if outer else None
+        # per-hit cluster records (y, z, row plane x, index bits), read by merge and compress
+        self.hit_rec = torch.empty((max(H, 1), 4), dtype=torch.float32, **kw) if hit_rec else None
 
     def desc(self):
         d = TracksDesc()
@@ -262,6 +264,8 @@ class TrackBuffers:
             setattr(d, k, _ptr(getattr(self, k)))
         if self.params_outer is not None:
             d.params_outer, d.cov_outer = _ptr(self.params_outer), _ptr(self.cov_outer)
+        if self.hit_rec is not None:
+            d.hit_rec = _ptr(self.hit_rec)
         return d
 
     def result(self, n_clusters):

@@ -19,11 +19,11 @@ def _np(res):
     return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
 
 
-def _gpu(f, n_tf=1, trk=None, tuning=None):
+def _gpu(f, n_tf=1, trk=None, tuning=None, hit_rec=False):
     from paper_2009_07515_amd import tpcsf
     trk = trk or tpcsf.Tracker(synth.row_x(), tuning=tuning)
     fr = tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off, n_tf=n_tf)
-    tb = tpcsf.TrackBuffers(fr.n_clusters)
+    tb = tpcsf.TrackBuffers(fr.n_clusters, hit_rec=hit_rec)
     tracks = _np(trk.track(fr, out=tb))
     codes, rows = trk.compress(fr, tb)
     yz = trk.decompress(tb, codes, rows)
@@ -48,10 +48,11 @@ def _check(f, tracks, codes, rows, yz, o_codes, o_resid, o_pred, label):
     print(f"{label}: {len(h)} clusters, {int(diff.sum())} codes at a rounding tie, decode deviation {dev:.2e} cm")
 
 
-@pytest.mark.parametrize("which", ["cfg1", "small", "cfg2"])
-def test_compress_parity_with_oracle(which, cfg1_frame, small_pbpb_frame, cfg2_frame, row_x):
+@pytest.mark.parametrize("which,rec", [("cfg1", False), ("small", False), ("small", True), ("cfg2", True)])
+def test_compress_parity_with_oracle(which, rec, cfg1_frame, small_pbpb_frame, cfg2_frame, row_x):
+    """rec: the encoder reads the tracking call's per-hit records instead of the clusters."""
     f = {"cfg1": cfg1_frame, "small": small_pbpb_frame, "cfg2": cfg2_frame}[which]
-    _, tracks, codes, rows, yz = _gpu(f)
+    _, tracks, codes, rows, yz = _gpu(f, hit_rec=rec)
     o = oracle.Oracle(row_x)
     r = o.track_frame(f.y, f.z, f.row_off)
     assert np.array_equal(r["hit_ids"], tracks["hit_ids"].astype(np.int64))
@@ -63,7 +64,7 @@ def test_compress_of_the_full_time_frame_equals_oracle(row_x):
     """The 2 ms Pb-Pb frame: the oracle compresses the GPU's own tracks."""
     f = synth.config3_time_frame()
     _, tracks, codes, rows, yz = _gpu(f, tuning=dict(bin_y=2.0, bin_z=4.0, cap_mul=4, block=512, tl_block=256,
-                                                     chunk=2))
+                                                     chunk=2), hit_rec=True)
     oc, ores, opred = oracle.Oracle(row_x).compress_frame(f.y, f.z, f.row_off, tracks)
     _check(f, tracks, codes, rows, yz, oc, ores, opred, "cfg3")
 

@@ -20,12 +20,12 @@ def _np(res):
     return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
 
 
-def _gpu_tracks_and_merge(f, n_tf=1, trk=None, cap_merged=None):
+def _gpu_tracks_and_merge(f, n_tf=1, trk=None, cap_merged=None, hit_rec=False):
     from paper_2009_07515_amd import tpcsf
     trk = trk or tpcsf.Tracker(synth.row_x())
     fr = tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off, n_tf=n_tf) if n_tf > 1 else \
         tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off)
-    tb = tpcsf.TrackBuffers(fr.n_clusters, outer=True)
+    tb = tpcsf.TrackBuffers(fr.n_clusters, outer=True, hit_rec=hit_rec)
     tracks = _np(trk.track(fr, out=tb))
     out = None
     if cap_merged is not None:
@@ -59,10 +59,11 @@ def _check_same_merge(g, o, label=""):
     assert np.allclose(g["link_chi2"][links], o["link_chi2"][links], rtol=1e-6, atol=1e-9)
 
 
-@pytest.mark.parametrize("which", ["small", "cfg2"])
-def test_merge_parity_with_oracle(which, small_pbpb_frame, cfg2_frame, row_x):
+@pytest.mark.parametrize("which,rec", [("small", False), ("small", True), ("cfg2", True)])
+def test_merge_parity_with_oracle(which, rec, small_pbpb_frame, cfg2_frame, row_x):
+    """rec: the refit reads the tracking call's per-hit records instead of the clusters."""
     f = {"small": small_pbpb_frame, "cfg2": cfg2_frame}[which]
-    _, tracks, merged = _gpu_tracks_and_merge(f)
+    _, tracks, merged = _gpu_tracks_and_merge(f, hit_rec=rec)
     o = oracle.Oracle(row_x)
     r = o.track_frame(f.y, f.z, f.row_off)
     assert tracks["n_tracks"] == r["n_tracks"]
@@ -84,7 +85,7 @@ def test_merge_of_the_full_time_frame_equals_oracle_merge_of_the_same_tracks(row
     f = synth.config3_time_frame()
     trk = tpcsf.Tracker(synth.row_x(), tuning=dict(bin_y=2.0, bin_z=4.0, cap_mul=4, block=512, tl_block=256,
                                                     chunk=2))
-    _, tracks, merged = _gpu_tracks_and_merge(f, trk=trk)
+    _, tracks, merged = _gpu_tracks_and_merge(f, trk=trk, hit_rec=True)
     o = oracle.Oracle(row_x)
     m = o.merge_frame(f.y, f.z, f.row_off, tracks)
     _check_same_merge(merged, m, "cfg3")

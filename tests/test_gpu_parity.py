@@ -142,6 +142,18 @@ def test_plain_equals_batch_and_is_deterministic(small_pbpb_frame):
     for k in ("hit_off", "hit_ids", "params", "cov", "chi2", "cluster_track", "sector", "tf", "z_beam"):
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(b[k], c[k]), k
+    # the optional per-hit records: the clusters' coordinates, row planes and indices
+    from paper_2009_07515_amd import tpcsf
+    tb = tpcsf.TrackBuffers(fr.n_clusters, hit_rec=True)
+    d = _np(trk.track(fr, out=tb))
+    H = d["n_hits"]
+    rec = tb.hit_rec[:H].cpu().numpy()
+    h = d["hit_ids"]
+    assert np.array_equal(rec[:, 3].view(np.int32), h)
+    assert np.array_equal(rec[:, 0], f.y[h]) and np.array_equal(rec[:, 1], f.z[h])
+    g = np.repeat(np.arange(len(f.row_off) - 1), np.diff(f.row_off))
+    assert np.array_equal(rec[:, 2], synth.row_x()[g[h] % 152])
+    assert np.array_equal(d["hit_ids"], b["hit_ids"])
 
 
 def test_multi_frame_batch_equals_frames_alone():
