@@ -13,10 +13,12 @@
 // of links become merged tracks, refitted across the sectors; a failed refit dissolves
 // the chain.  Merged tracks come in the order of their first segment.
 //
-// Layout: one lane per track in every kernel (the track counts are small next to the
-// tracking stages); the inner ends of each (time frame, sector, edge) are listed densely
-// in a region starting at that sector's first track, so that an outer end scans exactly
-// its candidate list.  Decisions that the oracle takes on cluster coordinates and on the
+// Layout: a lane per track for the per-track steps and per outer end for the match (8
+// lanes per outer end, splitting its window, measured slower), a wave per input track for
+// the cluster gathers and copies, 256 chains per block for the refit; the inner ends of
+// each (time frame, sector, edge) are listed densely in a region starting at that sector's
+// first track and ordered by z, so that an outer end scans only the part of its candidate
+// list its gate can accept.  Decisions that the oracle takes on cluster coordinates and on the
 // linear gate are evaluated without contraction, as there.
 #include "tpcsf_internal.h"
 #include "tpcsf_kalman.h"
