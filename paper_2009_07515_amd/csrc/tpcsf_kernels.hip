@@ -1630,10 +1630,29 @@ __global__ void __launch_bounds__(256) k_assign(Batch B, DevParams P, int64_t g0
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
         const int64_t sbase = B.row_sbase[g - g % nr];
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint32_t w = B.W[base + B.iperm[base + i]];
-            const int32_t T = w != 0u ? B.trk_out[sbase + (int64_t)(0xFFFFFFu - (w & 0xFFFFFFu))] : -1;
-            B.o_cluster_track[base + i] = T;
+        // four clusters per thread and pass: their loads are issued before they are used
+        constexpr int kU = 4;
+        for (int i0 = threadIdx.x; i0 < n; i0 += kU * blockDim.x) {
+            uint32_t ip[kU], w[kU];
+            int32_t T[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                ip[u] = i < n ? B.iperm[base + i] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                w[u] = i < n ? B.W[base + ip[u]] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                T[u] = w[u] != 0u ? B.trk_out[sbase + (int64_t)(0xFFFFFFu - (w[u] & 0xFFFFFFu))] : -1;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                if (i < n) B.o_cluster_track[base + i] = T[u];
+            }
         }
     }
 }
