@@ -142,8 +142,18 @@ def test_plain_equals_batch_and_is_deterministic(small_pbpb_frame):
     for k in ("hit_off", "hit_ids", "params", "cov", "chi2", "cluster_track", "sector", "tf", "z_beam"):
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(b[k], c[k]), k
-    # the optional per-hit records: the clusters' coordinates, row planes and indices
+    # the optional outputs (outer states, per-hit records) in both forms
     from paper_2009_07515_amd import tpcsf
+    opt = []
+    for mode in ("plain", "batch"):
+        ob = tpcsf.TrackBuffers(fr.n_clusters, outer=True, hit_rec=True)
+        res = _np(trk.track(fr, mode=mode, out=ob))
+        opt.append((res, ob.hit_rec[:res["n_hits"]].cpu().numpy()))
+    for k in ("params_outer", "cov_outer", "hit_ids", "params"):
+        assert np.array_equal(opt[0][0][k], opt[1][0][k]), k
+    assert np.array_equal(opt[0][1], opt[1][1])
+    assert np.array_equal(opt[1][0]["params"], b["params"])
+    # the optional per-hit records: the clusters' coordinates, row planes and indices
     tb = tpcsf.TrackBuffers(fr.n_clusters, hit_rec=True)
     d = _np(trk.track(fr, out=tb))
     H = d["n_hits"]
