@@ -511,11 +511,11 @@ def main():
         trk.sync()
         r_ms = e0.elapsed_time(e1) / args.reject_steps
         assert int(n_kept.item()) == kept
-        # per call: y, z, cluster->track map, keep flag and the bin-order mark of every
-        # cluster (15 B); per track its state and hit range (64 B)
-        rej_bytes = 15 * N + 64 * T0
+        # per call: y, z, bin-order position, cluster->track map and keep flag of every
+        # cluster (17 B); per track its state and hit range (64 B); the hit list (4 B a hit)
+        rej_bytes = 17 * N + 64 * T0 + 4 * H0
         rej_gbs = rej_bytes / (r_ms * 1e-3) / 1e9
-        reject = {"roofline": {"bound": "hbm", "kernel": "r_mark + r_final", "achieved": rej_gbs,
+        reject = {"roofline": {"bound": "hbm", "kernel": "r_span + r_fill + r_rows", "achieved": rej_gbs,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rej_gbs / HBM_PEAK_GBS,
                                "traffic": None, "algorithmic_bytes_per_launch": rej_bytes, "launch_ms": r_ms},
                   "ms_per_call": r_ms, "calls": args.reject_steps, "clusters": N, "kept": kept,

@@ -302,8 +302,9 @@ tpcsf_status tpcsf_merge_work(tpcsf_ctx* ctx, int64_t* work6);
 /* Hit removal for data compression, strategy B (Sec. 4): only the clusters in the
  * vicinity of good tracks are kept (the tracks' own clusters are found through their
  * cluster_track map, which must be the one of these tracks).  Definition: a good track has pT >= reject_pt_min
- * (|q/pT| * reject_pt_min <= 1); it keeps its own clusters, and at every row from its
- * innermost to its outermost cluster's row its state at x_ref, propagated in one helix
+ * (|q/pT| * reject_pt_min <= 1); it keeps its own clusters, and at every row from the row
+ * of its first cluster to the row of its last (none if the first lies further out) its
+ * state at x_ref, propagated in one helix
  * step to the row plane (no contribution where that step fails, see tpcsf_params), keeps
  * the clusters of its sector's row with |y - y_p| <= reject_window and
  * |z - z_p| <= reject_window (binary64).  Defaults: 0.05 GeV/c (the paper's 50 MeV/c
@@ -313,7 +314,9 @@ tpcsf_status tpcsf_merge_work(tpcsf_ctx* ctx, int64_t* work6);
  *   keep:   [device] [n_clusters] written: 1 = kept, 0 = removed, batch input order.
  *   n_kept: [device] scalar written.
  * Asynchronous on `stream`; tracks whose clusters lie outside their sector are skipped
- * and reported by tpcsf_sync as TPCSF_E_INVALID. */
+ * and reported by tpcsf_sync as TPCSF_E_INVALID.  Scratch: the (track, row) pairs of the
+ * windows, bucketed by row, 4 * cap_tracks * n_rows bytes plus small per-row arrays, held
+ * by the context from the first call (counted against hbm_budget_bytes; TPCSF_E_NOMEM). */
 tpcsf_status tpcsf_reject(tpcsf_ctx* ctx, const tpcsf_frame* frame, const tpcsf_tracks* tracks,
                           uint8_t* keep, int64_t* n_kept, void* stream);
 

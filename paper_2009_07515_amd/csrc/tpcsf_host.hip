@@ -27,7 +27,7 @@ struct Layout {
     size_t keep_n, fit_pos, cand_off, kept_list, keep_mask, fit_list;
     size_t trk_flag, hit_cnt, trk_idx, hit_pos, trk_out;
     size_t f_par, f_cov, f_chi2, f_xref, f_pout, f_cout, scan_part;
-    size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n, rmark;
+    size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n;
 };
 
 constexpr int kStages = 13;
@@ -65,6 +65,8 @@ struct tpcsf_ctx {
     size_t arena_size = 0;
     void* marena = nullptr;         // scratch of tpcsf_merge
     size_t marena_size = 0;
+    void* rarena = nullptr;         // scratch of tpcsf_reject
+    size_t rarena_size = 0;
     MergeCounters* d_mc = nullptr;
     Layout lay{};
     hipStream_t cap_stream = nullptr;
@@ -161,7 +163,6 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
     L.d_start_row = take(S * 4);
     L.d_start_idx = take(S * 4);
     L.d_tl_n = take(S * 4);
-    L.rmark = take(N);
     L.total = o;
     return L;
 }
@@ -254,7 +255,7 @@ tpcsf_status check_frame(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks*
 
 tpcsf_status ensure_arena(tpcsf_ctx* c, const Layout& L)
 {
-    if (c->budget && L.total + c->marena_size > c->budget)
+    if (c->budget && L.total + c->marena_size + c->rarena_size > c->budget)
         return fail(c, TPCSF_E_NOMEM, "scratch of " + std::to_string(L.total) + " bytes exceeds the HBM budget");
     if (c->arena && c->arena_size >= L.total) return TPCSF_OK;
     hipError_t e;
@@ -266,7 +267,7 @@ tpcsf_status ensure_arena(tpcsf_ctx* c, const Layout& L)
     }
     // reserved layouts are sized exactly; otherwise leave room for slightly larger batches
     const size_t want = c->reserve_n ? L.total : L.total + L.total / 8;
-    const size_t sz = (c->budget && want + c->marena_size > c->budget) ? L.total : want;
+    const size_t sz = (c->budget && want + c->marena_size + c->rarena_size > c->budget) ? L.total : want;
     if ((e = hipMalloc(&c->arena, sz)) != hipSuccess) {
         c->arena = nullptr;
         return fail(c, TPCSF_E_NOMEM, std::string("hipMalloc of the arena: ") + hipGetErrorString(e));
@@ -458,7 +459,7 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     const MergeLayout L = make_merge_layout(t->cap_tracks, K, t->cap_hits);
     hipError_t e;
     if (c->marena_size < L.total) {
-        if (c->budget && c->arena_size + L.total > c->budget)
+        if (c->budget && c->arena_size + c->rarena_size + L.total > c->budget)
             return fail(c, TPCSF_E_NOMEM, "merge scratch of " + std::to_string(L.total) + " bytes exceeds the HBM budget");
         if (c->marena) {
             if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
@@ -543,6 +544,37 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     return TPCSF_OK;
 }
 
+namespace {
+
+// Scratch of the hit removal: the (track, row) pairs of the vicinities bucketed by row.
+// A track contributes at most one pair per row, so cap_tracks * n_rows bounds the pairs.
+struct RejectLayout {
+    size_t total = 0;
+    int64_t cap_items = 0;
+    size_t rspan, rdiff, rcnt, rtmp, roff, rcur, ritems, scan_part;
+};
+
+RejectLayout make_reject_layout(int64_t T, int64_t R, int n_rows)
+{
+    RejectLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    const size_t t = (size_t)(T > 0 ? T : 1), r = (size_t)(R > 0 ? R : 1);
+    L.cap_items = (int64_t)t * n_rows;
+    L.rspan = take(t * 8);
+    L.rdiff = take((r + 1) * 4);
+    L.rcnt = take(r * 4);
+    L.rtmp = take((r + 1) * 8);
+    L.roff = take((r + 1) * 8);
+    L.rcur = take(r * 4);
+    L.ritems = take((size_t)L.cap_items * 4);
+    L.scan_part = take((4 * kScanBlocks + 2) * 8);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
 extern "C" tpcsf_status tpcsf_reject(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks* t, uint8_t* keep,
                                      int64_t* n_kept, void* stream)
 {
@@ -561,15 +593,42 @@ extern "C" tpcsf_status tpcsf_reject(tpcsf_ctx* c, const tpcsf_frame* f, const t
     A.par = t->params; A.xref = t->x_ref; A.sector = t->sector; A.tf = t->tf;
     A.hit_off = t->hit_off; A.hit_ids = t->hit_ids; A.cluster_track = t->cluster_track;
     A.n_tf = f->n_tf;
-    A.mark = (uint8_t*)c->arena + c->lay.rmark;
     A.pt_min = c->params.reject_pt_min;
     A.window = c->params.reject_window;
     A.keep = keep;
     A.n_kept = n_kept;
+    const RejectLayout L = make_reject_layout(t->cap_tracks, R, c->n_rows);
+    hipError_t e;
+    if (c->rarena_size < L.total) {
+        if (c->budget && c->arena_size + c->marena_size + L.total > c->budget)
+            return fail(c, TPCSF_E_NOMEM, "reject scratch of " + std::to_string(L.total) + " bytes exceeds the HBM budget");
+        if (c->rarena) {
+            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+            if ((e = hipFree(c->rarena)) != hipSuccess) return hip_fail(c, e, "hipFree");
+            c->rarena = nullptr;
+            c->rarena_size = 0;
+        }
+        if ((e = hipMalloc(&c->rarena, L.total)) != hipSuccess) {
+            c->rarena = nullptr;
+            return fail(c, TPCSF_E_NOMEM, std::string("hipMalloc of the reject scratch: ") + hipGetErrorString(e));
+        }
+        c->rarena_size = L.total;
+    }
+    char* ra = (char*)c->rarena;
+    A.rspan = (int32_t*)(ra + L.rspan);
+    A.rdiff = (int32_t*)(ra + L.rdiff);
+    A.rcnt = (int32_t*)(ra + L.rcnt);
+    A.rtmp = (int64_t*)(ra + L.rtmp);
+    A.roff = (int64_t*)(ra + L.roff);
+    A.rcur = (int32_t*)(ra + L.rcur);
+    A.ritems = (int32_t*)(ra + L.ritems);
+    A.cap_items = L.cap_items;
+    A.scan_part = (int64_t*)(ra + L.scan_part);
+    A.n_rows_total = (int32_t)R;
     Batch B = c->last;
     B.n = f->n_clusters;
     launch_reject(B, c->last_P, A, launch_cfg(c), (hipStream_t)stream);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "reject kernel launch");
     return TPCSF_OK;
 }
@@ -725,6 +784,7 @@ tpcsf_status tpcsf_destroy(tpcsf_ctx* c)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->arena) (void)hipFree(c->arena);
     if (c->marena) (void)hipFree(c->marena);
+    if (c->rarena) (void)hipFree(c->rarena);
     if (c->d_mc) (void)hipFree(c->d_mc);
     for (int i = 0; i <= kStages; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);

@@ -247,9 +247,19 @@ struct RejectArgs {
     const int32_t* cluster_track;   // [n_clusters] the tracks' cluster -> track map
     int32_t n_tf;
     double pt_min, window;
-    uint8_t* mark;                  // [arena, N] vicinity flags in sorted (bin) order
     uint8_t* keep;                  // [n_clusters]
     int64_t* n_kept;
+    // the (track, row) pairs of the vicinities, bucketed by row
+    int32_t* rspan;                 // [cap_tracks][2] rows of the first and last cluster, -1 none
+    int32_t* rdiff;                 // [R+1] difference array of the row counts
+    int32_t* rcnt;                  // [R] pairs per row
+    int64_t* rtmp;                  // [R+1] scan scratch
+    int64_t* roff;                  // [R+1] first pair of each row
+    int32_t* rcur;                  // [R] fill cursors
+    int32_t* ritems;                // [cap_items] tracks, row by row
+    int64_t cap_items;
+    int64_t* scan_part;             // [4 * kScanBlocks + 2]
+    int32_t n_rows_total;
 };
 void launch_reject(const Batch& b, const DevParams& p, const RejectArgs& r, const LaunchCfg& c, hipStream_t s);
 

@@ -1890,31 +1890,41 @@ void launch_assign(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, c
 // step to the row.  The rows are searched with the grids of the same call.  Wave per
 // track; the flags are bytes in input order (concurrent stores all write 1).
 // ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_r_clear(RejectArgs A, int64_t n)
+__global__ void __launch_bounds__(256) k_r_clear(RejectArgs A)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i0 == 0) *A.n_kept = 0;
-    for (int64_t i = i0; i < n; i += stride) A.mark[i] = 0;
-}
-
-// row of cluster h among the rows [g0, g0 + nr): the lanes test 64 rows per pass
-__device__ __forceinline__ int wave_row_of(const int64_t* off, int64_t g0, int nr, int64_t h)
-{
-    for (int r0 = 0; r0 < nr; r0 += 64) {
-        const int r = r0 + lane_id();
-        const bool in = r < nr && off[g0 + r] <= h && h < off[g0 + r + 1];
-        const uint64_t m = __ballot(in);
-        if (m != 0ull) return r0 + __ffsll((unsigned long long)m) - 1;
+    for (int64_t i = i0; i <= A.n_rows_total; i += stride) {
+        A.rdiff[i] = 0;
+        if (i < A.n_rows_total) A.rcur[i] = 0;
     }
-    return 0;
 }
 
-// vicinity of the good tracks, marked in sorted order.  A wave takes 64 neighbouring
-// tracks (lane per track) and sweeps their rows together, all lanes on the same row, so
-// that they share the row's record and nearby parts of its bin table; the input checks
-// are done by the whole wave, 64 clusters of one track per pass.
-__global__ void __launch_bounds__(256) k_r_mark(Batch B, DevParams P, RejectArgs A)
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t wave_min_l(int64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_max_l(int64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Row span of every good track (the rows of its first and last cluster) after the input
+// checks, and the +1 / -1 of that span in the difference array of the row counts.  A wave
+// takes 64 neighbouring tracks, whose cluster lists are adjacent, and checks them in
+// coalesced passes of 64 clusters; the few tracks a pass touches are visited in turn.
+__global__ void __launch_bounds__(256) k_r_span(Batch B, DevParams P, RejectArgs A)
 {
     const int nr = P.n_rows, ns = P.n_sectors;
     const int lane = lane_id();
@@ -1925,16 +1935,13 @@ __global__ void __launch_bounds__(256) k_r_mark(Batch B, DevParams P, RejectArgs
         const int64_t t = w0 + lane;
         bool on = false;
         int64_t g0 = 0, hb = 0, he = 0, lo = 0, hi = 0;
-        double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, x0 = 0.0;
         if (t < T) {
-            for (int q = 0; q < 5; ++q) p[q] = A.par[t * 5 + q];
-            x0 = A.xref[t];
             const int s = A.sector[t], f = A.tf[t];
             hb = A.hit_off[t];
             he = A.hit_off[t + 1];
             if (!(s >= 0 && s < ns && f >= 0 && f < A.n_tf && hb >= 0 && he > hb && he <= A.cap_hits)) {
                 atomicOr(&B.ctr->err, kErrInvalid);
-            } else if (fabs(p[4]) * A.pt_min <= 1.0) {
+            } else if (fabs(A.par[t * 5 + 4]) * A.pt_min <= 1.0) {
                 g0 = ((int64_t)f * ns + s) * nr;
                 lo = B.off[g0];
                 hi = B.off[g0 + nr];
@@ -1942,23 +1949,42 @@ __global__ void __launch_bounds__(256) k_r_mark(Batch B, DevParams P, RejectArgs
             }
         }
         // every cluster inside the track's own sector
-        uint64_t todo = __ballot(on);
-        while (todo) {
-            const int l = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1ull;
-            const int64_t b0 = __shfl(hb, l, 64), b1 = __shfl(he, l, 64);
-            const int64_t c0 = __shfl(lo, l, 64), c1 = __shfl(hi, l, 64);
-            bool out = false;
-            for (int64_t j = b0 + lane; j < b1; j += 64) {
-                const int64_t h = A.hit_ids[j];
-                out = out || h < c0 || h >= c1;
+        const int64_t H0 = wave_min_l(on ? hb : INT64_MAX), H1 = wave_max_l(on ? he : INT64_MIN);
+        bool bad = false;
+        for (int64_t jb = H0; jb < H1; jb += 8 * 64) {
+            int32_t hv[8];   // eight passes' loads issued together
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t j = jb + u * 64 + lane;
+                hv[u] = (j < H1) ? A.hit_ids[j] : 0;
             }
-            if (__ballot(out) != 0ull && lane == l) {
-                on = false;
-                atomicOr(&B.ctr->err, kErrInvalid);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t j0 = jb + u * 64, j = j0 + lane;
+                const int64_t h = hv[u];
+                uint64_t own = __ballot(on && hb < j0 + 64 && he > j0);
+                int who = -1;
+                while (own) {
+                    const int o = __ffsll((unsigned long long)own) - 1;
+                    own &= own - 1ull;
+                    const int64_t ob = readlane64(hb, o), oe = readlane64(he, o);
+                    const int64_t ol = readlane64(lo, o), oh = readlane64(hi, o);
+                    if (j >= ob && j < oe && (h < ol || h >= oh)) who = o;
+                }
+                uint64_t bm = __ballot(who >= 0);
+                while (bm) {
+                    const int l = __ffsll((unsigned long long)bm) - 1;
+                    bm &= bm - 1ull;
+                    if (lane == __shfl(who, l, 64)) bad = true;
+                }
             }
         }
-        int r0 = 0, r1 = -1;
+        if (bad) {
+            on = false;
+            atomicOr(&B.ctr->err, kErrInvalid);
+        }
+        // rows of the first and the last cluster; the span is empty if the first is further out
+        int r0 = -1, r1 = -1;
         if (on) {
             const int64_t hs[2] = {A.hit_ids[hb], A.hit_ids[he - 1]};
             int rr[2];
@@ -1970,62 +1996,215 @@ __global__ void __launch_bounds__(256) k_r_mark(Batch B, DevParams P, RejectArgs
                 }
                 rr[q] = a;
             }
-            r0 = rr[0];
-            r1 = rr[1];
+            if (rr[0] <= rr[1]) {
+                r0 = rr[0];
+                r1 = rr[1];
+            }
         }
-        const int rlo = wave_min_i(on ? r0 : nr), rhi = wave_max_i(on ? r1 : -1);
-        const double w = A.window;
-        for (int r = rlo; r <= rhi; ++r) {
-            if (!(on && r >= r0 && r <= r1)) continue;
-            double yp, zp;
-            if (!trk_predict(p, x0, (double)P.rx[r], P, yp, zp)) continue;
-            if (!(fabs(yp) < 1.0e6) || !(fabs(zp) < 1.0e6)) continue;
-            const int64_t g = g0 + r;
-            const RowView v = row_view(B, P, g);
-            if (v.n == 0) continue;
-            int iy0, iy1, iz0, iz1;
-            bin_span((float)yp, (float)w, v.ylo, v.iby, v.ny, iy0, iy1);
-            bin_span((float)zp, (float)w, v.zlo, v.ibz, v.nz, iz0, iz1);
-            const float2* yz = B.yz + v.first;
-            for (int iz = iz0; iz <= iz1; ++iz) {
-                const uint32_t a0 = v.bs[iz * v.ny + iy0], a1 = v.bs[iz * v.ny + iy1 + 1];
-                for (uint32_t k = a0; k < a1; ++k) {
-                    const float2 c = yz[k];
-                    if (fabs((double)c.x - yp) <= w && fabs((double)c.y - zp) <= w) A.mark[v.first + k] = 1;
+        if (t < T) {
+            A.rspan[2 * t] = r0;
+            A.rspan[2 * t + 1] = r1;
+        }
+        // most tracks of a sector start and end on the same few rows: one atomic per
+        // distinct entry of the wave
+        for (int e = 0; e < 2; ++e) {
+            const int64_t key = (r0 >= 0) ? (e == 0 ? g0 + r0 : g0 + r1 + 1) : -1;
+            uint64_t todo = __ballot(key >= 0);
+            while (todo) {
+                const int64_t kw = readlane64(key, __ffsll((unsigned long long)todo) - 1);
+                const uint64_t same = __ballot(key == kw);
+                todo &= ~same;
+                if (lane == __ffsll((unsigned long long)same) - 1)
+                    atomicAdd(&A.rdiff[kw], e == 0 ? (int)__popcll(same) : -(int)__popcll(same));
+            }
+        }
+    }
+}
+
+// pairs per row: the inclusive prefix of the difference array
+__global__ void __launch_bounds__(256) k_r_count(RejectArgs A)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < A.n_rows_total; g += stride)
+        A.rcnt[g] = (int32_t)(A.rtmp[g] + A.rdiff[g]);
+}
+
+// The pairs into their rows' buckets.  A wave takes 64 neighbouring tracks and serves the
+// sectors among them in turn (usually one): it counts the sector's tracks on each row with
+// ballots, takes every row's positions with one atomic, the atomics of 64 rows issued
+// together, and then writes the pairs.
+__global__ void __launch_bounds__(256) k_r_fill(Batch B, DevParams P, RejectArgs A)
+{
+    const int nr = P.n_rows, ns = P.n_sectors;
+    const int lane = lane_id();
+    int64_t T = *A.n_tracks;
+    if (T > A.cap_tracks) T = A.cap_tracks;
+    if (A.roff[A.n_rows_total] > A.cap_items) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&B.ctr->err, kErrOutCap);
+        return;
+    }
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; w0 < T; w0 += nw * 64) {
+        const int64_t t = w0 + lane;
+        int r0 = -1, r1 = -1;
+        int64_t g0 = -1;
+        if (t < T) {
+            r0 = A.rspan[2 * t];
+            r1 = A.rspan[2 * t + 1];
+            if (r0 >= 0) g0 = ((int64_t)A.tf[t] * ns + A.sector[t]) * nr;
+        }
+        uint64_t todo = __ballot(r0 >= 0);
+        while (todo) {
+            const int64_t gw = readlane64(g0, __ffsll((unsigned long long)todo) - 1);
+            const bool on = r0 >= 0 && g0 == gw;
+            todo &= ~__ballot(on);
+            const int rlo = wave_min_i(on ? r0 : nr), rhi = wave_max_i(on ? r1 : -1);
+            for (int c0 = rlo; c0 <= rhi; c0 += 64) {
+                // lane L owns row c0 + L: count, then one atomic per row
+                const int cn = min(64, rhi - c0 + 1);
+                int cnt = 0;
+                for (int q = 0; q < cn; ++q) {
+                    const int r = c0 + q;
+                    const int m = __popcll(__ballot(on && r >= r0 && r <= r1));
+                    if (lane == q) cnt = m;
+                }
+                int64_t at = 0;
+                if (lane < cn && cnt > 0) at = A.roff[gw + c0 + lane] + atomicAdd(&A.rcur[gw + c0 + lane], cnt);
+                for (int q = 0; q < cn; ++q) {
+                    const int r = c0 + q;
+                    const bool act = on && r >= r0 && r <= r1;
+                    const uint64_t m = __ballot(act);
+                    const int64_t b = readlane64(at, q);
+                    if (act) A.ritems[b + __popcll(m & lanemask_lt())] = (int32_t)t;
                 }
             }
         }
     }
 }
 
-// keep flags in input order, per row: in the vicinity of a good track, or a cluster of one
-__global__ void __launch_bounds__(256) k_r_final(Batch B, RejectArgs A, int64_t g0, int64_t g1)
+// Vicinity flags and keep flags, a block per row: a thread takes a pair, predicts its
+// track's position on the row and tests the candidates of the window's bins.  The flags
+// live in LDS; rows with more clusters than it holds take several passes, each flagging
+// one slice of the row.  The keep flags are then written in input order: in the vicinity
+// of a good track, or a cluster of one.
+constexpr int kRowFlags = 16384;
+
+__global__ void __launch_bounds__(256) k_r_rows(Batch B, DevParams P, RejectArgs A)
 {
+    __shared__ uint8_t lf[kRowFlags];
+    const int nr = P.n_rows;
+    const int lane = lane_id();
     int64_t T = *A.n_tracks;
     if (T > A.cap_tracks) T = A.cap_tracks;
-    int64_t c = 0;
-    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
+    const bool have = A.roff[A.n_rows_total] <= A.cap_items;
+    const double w = A.window;
+    int64_t kept = 0;
+    for (int64_t g = xcd_block(); g < A.n_rows_total; g += gridDim.x) {
         const int64_t base = B.off[g];
         const int n = (int)(B.off[g + 1] - base);
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const int32_t t = A.cluster_track[base + i];
-            bool k = A.mark[base + B.iperm[base + i]] != 0;
-            if (!k && t >= 0 && t < T) k = fabs(A.par[(int64_t)t * 5 + 4]) * A.pt_min <= 1.0;
-            A.keep[base + i] = k ? 1 : 0;
-            c += k;
+        if (n == 0) continue;
+        const int64_t i0 = have ? A.roff[g] : 0, i1 = have ? A.roff[g + 1] : 0;
+        const RowView v = row_view(B, P, g);
+        const double x1 = (double)P.rx[g % nr];
+        const float2* yz = B.yz + v.first;
+        for (int c0 = 0; c0 < n; c0 += kRowFlags) {
+            const int c1 = min(n, c0 + kRowFlags);
+            for (int k = threadIdx.x; k < c1 - c0; k += blockDim.x) lf[k] = 0;
+            __syncthreads();
+            // pairs of this thread: i0 + threadIdx.x + m * blockDim.x; the next pair's track
+            // and state are loaded while the current one is searched
+            int64_t i = i0 + threadIdx.x;
+            const int64_t tc = (i < i1) ? A.ritems[i] : -1;
+            double p[5], x0 = 0.0;
+            if (tc >= 0) {
+                for (int q = 0; q < 5; ++q) p[q] = A.par[tc * 5 + q];
+                x0 = A.xref[tc];
+            }
+            for (; i < i1; i += blockDim.x) {
+                const int64_t tn = (i + blockDim.x < i1) ? A.ritems[i + blockDim.x] : -1;
+                double yp = 0.0, zp = 0.0;
+                int iy0 = 0, iy1 = 0, iz0 = 0, iz1 = -1;
+                const bool ok = trk_predict(p, x0, x1, P, yp, zp) && fabs(yp) < 1.0e6 && fabs(zp) < 1.0e6;
+                if (ok) {
+                    bin_span((float)yp, (float)w, v.ylo, v.iby, v.ny, iy0, iy1);
+                    bin_span((float)zp, (float)w, v.zlo, v.ibz, v.nz, iz0, iz1);
+                }
+                uint32_t a0 = 0, a1 = 0;
+                if (ok) {
+                    a0 = v.bs[iz0 * v.ny + iy0];
+                    a1 = v.bs[iz0 * v.ny + iy1 + 1];
+                }
+                if (tn >= 0) {
+                    for (int q = 0; q < 5; ++q) p[q] = A.par[tn * 5 + q];
+                    x0 = A.xref[tn];
+                }
+                if (ok) {
+                    // the window's bin rows; the next one's bounds are loaded ahead, and the
+                    // candidates are read eight at a time
+                    for (int iz = iz0; iz <= iz1; ++iz) {
+                        uint32_t n0 = 0, n1 = 0;
+                        if (iz < iz1) {
+                            n0 = v.bs[(iz + 1) * v.ny + iy0];
+                            n1 = v.bs[(iz + 1) * v.ny + iy1 + 1];
+                        }
+                        for (uint32_t k = a0; k < a1; k += 8) {
+                            float2 cc[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) cc[q] = yz[min(k + (uint32_t)q, a1 - 1u)];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const int kk = (int)k + q;
+                                if ((uint32_t)kk < a1 && fabs((double)cc[q].x - yp) <= w &&
+                                    fabs((double)cc[q].y - zp) <= w && kk >= c0 && kk < c1)
+                                    lf[kk - c0] = 1;
+                            }
+                        }
+                        a0 = n0;
+                        a1 = n1;
+                    }
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int k = (int)B.iperm[base + i];
+                if (k < c0 || k >= c1) continue;
+                bool kp = lf[k - c0] != 0;
+                if (!kp) {
+                    const int32_t t = A.cluster_track[base + i];
+                    if (t >= 0 && t < T) kp = fabs(A.par[(int64_t)t * 5 + 4]) * A.pt_min <= 1.0;
+                }
+                A.keep[base + i] = kp ? 1 : 0;
+                kept += kp;
+            }
+            __syncthreads();
         }
     }
-    c = wave_sum(c);
-    if (lane_id() == 0 && c) atomicAdd((unsigned long long*)A.n_kept, (unsigned long long)c);
+    kept = wave_sum(kept);
+    if (lane == 0 && kept) atomicAdd((unsigned long long*)A.n_kept, (unsigned long long)kept);
 }
 
 void launch_reject(const Batch& b, const DevParams& p, const RejectArgs& r, const LaunchCfg& c, hipStream_t s)
 {
-    const unsigned g = (unsigned)(c.n_cu * 4);
-    hipLaunchKernelGGL(k_r_clear, dim3(g), dim3(256), 0, s, r, b.n);
-    hipLaunchKernelGGL(k_r_mark, dim3(c.n_cu * 8), dim3(256), 0, s, b, p, r);
-    hipLaunchKernelGGL(k_r_final, dim3(grid_for(b.n_rows_total, 1, 1 << 16)), dim3(256), 0, s, b, r, (int64_t)0,
-                       (int64_t)b.n_rows_total);
+    hipLaunchKernelGGL(k_r_clear, dim3(grid_for(r.n_rows_total + 1, 256, 1 << 16)), dim3(256), 0, s, r);
+    hipLaunchKernelGGL(k_r_span, dim3(c.n_cu * 4), dim3(256), 0, s, b, p, r);
+    ScanJob J1{};   // exclusive prefix of the difference array
+    J1.a32 = r.rdiff;
+    J1.outA = r.rtmp;
+    J1.lo = 0;
+    J1.hi = r.n_rows_total;
+    J1.part = r.scan_part;
+    launch_scan(J1, s);
+    hipLaunchKernelGGL(k_r_count, dim3(grid_for(r.n_rows_total, 256, 1 << 16)), dim3(256), 0, s, r);
+    ScanJob J2{};   // first pair of each row; roff[R] = all pairs
+    J2.a32 = r.rcnt;
+    J2.outA = r.roff;
+    J2.lo = 0;
+    J2.hi = r.n_rows_total;
+    J2.totA = r.roff + r.n_rows_total;
+    J2.part = r.scan_part;
+    launch_scan(J2, s);
+    hipLaunchKernelGGL(k_r_fill, dim3(c.n_cu * 8), dim3(256), 0, s, b, p, r);
+    hipLaunchKernelGGL(k_r_rows, dim3(grid_for(r.n_rows_total, 1, 1 << 16)), dim3(256), 0, s, b, p, r);
 }
 
 void launch_hash(const Batch& b, int64_t n_clusters, const LaunchCfg& c, hipStream_t s)
