@@ -314,6 +314,8 @@ def main():
                     help="timed calls of the strategy-B hit removal (0: skip)")
     ap.add_argument("--merge-steps", type=int, default=20,
                     help="timed calls of the merge across sector edges (0: skip)")
+    ap.add_argument("--size-curve", type=str, default="100,250,500,1000",
+                    help="shorter Pb-Pb frame lengths (us) timed in both forms, besides the main frame; '' skips")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for byte-counter calibration)")
     args = ap.parse_args()
@@ -394,6 +396,52 @@ def main():
         ms_p = wall_p * 1e3 / args.plain_steps
         plain = {"value": N / (wall_p / args.plain_steps), "ms_per_step": ms_p, "steps": args.plain_steps}
         log(f"plain: {ms_p:.3f} ms/step, {plain['value'] / 1e9:.3f} G clusters/s")
+
+    # clusters/s against the frame length, both forms: Pb-Pb frames of the same recipe
+    # (50 kHz, 0.1 ms up to the main frame's length), each tracked with the tuning above
+    size_curve = None
+    lengths = [float(x) for x in args.size_curve.split(",") if x.strip()]
+    if lengths:
+        size_curve = []
+        for L in lengths:
+            fs = synth.config3_time_frame(length_us=L)
+            ns = fs.n_clusters
+            frs = tpcsf.DeviceFrame.from_numpy(fs.y, fs.z, fs.row_off, device="cuda:0")
+            outs = tpcsf.TrackBuffers(ns)
+            rs = trk.track(frs, out=outs, mode="batch")
+            for _ in range(2):
+                trk.launch(frs, outs, "batch")
+            torch.cuda.synchronize()
+            ks = max(5, args.steps // 2)
+            t0 = time.perf_counter()
+            for _ in range(ks):
+                trk.launch(frs, outs, "batch")
+            torch.cuda.synchronize()
+            wb = (time.perf_counter() - t0) / ks
+            trk.sync()
+            assert int(outs.n_tracks.item()) == rs["n_tracks"]
+            pt = {"tf_us": L, "clusters": ns, "tracks": rs["n_tracks"], "batch_ms": wb * 1e3,
+                  "batch_clusters_per_s": ns / wb}
+            if args.plain_steps > 0:
+                trk.track(frs, out=outs, mode="plain")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.plain_steps):
+                    trk.launch(frs, outs, "plain")
+                torch.cuda.synchronize()
+                wp = (time.perf_counter() - t0) / args.plain_steps
+                trk.sync()
+                assert int(outs.n_tracks.item()) == rs["n_tracks"]
+                pt.update({"plain_ms": wp * 1e3, "plain_clusters_per_s": ns / wp})
+            size_curve.append(pt)
+            log(f"frame {L:.0f} us: {ns} clusters, batched {wb * 1e3:.3f} ms ({ns / wb / 1e9:.3f} G/s)"
+                + (f", plain {pt['plain_ms']:.3f} ms ({pt['plain_clusters_per_s'] / 1e9:.3f} G/s)" if "plain_ms" in pt
+                   else ""))
+            del frs, outs
+        main_pt = {"tf_us": args.tf_us, "clusters": N, "tracks": T0, "batch_ms": ms, "batch_clusters_per_s": value}
+        if plain:
+            main_pt.update({"plain_ms": plain["ms_per_step"], "plain_clusters_per_s": plain["value"]})
+        size_curve.append(main_pt)
 
     # calibration copy for hardware byte counters: one device copy of a known size
     if args.calib_copy_mib > 0:
@@ -583,6 +631,7 @@ def main():
         "merge": merge,
         "reject": reject,
         "compress": compress,
+        "size_curve": size_curve,
         "path_hbm": {"bytes_per_cluster": path_bytes / N,
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
                      "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
