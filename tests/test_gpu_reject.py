@@ -73,3 +73,54 @@ def test_reject_needs_the_last_frame(small_pbpb_frame, cfg1_frame):
     assert e.value.status == tpcsf.E_INVALID
     keep, k = trk.reject(fb, tbb)
     assert k > 0
+
+
+def test_reject_of_a_row_larger_than_the_flag_table(cfg1_frame, row_x):
+    """A row of more than 20,000 clusters (dense noise added to row 60 of sector 0): more
+    than one pass of the row kernel's on-chip flag table, whose slices must together give
+    the oracle's keep flags."""
+    f = cfg1_frame
+    g = 60
+    rng = np.random.Generator(np.random.PCG64(11))
+    m = 20000
+    half = float(row_x[g]) * np.tan(np.pi / 18)
+    ny = rng.uniform(-half, half, m).astype(np.float32)
+    nz = rng.uniform(-250.0, 250.0, m).astype(np.float32)
+    at = int(f.row_off[g + 1])
+    y = np.insert(f.y, at, ny)
+    z = np.insert(f.z, at, nz)
+    ro = f.row_off.copy()
+    ro[g + 1:] += m
+    frame = type("F", (), dict(y=y, z=z, row_off=ro))
+    assert ro[g + 1] - ro[g] > 16384
+    _, tracks, keep, k = _gpu(frame)
+    ko, kk = oracle.Oracle(row_x).reject_frame(y, z, ro, tracks)
+    assert k == kk and np.array_equal(keep, ko)
+    row_keep = keep[ro[g]:ro[g + 1]]
+    own = np.zeros(ro[g + 1] - ro[g], bool)
+    own[tracks["cluster_track"][ro[g]:ro[g + 1]] >= 0] = True
+    # clusters kept for lying in a track's window only, not for being a track's own
+    assert int(row_keep[~own].sum()) > 20
+    print(f"row of {ro[g + 1] - ro[g]} clusters: {int(row_keep.sum())} kept, {tracks['n_tracks']} tracks")
+
+
+def test_reject_reports_tracks_outside_their_sector(small_pbpb_frame):
+    from paper_2009_07515_amd import tpcsf
+    f = small_pbpb_frame
+    trk = tpcsf.Tracker(synth.row_x())
+    fr = tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off)
+    tb = tpcsf.TrackBuffers(fr.n_clusters)
+    trk.track(fr, out=tb)
+    keep0, k0 = trk.reject(fr, tb)
+    s0 = int(tb.sector[0].item())
+    tb.sector[0] = (s0 + 1) % 36          # its clusters now lie outside its sector
+    with pytest.raises(tpcsf.TpcsfError) as e:
+        trk.reject(fr, tb)
+    assert e.value.status == tpcsf.E_INVALID
+    tb.sector[0] = s0
+    keep1, k1 = trk.reject(fr, tb)        # the context keeps working
+    assert k1 == k0 and torch_equal(keep1, keep0)
+
+
+def torch_equal(a, b):
+    return bool((a == b).all().item())
