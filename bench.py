@@ -315,7 +315,7 @@ def main():
     ap.add_argument("--merge-steps", type=int, default=20,
                     help="timed calls of the merge across sector edges (0: skip)")
     ap.add_argument("--size-curve", type=str, default="100,250,500,1000",
-                    help="shorter Pb-Pb frame lengths (us) timed in both forms, besides the main frame; '' skips")
+                    help="shorter Pb-Pb frame lengths (us) timed in both forms, besides the main frame; 'none' skips")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for byte-counter calibration)")
     args = ap.parse_args()
@@ -400,7 +400,8 @@ def main():
     # clusters/s against the frame length, both forms: Pb-Pb frames of the same recipe
     # (50 kHz, 0.1 ms up to the main frame's length), each tracked with the tuning above
     size_curve = None
-    lengths = [float(x) for x in args.size_curve.split(",") if x.strip()]
+    lengths = [] if args.size_curve.strip().lower() in ("", "none") else \
+        [float(x) for x in args.size_curve.split(",") if x.strip()]
     if lengths:
         size_curve = []
         for L in lengths:

@@ -361,36 +361,51 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_match(MergeBatch M, DevPara
                 if ((double)M.zs[base + mid] < qlo) lo = mid + 1; else hi = mid;
             }
             j0 = lo;
-            int32_t e1 = j0;
-            while (e1 < n && (double)M.zs[base + e1] <= qhi) ++e1;
-            j1 = e1;
+            hi = n;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if ((double)M.zs[base + mid] <= qhi) lo = mid + 1; else hi = mid;
+            }
+            j1 = lo;
         }
         int32_t best = -1;
         double bestc = 0.0;
-        for (int32_t j = j0; j < j1; ++j) {
-            const double4 r = M.brec_s[base + j];
-            bool pass;
-            {
+        // the window's entries four at a time, their loads issued together; the few that
+        // pass the gate are propagated and scored
+        for (int32_t jb = j0; jb < j1; jb += 4) {
+            double4 rr[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) rr[u] = M.brec_s[base + min(jb + u, j1 - 1)];
+            uint32_t passm = 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
 #pragma clang fp contract(off)
+                const double4 r = rr[u];
                 const double dx = r.x - a.x;
                 const double ylin = a.p[0] + dx * ty;
                 const double zlin = a.p[1] + dx * tz;
-                pass = r.y > ro2 && fabs(ylin - r.z) <= Q.window && fabs(zlin - r.w) <= Q.window;
+                if (jb + u < j1 && r.y > ro2 && fabs(ylin - r.z) <= Q.window && fabs(zlin - r.w) <= Q.window)
+                    passm |= 1u << u;
             }
-            if (!pass) continue;
-            ++n_gate;
-            const int32_t b = M.bidx_s[base + j];
-            Trk a1 = a;
-            ++n_prop;
-            if (!trk_propagate(a1, r.x, P)) continue;
-            double d[5], Ss[15], c2;
-            for (int q = 0; q < 5; ++q) d[q] = a1.p[q] - M.par[(int64_t)b * 5 + q];
-            for (int q = 0; q < 15; ++q) Ss[q] = a1.c[q] + M.cov[(int64_t)b * 15 + q];
-            ++n_chi2;
-            if (!chi2_5(Ss, d, c2) || !(c2 <= Q.chi2)) continue;
-            if (best < 0 || c2 < bestc || (c2 == bestc && b < best)) {
-                best = b;
-                bestc = c2;
+            while (passm) {
+                const int u = __ffs(passm) - 1;
+                passm &= passm - 1u;
+                const int32_t j = jb + u;
+                const double4 r = M.brec_s[base + j];
+                ++n_gate;
+                const int32_t b = M.bidx_s[base + j];
+                Trk a1 = a;
+                ++n_prop;
+                if (!trk_propagate(a1, r.x, P)) continue;
+                double d[5], Ss[15], c2;
+                for (int q = 0; q < 5; ++q) d[q] = a1.p[q] - M.par[(int64_t)b * 5 + q];
+                for (int q = 0; q < 15; ++q) Ss[q] = a1.c[q] + M.cov[(int64_t)b * 15 + q];
+                ++n_chi2;
+                if (!chi2_5(Ss, d, c2) || !(c2 <= Q.chi2)) continue;
+                if (best < 0 || c2 < bestc || (c2 == bestc && b < best)) {
+                    best = b;
+                    bestc = c2;
+                }
             }
         }
         M.bestB[t] = best;
