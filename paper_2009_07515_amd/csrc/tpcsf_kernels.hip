@@ -478,6 +478,8 @@ __device__ __forceinline__ void first_range(const RowView& V, int iy0, int iy1, 
 
 constexpr int kSlots = 6;
 
+constexpr int kLinkBatch = 3;   // candidates per load batch of the link search
+
 struct LinkBest {
     float D;
     int ku, kd;      // sorted positions, -1 = none
@@ -518,24 +520,30 @@ __device__ __forceinline__ int gather_side(const RowView& V, const float2* yz, i
             qe = V.bs[iz * V.ny + iy1 + 1];
         }
         if (q >= qe) break;
-        const float2 c = yz[q];
-        if (fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz) {
-            const int slot = cnt - skip;
-            if (slot >= 0 && slot < kSlots) {
-                const float sy = above ? (c.x - yh) / dx : (yh - c.x) / dx;
-                const float sz = above ? (c.y - zh) / dx : (zh - c.y) / dx;
+        float2 cb[kLinkBatch];
 #pragma unroll
-                for (int m = 0; m < kSlots; ++m)
-                    if (m == slot) { ty[m] = sy; tz[m] = sz; kk[m] = (int)q; }
+        for (int u = 0; u < kLinkBatch; ++u) cb[u] = yz[min(q + (uint32_t)u, qe - 1u)];
+#pragma unroll
+        for (int u = 0; u < kLinkBatch; ++u) {
+            const float2 c = cb[u];
+            if (q + u < qe && fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz) {
+                const int slot = cnt - skip;
+                if (slot >= 0 && slot < kSlots) {
+                    const float sy = above ? (c.x - yh) / dx : (yh - c.x) / dx;
+                    const float sz = above ? (c.y - zh) / dx : (zh - c.y) / dx;
+#pragma unroll
+                    for (int m = 0; m < kSlots; ++m)
+                        if (m == slot) { ty[m] = sy; tz[m] = sz; kk[m] = (int)(q + u); }
+                }
+                ++cnt;
             }
-            ++cnt;
         }
-        ++q;
+        q += kLinkBatch;
     }
     return cnt;
 }
 
-__global__ void __launch_bounds__(256) k_links(Batch B, DevParams P, int64_t g0, int64_t g1)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_links(Batch B, DevParams P, int64_t g0, int64_t g1)
 {
 #pragma clang fp contract(off)
     const int nr = P.n_rows;
@@ -589,22 +597,27 @@ __global__ void __launch_bounds__(256) k_links(Batch B, DevParams P, int64_t g0,
                             qe = D.bs[iz * D.ny + dy1 + 1];
                         }
                         if (q >= qe) break;
-                        const float2 c = yzd[q];
-                        if (fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz) {
-                            const float ty = (yh - c.x) / dxd;
-                            const float tz = (zh - c.y) / dxd;
+                        float2 cb[kLinkBatch];
 #pragma unroll
-                            for (int i = 0; i < kSlots; ++i) {
-                                if (i < nu) {
-                                    const float ay = uty[i] - ty;
-                                    const float az = utz[i] - tz;
-                                    const float sy = ay * ay;
-                                    const float sz = az * az;
-                                    link_consider(best, sy + sz, uk[i], (int)q, kmax, pu, pd);
+                        for (int u = 0; u < kLinkBatch; ++u) cb[u] = yzd[min(q + (uint32_t)u, qe - 1u)];
+                        for (int u = 0; u < kLinkBatch; ++u) {
+                            const float2 c = cb[u];
+                            if (q + u < qe && fabsf(c.x - yh) <= wy && fabsf(c.y - zh) <= wz) {
+                                const float ty = (yh - c.x) / dxd;
+                                const float tz = (zh - c.y) / dxd;
+#pragma unroll
+                                for (int i = 0; i < kSlots; ++i) {
+                                    if (i < nu) {
+                                        const float ay = uty[i] - ty;
+                                        const float az = utz[i] - tz;
+                                        const float sy = ay * ay;
+                                        const float sz = az * az;
+                                        link_consider(best, sy + sz, uk[i], (int)(q + u), kmax, pu, pd);
+                                    }
                                 }
                             }
                         }
-                        ++q;
+                        q += kLinkBatch;
                     }
                 }
                 if (us + kSlots >= nu_all) break;
