@@ -379,7 +379,7 @@ void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t
 // Scratch of one merge call: T = input track capacity, K = n_tf * n_sectors.
 struct MergeLayout {
     size_t total = 0;
-    size_t ends, a_list, b_list, sec_first, cnt, brec, bidx, brec_s, bidx_s, zs, lsorted, mstate, bestB, bestChi,
+    size_t ends, a_list, a_idx, b_list, sec_first, cnt, brec, bidx, brec_s, bidx_s, zs, lsorted, mstate, bestB, bestChi,
         keepChi, keepA;
     size_t next, prev, nseg, chain_hits, fit_ok, diss, lead, nh, fit_list, seg_head, seg_pre, fit_off, grec, m_idx,
         m_hpos, scan_part;
@@ -393,6 +393,7 @@ MergeLayout make_merge_layout(int64_t T, int64_t K, int64_t H)
     const size_t t = (size_t)(T > 0 ? T : 1), k = (size_t)(K > 0 ? K : 1);
     L.ends = take(t * 16);
     L.a_list = take(t * 4);
+    L.a_idx = take(t * 4);
     L.b_list = take(t * 4);
     L.sec_first = take(k * 4);
     L.cnt = take(2 * k * 4);
@@ -489,6 +490,7 @@ extern "C" tpcsf_status tpcsf_merge(tpcsf_ctx* c, const tpcsf_frame* f, const tp
     M.n_tf = f->n_tf;
     M.ends = (float4*)(a + L.ends);
     M.a_list = (int32_t*)(a + L.a_list);
+    M.a_idx = (int32_t*)(a + L.a_idx);
     M.b_list = (int32_t*)(a + L.b_list);
     M.sec_first = (int32_t*)(a + L.sec_first);
     M.cnt = (int32_t*)(a + L.cnt);

@@ -180,6 +180,7 @@ struct MergeCounters {
     int32_t n_fit;                  // chains of several segments
     int32_t bad;                    // invalid input seen: nothing is merged
     unsigned long long fit_hits;    // clusters of those chains (gather offsets)
+    int32_t n_outer;                // outer ends listed in a_idx
     // algorithmic work: candidate pairs through the gate, their propagations (attempts),
     // chi2 evaluations; merged-fit rotations, propagations, updates
     int64_t work[6];
@@ -199,6 +200,7 @@ struct MergeBatch {
     // scratch
     float4* ends;                   // [T] innermost (x, y) and outermost (x, y) cluster
     int32_t* a_list;                // [T] list an outer end is matched against, or -1
+    int32_t* a_idx;                 // [T] the tracks with an outer end, compactly (any order)
     int32_t* b_list;                // [T] list of an inner end, or -1
     int32_t* sec_first;             // [K] first track of each (time frame, sector)
     int32_t* cnt;                   // [2K] entries per list (list = key * 2 + edge)

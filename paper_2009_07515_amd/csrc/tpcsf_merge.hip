@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_init(MergeBatch M, int64_t 
         M.mc->n_fit = 0;
         M.mc->bad = 0;
         M.mc->fit_hits = 0;
+        M.mc->n_outer = 0;
         for (int k = 0; k < 6; ++k) M.mc->work[k] = 0;
     }
     for (int64_t i = i0; i < M.cap_tracks; i += stride) {
@@ -227,10 +228,29 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_lists(MergeBatch M)
 {
     if (M.mc->bad) return;
     const int64_t T = M.mc->T;
-    const int lane = threadIdx.x & 63;
+    __shared__ int32_t wcnt[kMergeThreads / 64];
+    __shared__ int32_t bbase;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < T; t0 += stride) {
-        const int64_t t = t0 + lane;
+    for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < T; b0 += stride) {   // block-uniform
+        const int64_t t = b0 + threadIdx.x;
+        // the outer ends, listed compactly for the match (one atomic per block)
+        const bool oe = t < T && M.a_list[t] >= 0;
+        const uint64_t om = __ballot(oe);
+        if (lane == 0) wcnt[wv] = (int32_t)__popcll(om);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t tot = 0;
+            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+                const int32_t c = wcnt[k];
+                wcnt[k] = tot;
+                tot += c;
+            }
+            bbase = tot > 0 ? atomicAdd(&M.mc->n_outer, tot) : 0;
+        }
+        __syncthreads();
+        if (oe) M.a_idx[bbase + wcnt[wv] + (int32_t)__popcll(om & ((1ull << lane) - 1ull))] = (int32_t)t;
+        __syncthreads();   // wcnt and bbase are reused by the next pass
         const int32_t L = t < T ? M.b_list[t] : -1;
         uint64_t todo = __ballot(L >= 0);
         int32_t pos = 0;
@@ -317,17 +337,19 @@ __global__ void __launch_bounds__(kSortThreads) k_m_sort(MergeBatch M, int64_t n
 }
 
 // ------------------------------------------------------------------------------------
-// 3: each outer end's least-chi2 inner end; the least chi2 per inner end
+// 3: each outer end's least-chi2 inner end; the least chi2 per inner end (a lane per
+// listed outer end)
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kMergeThreads) k_m_match(MergeBatch M, DevParams P, MergeParams Q)
 {
     if (M.mc->bad) return;
-    const int64_t T = M.mc->T;
+    const int64_t n_outer = M.mc->n_outer;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t n_gate = 0, n_prop = 0, n_chi2 = 0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += stride) {
+    // over the listed outer ends, so that every lane has one
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_outer; i += stride) {
+        const int64_t t = M.a_idx[i];
         const int32_t L = M.a_list[t];
-        if (L < 0) continue;
         const int32_t n = M.cnt[L];
         if (n == 0) continue;
         const int64_t base = (int64_t)(L & 1) * M.cap_tracks + M.sec_first[L >> 1];
