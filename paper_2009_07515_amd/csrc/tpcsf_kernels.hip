@@ -1569,6 +1569,8 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 // input cluster indices (from the kept list), each track's z at the beam line and, on
 // request, its outer state.  Writes beyond the caller's capacity are dropped and flagged.
 // ------------------------------------------------------------------------------------
+constexpr int kEmitTracks = 4;   // hit lists copied per pass of the emit
+
 __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
@@ -1614,16 +1616,33 @@ __global__ void __launch_bounds__(256) k_emit(Batch B, DevParams P)
                 }
             }
         }
+        // four tracks' hit lists per pass, the loads of all four issued before the stores
         uint64_t todo = __ballot(on);
         while (todo != 0ull) {
-            const int l = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1ull;
-            const int64_t d = __shfl(hp, l, 64), sj = __shfl(src, l, 64);
-            const int m = __shfl(nk, l, 64);
-            for (int q = lane; q < m; q += 64) {
-                const float4 e = B.kept_list[sj + q];
-                B.o_hit_ids[d + q] = __float_as_int(e.w);
-                if (B.o_hit_rec) B.o_hit_rec[d + q] = e;
+            int64_t d[kEmitTracks], sj[kEmitTracks];
+            int m[kEmitTracks];
+            int mm = 0;
+#pragma unroll
+            for (int u = 0; u < kEmitTracks; ++u) {
+                const int l = todo != 0ull ? __ffsll((unsigned long long)todo) - 1 : 0;
+                const bool has = todo != 0ull;
+                todo &= todo - 1ull;
+                d[u] = __shfl(hp, l, 64);
+                sj[u] = __shfl(src, l, 64);
+                m[u] = has ? __shfl(nk, l, 64) : 0;
+                mm = max(mm, m[u]);
+            }
+            for (int q = lane; q < mm; q += 64) {
+                float4 e[kEmitTracks];
+#pragma unroll
+                for (int u = 0; u < kEmitTracks; ++u)
+                    e[u] = q < m[u] ? B.kept_list[sj[u] + q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                for (int u = 0; u < kEmitTracks; ++u) {
+                    if (q >= m[u]) continue;
+                    B.o_hit_ids[d[u] + q] = __float_as_int(e[u].w);
+                    if (B.o_hit_rec) B.o_hit_rec[d[u] + q] = e[u];
+                }
             }
         }
     }

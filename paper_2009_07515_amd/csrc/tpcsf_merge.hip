@@ -726,30 +726,62 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_emit(MergeBatch M, DevParam
 }
 
 // 10: every input track's clusters into its merged track's hit list, and its entry in the
-// input-to-merged map; one wave per input track
+// input-to-merged map; a wave takes 64 input tracks
+constexpr int kCopyTracks = 4;   // hit lists copied per pass
+
 __global__ void __launch_bounds__(kMergeThreads) k_m_copy(MergeBatch M)
 {
     if (M.mc->bad) return;
     const int64_t T = M.mc->T;
     const int lane = threadIdx.x & 63;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < T; u += nw) {
-        const int32_t head = M.seg_head[u];
-        if (head < 0) continue;
-        const bool whole = M.prev[head] < 0 && M.nseg[head] >= 2 && M.fit_ok[head];
-        int64_t m, dst;
-        if (whole) {
-            m = M.m_idx[head];
-            dst = M.m_hpos[head] + M.seg_pre[u];
-        } else {
-            if (!M.lead[u]) continue;
-            m = M.m_idx[u];
-            dst = M.m_hpos[u];
+    for (int64_t u0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; u0 < T; u0 += nw * 64) {
+        // each lane finds its track's place, then the wave copies the hit lists
+        const int64_t u = u0 + lane;
+        bool on = false;
+        int64_t dst = 0, hb = 0, n = 0;
+        if (u < T) {
+            const int32_t head = M.seg_head[u];
+            if (head >= 0) {
+                const bool whole = M.prev[head] < 0 && M.nseg[head] >= 2 && M.fit_ok[head];
+                int64_t m = -1;
+                if (whole) {
+                    m = M.m_idx[head];
+                    dst = M.m_hpos[head] + M.seg_pre[u];
+                } else if (M.lead[u]) {
+                    m = M.m_idx[u];
+                    dst = M.m_hpos[u];
+                }
+                hb = M.hit_off[u];
+                n = M.hit_off[u + 1] - hb;
+                on = m >= 0 && m < M.cap_merged && dst + n <= M.cap_hits;
+                if (on) M.o_track_merged[u] = (int32_t)m;
+            }
         }
-        const int64_t hb = M.hit_off[u], n = M.hit_off[u + 1] - hb;
-        if (m >= M.cap_merged || dst + n > M.cap_hits) continue;
-        if (lane == 0) M.o_track_merged[u] = (int32_t)m;
-        for (int64_t j = lane; j < n; j += 64) M.o_hit_ids[dst + j] = M.hit_ids[hb + j];
+        // kCopyTracks lists per pass, the loads of all of them issued before the stores
+        uint64_t todo = __ballot(on);
+        while (todo != 0ull) {
+            int64_t d[kCopyTracks], sb[kCopyTracks], c[kCopyTracks];
+            int64_t mm = 0;
+#pragma unroll
+            for (int k = 0; k < kCopyTracks; ++k) {
+                const bool has = todo != 0ull;
+                const int l = has ? __ffsll((unsigned long long)todo) - 1 : 0;
+                todo &= todo - 1ull;
+                d[k] = __shfl(dst, l, 64);
+                sb[k] = __shfl(hb, l, 64);
+                c[k] = has ? __shfl(n, l, 64) : 0;
+                mm = c[k] > mm ? c[k] : mm;
+            }
+            for (int64_t j = lane; j < mm; j += 64) {
+                int32_t h[kCopyTracks];
+#pragma unroll
+                for (int k = 0; k < kCopyTracks; ++k) h[k] = j < c[k] ? M.hit_ids[sb[k] + j] : 0;
+#pragma unroll
+                for (int k = 0; k < kCopyTracks; ++k)
+                    if (j < c[k]) M.o_hit_ids[d[k] + j] = h[k];
+            }
+        }
     }
 }
 
