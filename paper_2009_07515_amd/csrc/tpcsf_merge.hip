@@ -30,6 +30,7 @@ namespace tpcsf {
 namespace {
 
 constexpr int kMergeThreads = 256;
+constexpr int kCopyTracks = 4;   // hit lists copied per pass by the gather and copy kernels
 
 __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 {
@@ -513,20 +514,60 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_gather(MergeBatch M, DevPar
     const int lane = threadIdx.x & 63;
     int64_t* o = offs[threadIdx.x >> 6];
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    if (M.hit_rec) {
+        // the tracking call's own records of these clusters, contiguous: a wave takes 64
+        // input tracks, each lane finds its track's place, and the wave copies
+        // kCopyTracks lists per pass with the loads of all of them issued together
+        for (int64_t u0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; u0 < T; u0 += nw * 64) {
+            const int64_t u = u0 + lane;
+            bool on = false;
+            int64_t k = 0, hb = 0, n = 0;
+            int su = 0;
+            if (u < T) {
+                const int32_t head = M.seg_head[u];
+                if (head >= 0 && M.nseg[head] >= 2) {
+                    on = true;
+                    su = M.sector[u];
+                    k = M.fit_off[head] + M.seg_pre[u];
+                    hb = M.hit_off[u];
+                    n = M.hit_off[u + 1] - hb;
+                }
+            }
+            uint64_t todo = __ballot(on);
+            while (todo != 0ull) {
+                int64_t d[kCopyTracks], sb[kCopyTracks], c[kCopyTracks];
+                float sf[kCopyTracks];
+                int64_t mm = 0;
+#pragma unroll
+                for (int q = 0; q < kCopyTracks; ++q) {
+                    const bool has = todo != 0ull;
+                    const int l = has ? __ffsll((unsigned long long)todo) - 1 : 0;
+                    todo &= todo - 1ull;
+                    d[q] = __shfl(k, l, 64);
+                    sb[q] = __shfl(hb, l, 64);
+                    c[q] = has ? __shfl(n, l, 64) : 0;
+                    sf[q] = __int_as_float(__shfl(su, l, 64));
+                    mm = c[q] > mm ? c[q] : mm;
+                }
+                for (int64_t j = lane; j < mm; j += 64) {
+                    float4 e[kCopyTracks];
+#pragma unroll
+                    for (int q = 0; q < kCopyTracks; ++q)
+                        e[q] = j < c[q] ? M.hit_rec[sb[q] + j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                    for (int q = 0; q < kCopyTracks; ++q)
+                        if (j < c[q]) M.grec[d[q] + j] = make_float4(e[q].x, e[q].y, e[q].z, sf[q]);
+                }
+            }
+        }
+        return;
+    }
     for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < T; u += nw) {
         const int32_t head = M.seg_head[u];
         if (head < 0 || M.nseg[head] < 2) continue;
         const int su = M.sector[u];
         const int64_t k = M.fit_off[head] + M.seg_pre[u];
         const int64_t hb = M.hit_off[u], n = M.hit_off[u + 1] - hb;
-        if (M.hit_rec) {
-            // the tracking call's own records of these clusters, contiguous
-            for (int64_t j = lane; j < n; j += 64) {
-                const float4 e = M.hit_rec[hb + j];
-                M.grec[k + j] = make_float4(e.x, e.y, e.z, __int_as_float(su));
-            }
-            continue;
-        }
         const int64_t g0 = ((int64_t)M.tf[u] * ns + su) * nr;
         wave_lds_sync();
         for (int r = lane; r <= nr; r += 64) o[r] = M.off[g0 + r];
@@ -727,8 +768,6 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_emit(MergeBatch M, DevParam
 
 // 10: every input track's clusters into its merged track's hit list, and its entry in the
 // input-to-merged map; a wave takes 64 input tracks
-constexpr int kCopyTracks = 4;   // hit lists copied per pass
-
 __global__ void __launch_bounds__(kMergeThreads) k_m_copy(MergeBatch M)
 {
     if (M.mc->bad) return;
