@@ -98,7 +98,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2009_07515_amd.build` first")
     # torch ships its own HIP runtime under the same soname; load it first so that the
     # library and torch's allocator and streams share one runtime in this process
     import torch  # noqa: F401
