@@ -115,6 +115,9 @@ def _lib(mode):
         lib.orc_reject_frame.restype = C.c_int64
         lib.orc_compress_frame.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.POINTER(_Tracks), C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.orc_select.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.orc_select.restype = None
         lib.orc_merge_frame.argtypes = [C.POINTER(_Cfg), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.POINTER(_Tracks), C.POINTER(_Merged)]
         _LIBS[mode] = lib
@@ -292,6 +295,22 @@ class Oracle:
         return codes[:H], resid[:H], pred[:H]
 
     # -- single steps ----------------------------------------------------------------
+    def select(self, n_clusters, tl_n, rank, hits, shuffle_seed=0):
+        """Selection among one sector's tracklets (orc_select).  hits: [K, n_rows] cluster
+        index per row (-1 none).  Returns (W [n_clusters] uint64, weights [K] uint64,
+        kept [K] int32)."""
+        tl_n = np.ascontiguousarray(tl_n, dtype=np.int32)
+        rank = np.ascontiguousarray(rank, dtype=np.int64)
+        hits = np.ascontiguousarray(hits, dtype=np.int32)
+        K = int(tl_n.shape[0])
+        assert hits.shape == (K, self.n_rows)
+        W = np.zeros(max(n_clusters, 1), np.uint64)
+        wt = np.zeros(max(K, 1), np.uint64)
+        kept = np.zeros(max(K, 1), np.int32)
+        self.lib.orc_select(C.byref(self.cfg), int(n_clusters), K, _ptr(tl_n), _ptr(rank), _ptr(hits),
+                            int(shuffle_seed), _ptr(W), _ptr(wt), _ptr(kept))
+        return W[:n_clusters], wt[:K], kept[:K]
+
     def grid_row(self, y, z):
         y = np.ascontiguousarray(y, dtype=np.float32)
         z = np.ascontiguousarray(z, dtype=np.float32)

@@ -764,6 +764,54 @@ static uint64_t mix64(uint64_t* s)
 }
 
 /* ---------------------------------------------------------------------------------- */
+/* Step 6: selection.  A tracklet's weight is w = (n << 32) | (2^32 - 1 - rank): more     */
+/* clusters win, and at equal size the smaller start rank.  Every cluster takes the      */
+/* largest weight of the tracklets holding it; a tracklet keeps the clusters whose weight */
+/* is its own.  One pass: clusters a losing tracklet gives up are not handed on.        */
+/* Tracklets with fewer than min_track_hits clusters can neither be accepted nor outweigh */
+/* a longer one, so they do not take part (weight 0, nothing kept).                      */
+/* ---------------------------------------------------------------------------------- */
+void orc_select(const orc_cfg* cfg, int64_t n_clusters, int64_t n_tl, const int32_t* tl_n,
+                const int64_t* rank, const int32_t* hits, uint64_t shuffle_seed, uint64_t* W,
+                uint64_t* wt, int32_t* kept)
+{
+    const int nr = cfg->n_rows;
+    for (int64_t h = 0; h < n_clusters; ++h) W[h] = 0;
+    for (int64_t t = 0; t < n_tl; ++t) {
+        wt[t] = tl_n[t] < cfg->min_track_hits
+                    ? 0
+                    : ((uint64_t)tl_n[t] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)rank[t]);
+        kept[t] = 0;
+    }
+    /* visiting order: identity, or a shuffle that must not change the result */
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_tl > 0 ? n_tl : 1));
+    for (int64_t t = 0; t < n_tl; ++t) order[t] = t;
+    if (shuffle_seed) {
+        uint64_t st = shuffle_seed;
+        for (int64_t t = n_tl - 1; t > 0; --t) {
+            int64_t j = (int64_t)(mix64(&st) % (uint64_t)(t + 1));
+            int64_t tmp = order[t]; order[t] = order[j]; order[j] = tmp;
+        }
+    }
+    for (int64_t q = 0; q < n_tl; ++q) {
+        const int64_t t = order[q];
+        if (wt[t] == 0) continue;
+        for (int r = 0; r < nr; ++r) {
+            const int32_t h = hits[t * nr + r];
+            if (h >= 0 && wt[t] > W[h]) W[h] = wt[t];
+        }
+    }
+    for (int64_t t = 0; t < n_tl; ++t) {
+        if (wt[t] == 0) continue;
+        for (int r = 0; r < nr; ++r) {
+            const int32_t h = hits[t * nr + r];
+            if (h >= 0 && W[h] == wt[t]) kept[t] += 1;
+        }
+    }
+    free(order);
+}
+
+/* ---------------------------------------------------------------------------------- */
 /* Driver: every sector independently, in frame order.                                */
 /* ---------------------------------------------------------------------------------- */
 int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
@@ -852,32 +900,22 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
                 ++k;
             }
 
-        /* Step 6: selection.  w = (n << 32) | (2^32 - 1 - rank); every cluster keeps the
-         * largest w of the tracklets that contain it; a tracklet keeps the clusters whose
-         * weight equals its own and is accepted if it keeps >= min_track_hits of them.
-         * Tracklets shorter than min_track_hits can never be accepted and cannot outweigh a
-         * longer one, so they do not take part. */
+        /* Step 6: selection (orc_select) over this sector's tracklets, ranked from n_tl */
         uint64_t* W = (uint64_t*)calloc(nn, sizeof(uint64_t));
-        int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_start > 0 ? n_start : 1));
-        for (int64_t t = 0; t < n_start; ++t) order[t] = t;
-        if (shuffle_seed) {
-            uint64_t st = shuffle_seed;
-            for (int64_t t = n_start - 1; t > 0; --t) {
-                int64_t j = (int64_t)(mix64(&st) % (uint64_t)(t + 1));
-                int64_t tmp = order[t]; order[t] = order[j]; order[j] = tmp;
-            }
-        }
-        for (int64_t q = 0; q < n_start; ++q) {
-            int64_t t = order[q];
-            if (tl_n[t] < cfg->min_track_hits) continue;
-            uint64_t w = ((uint64_t)tl_n[t] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)(n_tl + t));
+        const size_t ns1 = (size_t)(n_start > 0 ? n_start : 1);
+        int64_t* rank = (int64_t*)malloc(sizeof(int64_t) * ns1);
+        uint64_t* wt = (uint64_t*)malloc(sizeof(uint64_t) * ns1);
+        int32_t* kept = (int32_t*)malloc(sizeof(int32_t) * ns1);
+        int32_t* sel_hits = (int32_t*)malloc(sizeof(int32_t) * ns1 * (size_t)nr);
+        for (int64_t t = 0; t < n_start; ++t) {
+            rank[t] = n_tl + t;
             for (int r = 0; r < nr; ++r) {
                 int32_t c = tl_hits[t * nr + r];
-                if (c < 0) continue;
-                int64_t h = ro[r] - base + c;
-                if (w > W[h]) W[h] = w;
+                sel_hits[t * nr + r] = c < 0 ? -1 : (int32_t)(ro[r] - base + c);
             }
         }
+        orc_select(cfg, nsec, n_start, tl_n, rank, sel_hits, shuffle_seed, W, wt, kept);
+        free(sel_hits);
         if (dbg && dbg->W) memcpy(dbg->W + base, W, sizeof(uint64_t) * (size_t)nsec);
 
         /* Step 7: final fit of the accepted tracklets' kept clusters, in rank order */
@@ -886,8 +924,8 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
         orc_real* fz = fy + nr;
         int64_t* fid = (int64_t*)malloc(sizeof(int64_t) * (size_t)nr);
         for (int64_t t = 0; t < n_start; ++t) {
-            if (tl_n[t] < cfg->min_track_hits) continue;
-            uint64_t w = ((uint64_t)tl_n[t] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)(n_tl + t));
+            if (kept[t] < cfg->min_track_hits) continue;
+            const uint64_t w = wt[t];
             int32_t m = 0;
             for (int r = 0; r < nr; ++r) {
                 int32_t c = tl_hits[t * nr + r];
@@ -934,7 +972,7 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
             n_hits += m;
         }
         n_tl += n_start;
-        free(fx); free(fid); free(W); free(order); free(tl_hits); free(tl_n);
+        free(fx); free(fid); free(W); free(rank); free(wt); free(kept); free(tl_hits); free(tl_n);
         free(up); free(dn); free(cup); free(cdn); free(sidx);
     }
     out->n_tracks = n_tracks;
@@ -1088,9 +1126,7 @@ int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
         for (int i = 0; i < 5; ++i) A0.p[i] = (orc_real)trk->params_outer[a * 5 + i];
         for (int i = 0; i < 15; ++i) A0.C[i] = (orc_real)trk->cov_outer[a * 15 + i];
         if (krotate(cfg, &A0, frame_delta(cfg, sa, sb), NULL) != 0) continue;
-        /* slopes of the linear prediction: tan phi' and tan(lambda) / cos phi' */
         const orc_real c1 = R_SQRT(1 - A0.p[2] * A0.p[2]);
-        const orc_real ty = A0.p[2] / c1, tz = A0.p[3] / c1;
         for (int64_t j = sec_start[sb]; j < sec_start[sb + 1]; ++j) {
             const int64_t b = sec_list[j];
             if (up ? !(yi[b] < 0) : !(yi[b] >= 0)) continue;
@@ -1098,8 +1134,9 @@ int orc_merge_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
             if (!(xi[b] * xi[b] + yi[b] * yi[b] > ro2)) continue;
             const double* pb = trk->params + b * 5;
             const orc_real dx = (orc_real)xi[b] - A0.x;
-            const orc_real ylin = A0.p[0] + dx * ty;
-            const orc_real zlin = A0.p[1] + dx * tz;
+            /* linear prediction at B's row: y' + dx tan phi', z' + dx tan(lambda) / cos phi' */
+            const orc_real ylin = A0.p[0] + dx * A0.p[2] / c1;
+            const orc_real zlin = A0.p[1] + dx * A0.p[3] / c1;
             if (!(R_FABS(ylin - (orc_real)pb[0]) <= (orc_real)W && R_FABS(zlin - (orc_real)pb[1]) <= (orc_real)W))
                 continue;
             kstate A1 = A0;

@@ -108,6 +108,18 @@ int orc_track_frame(const orc_cfg* cfg, int64_t n, const float* y, const float* 
                     const int64_t* row_off, orc_tracks* out, orc_debug* dbg,
                     uint64_t shuffle_seed);
 
+/* Selection among the tracklets of one sector.  hits[t*n_rows + r] is the cluster of
+ * tracklet t at row r as an index into the sector's n_clusters clusters (-1: none);
+ * tl_n[t] its cluster count, rank[t] the frame rank of its start.  Tracklets with
+ * tl_n >= min_track_hits take part with the weight w = (n << 32) | (2^32 - 1 - rank)
+ * (wt[t], 0 for the others); W[h] receives the largest weight of the tracklets holding
+ * cluster h (0: none), kept[t] the clusters of t whose W equals its own weight.  A
+ * tracklet is accepted when kept >= min_track_hits.  shuffle_seed != 0 visits the
+ * tracklets in a pseudo-random order (the result must not change). */
+void orc_select(const orc_cfg* cfg, int64_t n_clusters, int64_t n_tl, const int32_t* tl_n,
+                const int64_t* rank, const int32_t* hits, uint64_t shuffle_seed, uint64_t* W,
+                uint64_t* wt, int32_t* kept);
+
 /* Grid of one row (binary32).  bin_start has room for cap entries.  Returns 0 or -3. */
 int orc_grid_row(const orc_cfg* cfg, int64_t n, const float* y, const float* z,
                  float* ylo, float* zlo, float* by, float* bz, int32_t* ny, int32_t* nz,

@@ -4,6 +4,14 @@ Contract: the links between sector tracks, the merged tracks' composition, order
 lists, and the input-to-merged map are identical to the oracle's; merged parameters are
 within 1e-4 of the oracle's, |dp_i| <= 1e-4 * max(|p_i|, f_i) with floors
 f = (10 cm, 10 cm, 0.1, 0.1, 0.1 c/GeV), covariance diagonals alike, chi2 to 1e-6.
+
+The gate and chi2 cuts are binary64 decisions whose operands the GPU rounds in its own
+order, so a pair lying within rounding of a cut may be decided the other way.  Such a
+link difference is accepted, and counted, only if the oracle itself takes the GPU's
+decision for that outer end once its cuts move by a small relative band (1e-12 when both
+merge the same tracks; 1e-8 when the oracle merges its own tracks, whose parameters
+differ from the GPU's by ~1e-9); the merged tracks holding those ends are then left out
+of the element-wise comparison.
 """
 import numpy as np
 import pytest
@@ -41,21 +49,81 @@ def _close(a, b):
     assert np.all(err <= tol), (err / tol).max(axis=0)
 
 
-def _check_same_merge(g, o, label=""):
-    assert g["n_merged"] == o["n_merged"], label
-    assert np.array_equal(g["next"], o["next"]), label
-    assert np.array_equal(g["track_merged"], o["track_merged"]), label
-    assert np.array_equal(g["hit_off"], o["hit_off"]), label
-    assert np.array_equal(g["hit_ids"].astype(np.int64), o["hit_ids"]), label
+def _members(m):
+    """Input tracks of every merged track, in chain order (head first)."""
+    T = len(m["track_merged"])
+    nxt = np.asarray(m["next"])
+    has_prev = np.zeros(T, bool)
+    has_prev[nxt[nxt >= 0]] = True
+    chains = {}
+    for h in np.flatnonzero(~has_prev):
+        c, t = [], int(h)
+        while t >= 0:
+            c.append(t)
+            t = int(nxt[t])
+        chains[int(m["track_merged"][h])] = tuple(c)
+    return chains
+
+
+def _borderline_links(g, o, frame, tracks, row_x, band):
+    """Outer ends whose GPU link differs from the oracle's; each must be reproduced by the
+    oracle with its gate window or chi2 cut moved by `band` relative."""
+    diff = np.flatnonzero(g["next"] != o["next"])
+    if diff.size == 0:
+        return diff
+    p = oracle.DEFAULT_PARAMS
+    alt = []
+    for key in ("merge_window", "merge_chi2"):
+        for f in (1 - band, 1 + band):
+            oo = oracle.Oracle(row_x, params={key: p[key] * f})
+            alt.append(oo.merge_frame(frame.y, frame.z, frame.row_off, tracks)["next"])
+    for a in diff:
+        assert any(n[a] == g["next"][a] for n in alt), f"outer end {a}: link {g['next'][a]} vs {o['next'][a]}"
+    return diff
+
+
+def _check_same_merge(g, o, label="", frame=None, tracks=None, row_x=None, band=1e-12):
+    diff = np.zeros(0, np.int64)
+    if frame is not None and not np.array_equal(g["next"], o["next"]):
+        diff = _borderline_links(g, o, frame, tracks, row_x, band)
+    print(f"{label}: {diff.size} link decisions within rounding of a cut")
+    if diff.size == 0:
+        assert g["n_merged"] == o["n_merged"], label
+        assert np.array_equal(g["next"], o["next"]), label
+        assert np.array_equal(g["track_merged"], o["track_merged"]), label
+        assert np.array_equal(g["hit_off"], o["hit_off"]), label
+        assert np.array_equal(g["hit_ids"].astype(np.int64), o["hit_ids"]), label
+        gi = oi = np.arange(g["n_merged"])
+    else:
+        # compare the merged tracks made of the same input tracks, none of them touched
+        touched = set(int(a) for a in diff)
+        for a in diff:
+            touched.update(int(v) for v in (g["next"][a], o["next"][a]) if v >= 0)
+        cg, co = _members(g), _members(o)
+        by_members = {c: k for k, c in co.items()}
+        gi, oi = [], []
+        for k in sorted(cg):
+            c = cg[k]
+            if touched.isdisjoint(c):
+                assert c in by_members, (label, c)
+                gi.append(k)
+                oi.append(by_members[c])
+        gi, oi = np.array(gi, np.int64), np.array(oi, np.int64)
+        assert len(gi) >= len(cg) - 4 * diff.size
+        for kg, ko in zip(gi, oi):
+            hg = g["hit_ids"][g["hit_off"][kg]:g["hit_off"][kg + 1]].astype(np.int64)
+            ho = o["hit_ids"][o["hit_off"][ko]:o["hit_off"][ko + 1]]
+            assert np.array_equal(hg, ho), label
     for k in ("n_segments", "sector", "nhits", "ndf"):
-        assert np.array_equal(g[k], o[k]), (label, k)
-    assert np.array_equal(g["x_ref"], o["x_ref"])
-    _close(g["params"], o["params"])
-    sg, so = np.sqrt(g["cov"][:, [0, 2, 5, 9, 14]]), np.sqrt(o["cov"][:, [0, 2, 5, 9, 14]])
+        assert np.array_equal(g[k][gi], o[k][oi]), (label, k)
+    assert np.array_equal(g["x_ref"][gi], o["x_ref"][oi])
+    _close(g["params"][gi], o["params"][oi])
+    sg, so = np.sqrt(g["cov"][gi][:, [0, 2, 5, 9, 14]]), np.sqrt(o["cov"][oi][:, [0, 2, 5, 9, 14]])
     assert np.all(np.abs(sg - so) <= 1e-4 * so)
-    assert np.allclose(g["chi2"], o["chi2"], rtol=1e-6, atol=1e-9)
-    assert np.all(np.abs(g["z_beam"] - o["z_beam"]) <= 1e-4 * np.maximum(np.abs(o["z_beam"]), 10.0))
-    links = o["next"] >= 0
+    assert np.allclose(g["chi2"][gi], o["chi2"][oi], rtol=1e-6, atol=1e-9)
+    zg, zo = g["z_beam"][gi], o["z_beam"][oi]
+    assert np.all(np.abs(zg - zo) <= 1e-4 * np.maximum(np.abs(zo), 10.0))
+    links = (o["next"] >= 0) & (g["next"] == o["next"])
     assert np.allclose(g["link_chi2"][links], o["link_chi2"][links], rtol=1e-6, atol=1e-9)
 
 
@@ -71,7 +139,8 @@ def test_merge_parity_with_oracle(which, rec, small_pbpb_frame, cfg2_frame, row_
     so = np.sqrt(r["cov_outer"][:, [0, 2, 5, 9, 14]])
     assert np.all(np.abs(np.sqrt(tracks["cov_outer"][:, [0, 2, 5, 9, 14]]) - so) <= 1e-4 * so)
     m = o.merge_frame(f.y, f.z, f.row_off, r)
-    _check_same_merge(merged, m, which)
+    # the oracle merges its own tracks, whose parameters differ from the GPU's by ~1e-9
+    _check_same_merge(merged, m, which, f, r, row_x, band=1e-8)
     n_multi = int(np.sum(merged["n_segments"] >= 2))
     print(f"{which}: {tracks['n_tracks']} sector tracks -> {merged['n_merged']} merged, {n_multi} of several")
     assert n_multi > 0
@@ -88,7 +157,7 @@ def test_merge_of_the_full_time_frame_equals_oracle_merge_of_the_same_tracks(row
     _, tracks, merged = _gpu_tracks_and_merge(f, trk=trk, hit_rec=True)
     o = oracle.Oracle(row_x)
     m = o.merge_frame(f.y, f.z, f.row_off, tracks)
-    _check_same_merge(merged, m, "cfg3")
+    _check_same_merge(merged, m, "cfg3", f, tracks, row_x)
     print(f"cfg3: {tracks['n_tracks']} sector tracks -> {merged['n_merged']} merged")
 
 
