@@ -54,7 +54,7 @@ typedef struct tpcsf_ctx tpcsf_ctx;
  * x = row_x[r] of the sector frame; rows must be strictly increasing in x. */
 typedef struct {
     int32_t n_sectors;        /* sectors per time frame (36)                      */
-    int32_t n_rows;           /* pad rows per sector (152); 3 <= n_rows <= 256     */
+    int32_t n_rows;           /* pad rows per sector (152); 3 <= n_rows <= 255     */
     const float* row_x;       /* [host] [n_rows] row plane positions (cm)           */
     double bz;                /* solenoid field along z (T)                         */
 } tpcsf_geometry;
@@ -84,8 +84,8 @@ typedef struct {
  *   bins (the z bin, then the y bin, doubles until it fits).
  *   block: threads per block of the row kernels (64..1024, multiple of 64).
  *   tl_block: threads per block of the tracklet kernel (64..256, multiple of 64).
- *   chunk: idle lanes at which a tracklet wave takes new work from the queue (1..64;
- *   a wave with no busy lane always takes work). */
+ *   chunk: work-queue chunk of the persistent tracklet kernel: a wave takes 64 * chunk
+ *   tracklets per queue atomic and sweeps them 64 at a time (1..64). */
 typedef struct {
     float bin_y, bin_z;
     int32_t cap_mul, cap_add;
@@ -181,6 +181,22 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_t
 tpcsf_status tpcsf_autotune(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_tracks* out,
                             const tpcsf_tuning* points, int32_t n_points, int32_t reps, float* ms_out,
                             int32_t* best, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): tpcsf_track_batch with the scratch in a
+ * fixed device array of TPCSF_NOALLOC_SCRATCH_BYTES per GPU instead of the context's arena.
+ * The call allocates nothing (no hipMalloc, hipFree or graph instantiation): it validates
+ * on the host and launches the stage sequence eagerly on `stream`; the outputs are the
+ * same as tpcsf_track_batch's.  The caller still provides every input and output buffer.
+ * A batch whose scratch (tpcsf_arena_bytes without a reservation, about 320 bytes per
+ * cluster, so up to roughly 800k clusters) exceeds the array is refused with
+ * TPCSF_E_NOMEM before anything is launched.  The array exists once per GPU and is shared
+ * by every context and thread on it, is not counted against the HBM budget, is held until
+ * the process ends and keeps the last call's contents: calls that overlap on one GPU race,
+ * so the caller must order them (one stream, or events).  tpcsf_debug and tpcsf_reject
+ * after this call read that array. */
+#define TPCSF_NOALLOC_SCRATCH_BYTES (256ull << 20)
+tpcsf_status tpcsf_track_batch_noalloc(tpcsf_ctx* ctx, const tpcsf_frame* frame, tpcsf_tracks* out, void* stream);
 
 /* Wait for the stream and report errors the device found since the last sync:
  * TPCSF_E_INVALID (non-finite or |coordinate| > 1e5 cm), TPCSF_E_CAPACITY, or TPCSF_OK. */

@@ -143,7 +143,7 @@ static int in_window(float yc, float zc, float yh, float zh, float wy, float wz)
 }
 
 /* y-sorted order of a row's clusters (ties by in-row index), for window scans */
-static const float* g_sort_y;
+static __thread const float* g_sort_y;   /* per thread: callers may track sectors in parallel */
 static int cmp_y(const void* a, const void* b)
 {
     int32_t i = *(const int32_t*)a, j = *(const int32_t*)b;

@@ -9,10 +9,40 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace tpcsf;
+
+// Scratch of tpcsf_track_batch_noalloc: one fixed array per GPU, held from the loading of
+// the library's code on that GPU until the process ends.  In host code `scratch` names
+// only a host-side stand-in: its device address on each GPU comes from
+// hipGetSymbolAddress (at context creation, with that GPU current) and is kept in
+// g_scratch_ptr; that address, never the name, is what kernels receive.
+static __device__ __align__(256) unsigned char scratch[TPCSF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's fixed scratch array (looked up once per device).
+hipError_t scratch_setup(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -63,6 +93,7 @@ struct tpcsf_ctx {
     Counters* d_ctr = nullptr;
     void* arena = nullptr;
     size_t arena_size = 0;
+    void* fixed_scratch = nullptr;  // this device's fixed scratch array (tpcsf_track_batch_noalloc)
     void* marena = nullptr;         // scratch of tpcsf_merge
     size_t marena_size = 0;
     void* rarena = nullptr;         // scratch of tpcsf_reject
@@ -97,10 +128,11 @@ tpcsf_status hip_fail(tpcsf_ctx* c, hipError_t e, const char* what)
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf)
+// Scratch layout of a batch; `reserved` applies the capacity fixed by tpcsf_reserve.
+Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf, bool reserved = true)
 {
-    if (n < c->reserve_n) n = c->reserve_n;
-    if (n_tf < c->reserve_tf) n_tf = c->reserve_tf;
+    if (reserved && n < c->reserve_n) n = c->reserve_n;
+    if (reserved && n_tf < c->reserve_tf) n_tf = c->reserve_tf;
     Layout L;
     L.n = n;
     L.R = (int64_t)n_tf * c->n_sectors * c->n_rows;
@@ -276,9 +308,8 @@ tpcsf_status ensure_arena(tpcsf_ctx* c, const Layout& L)
     return TPCSF_OK;
 }
 
-Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcsf_tracks* o)
+Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcsf_tracks* o, char* a)
 {
-    char* a = (char*)c->arena;
     Batch B;
     B.y = f->y; B.z = f->z; B.off = f->row_offsets; B.n = L.n;
     B.n_rows_total = (int32_t)((int64_t)f->n_tf * c->n_sectors * c->n_rows);
@@ -735,7 +766,8 @@ tpcsf_status tpcsf_create(const tpcsf_geometry* geo, const tpcsf_params* params,
 {
     if (!out) return TPCSF_E_INVALID;
     *out = nullptr;
-    if (!geo || !geo->row_x || geo->n_sectors < 1 || geo->n_rows < 3 || geo->n_rows > kMaxRows) return TPCSF_E_INVALID;
+    if (!geo || !geo->row_x || geo->n_sectors < 1 || geo->n_rows < 3 || geo->n_rows > kMaxRowsGeo)
+        return TPCSF_E_INVALID;
     for (int r = 0; r + 1 < geo->n_rows; ++r)
         if (!(geo->row_x[r + 1] > geo->row_x[r])) return TPCSF_E_INVALID;
     if (!(geo->bz == geo->bz) || geo->bz > 100.0 || geo->bz < -100.0) return TPCSF_E_INVALID;
@@ -758,6 +790,7 @@ tpcsf_status tpcsf_create(const tpcsf_geometry* geo, const tpcsf_params* params,
     if ((e = hipGetDeviceProperties(&prop, c->device)) != hipSuccess) { delete c; return TPCSF_E_HIP; }
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->grid_lds_max = grid_lds_setup((int)prop.sharedMemPerBlock);
+    if ((e = scratch_setup(c->device, &c->fixed_scratch)) != hipSuccess) { delete c; return TPCSF_E_HIP; }
     if ((e = hipMalloc(&c->d_rx, sizeof(float) * c->n_rows)) != hipSuccess) { delete c; return TPCSF_E_NOMEM; }
     if ((e = hipMalloc(&c->d_ctr, sizeof(Counters))) != hipSuccess) {
         (void)hipFree(c->d_rx);
@@ -818,7 +851,7 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
     const Layout L = make_layout(c, f->n_clusters, f->n_tf);
     if ((st = ensure_arena(c, L)) != TPCSF_OK) return st;
     c->lay = L;
-    const Batch B = make_batch(c, L, f, o);
+    const Batch B = make_batch(c, L, f, o, (char*)c->arena);
     const DevParams P = dev_params(c);
     const LaunchCfg LC = launch_cfg(c);
     hipStream_t s = (hipStream_t)stream;
@@ -859,7 +892,7 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
     const Layout L = make_layout(c, f->n_clusters, f->n_tf);
     if ((st = ensure_arena(c, L)) != TPCSF_OK) return st;
     c->lay = L;
-    const Batch B = make_batch(c, L, f, o);
+    const Batch B = make_batch(c, L, f, o, (char*)c->arena);
     GraphKey k;
     std::memset(&k, 0, sizeof k);
     // the layout (not the cluster count) fixes every kernel argument
@@ -904,6 +937,30 @@ tpcsf_status tpcsf_track_batch(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
         c->gkey = k;
     }
     if ((e = hipGraphLaunch(c->gexec, (hipStream_t)stream)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    c->timed_last = false;
+    c->last = B;
+    c->last_P = dev_params(c);
+    c->have_last = true;
+    return TPCSF_OK;
+}
+
+tpcsf_status tpcsf_track_batch_noalloc(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks* o, void* stream)
+{
+    if (!c) return TPCSF_E_INVALID;
+    tpcsf_status st = check_frame(c, f, o);
+    if (st != TPCSF_OK) return st;
+    if (!c->fixed_scratch) return fail(c, TPCSF_E_HIP, "the fixed scratch array of this device is not set up");
+    // the exact layout of this batch (no reservation), inside the fixed array
+    const Layout L = make_layout(c, f->n_clusters, f->n_tf, false);
+    if (L.total > (size_t)TPCSF_NOALLOC_SCRATCH_BYTES)
+        return fail(c, TPCSF_E_NOMEM, "the batch needs " + std::to_string(L.total) +
+                                          " bytes of scratch; the fixed array of tpcsf_track_batch_noalloc holds " +
+                                          std::to_string((size_t)TPCSF_NOALLOC_SCRATCH_BYTES));
+    const Batch B = make_batch(c, L, f, o, (char*)c->fixed_scratch);
+    // eager launches: the same sequence as the batched form's graph, no allocation
+    enqueue_batch(c, B, (hipStream_t)stream, nullptr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
     c->timed_last = false;
     c->last = B;
     c->last_P = dev_params(c);

@@ -6,7 +6,9 @@
 
 namespace tpcsf {
 
-constexpr int kMaxRows = 256;
+constexpr int kMaxRows = 256;      // row tables are sized for this many rows
+constexpr int kMaxRowsGeo = 255;   // rows a geometry may have: a tracklet's cluster count
+                                   // fills the 8 high bits of its selection weight
 constexpr uint16_t kNoHit = 0xFFFF;
 constexpr int kScanBlocks = 256;     // blocks of the device-wide scan
 constexpr int kScanThreads = 256;
@@ -155,7 +157,7 @@ struct ScanJob {
 struct LaunchCfg {
     int block;      // row kernels
     int tl_block;   // tracklet kernels
-    int chunk;      // idle lanes that make a tracklet wave take new work
+    int chunk;      // groups of 64 tracklets a wave takes per work-queue atomic
     int n_cu;       // compute units
     int grid_lds;   // dynamic LDS bytes of the grid kernel
 };

@@ -988,7 +988,8 @@ __global__ void __launch_bounds__(256) k_order(Batch B, DevParams P)
 // (atomic max, order independent).  The claim is made by the lane that built the
 // tracklet, right after building it.  Weights are only ever compared within a sector, so
 // the rank counts from the sector's first start: w = (n << 24) | (2^24 - 1 - rank_s)
-// (n <= 255, rank_s < 2^24 since a sector holds < 2^24 starts).  Tracklets shorter than
+// (n <= n_rows <= 255, checked at context creation; rank_s < 2^24 since a sector of at
+// most 255 rows of < 65535 clusters holds < 2^23 starts).  Tracklets shorter than
 // min_track_hits can neither be accepted nor outweigh a longer one and do not take part.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P, int n, int64_t rank, int64_t gs)
@@ -1015,14 +1016,12 @@ __device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P
 // windows are shared between the lanes of the wave.
 // ------------------------------------------------------------------------------------
 // Hands work items of [lo, hi) to the idle lanes of a wave, in lane order.  The range is
-// split into one segment per XCD with a queue head each; a wave takes kGrab items of its
-// own XCD's segment at a time (one atomic per kGrab items) and moves on to the next
-// segment once its own is used up.  Returns -1 once every segment is used up.  `next`,
-// `end`, `seg` and `tried` are the wave's (uniform) queue state.
-constexpr int kGrab = 64;
-
-__device__ int64_t take_item(int32_t* heads, int64_t lo, int64_t hi, uint64_t idle, int64_t& next, int64_t& end,
-                             int& seg, int& tried)
+// split into one segment per XCD with a queue head each; a wave takes `grab` items of its
+// own XCD's segment at a time (one atomic per grab, the queue chunk of the tuning) and
+// moves on to the next segment once its own is used up.  Returns -1 once every segment
+// is used up.  `next`, `end`, `seg` and `tried` are the wave's (uniform) queue state.
+__device__ int64_t take_item(int32_t* heads, int64_t lo, int64_t hi, uint64_t idle, int grab, int64_t& next,
+                             int64_t& end, int& seg, int& tried)
 {
     const int parts = xcd_parts();
     const int want = __popcll(idle);
@@ -1035,7 +1034,7 @@ __device__ int64_t take_item(int32_t* heads, int64_t lo, int64_t hi, uint64_t id
             int64_t s0, s1;
             segment(lo, hi, seg, parts, s0, s1);
             int h = 0;
-            if (lane_id() == 0) h = atomicAdd(&heads[seg], kGrab);
+            if (lane_id() == 0) h = atomicAdd(&heads[seg], grab);
             h = __shfl(h, 0, 64);
             if (s0 + h >= s1) {
                 seg = (seg + 1) % parts;
@@ -1043,7 +1042,7 @@ __device__ int64_t take_item(int32_t* heads, int64_t lo, int64_t hi, uint64_t id
                 continue;
             }
             next = s0 + h;
-            end = (s0 + h + kGrab < s1) ? s0 + h + kGrab : s1;
+            end = (s0 + h + grab < s1) ? s0 + h + grab : s1;
         }
         const int64_t avail = end - next;
         const int take = (int64_t)(want - given) < avail ? want - given : (int)avail;
@@ -1078,13 +1077,13 @@ constexpr int kRowBatch = 8;   // rows per pass of the claim, keep and emit swee
 
 enum : int { kWait = 0, kFit = 1, kOut = 2, kUpDone = 3, kRefit = 4, kIn = 5, kDone = 6 };
 
-__global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P)
+__global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int grab)
 {
     const int nr = P.n_rows;
     int64_t q_next = 0, q_end = 0;
     int q_seg = (int)blockIdx.x % xcd_parts(), q_tried = 0;
     for (;;) {
-        const int64_t j = take_item(B.ctr->queue, 0, B.ctr->n_order, ~0ull, q_next, q_end, q_seg, q_tried);
+        const int64_t j = take_item(B.ctr->queue, 0, B.ctr->n_order, ~0ull, grab, q_next, q_end, q_seg, q_tried);
         if (__ballot(j >= 0) == 0ull) break;
         const int64_t p = j >= 0 ? (int64_t)B.order[j] : -1;
         const int L = p >= 0 ? B.tl_len[p] : 0;
@@ -1857,7 +1856,9 @@ void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hi
 {
     const int wpb = c.tl_block / 64;
     const int blocks = c.n_cu * (16 / wpb > 0 ? 16 / wpb : 1);
-    hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(c.tl_block), 0, s, b, p);
+    // a wave takes chunk groups of 64 tracklets per queue atomic and sweeps them one
+    // group after the other
+    hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(c.tl_block), 0, s, b, p, 64 * c.chunk);
 }
 
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)

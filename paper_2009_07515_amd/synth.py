@@ -401,6 +401,44 @@ def config4_frame(i, seed=None):
     return time_frame(s, length)
 
 
+@dataclasses.dataclass
+class LightFrame:
+    """A frame without its per-cluster truth beyond the labels (batches of many frames)."""
+    y: np.ndarray
+    z: np.ndarray
+    row_off: np.ndarray
+    label: np.ndarray
+    tf_length_us: float
+    n_events: int
+
+    @property
+    def n_clusters(self) -> int:
+        return int(self.y.shape[0])
+
+
+def _config4_light(i: int) -> LightFrame:
+    f = config4_frame(i)
+    return LightFrame(f.y, f.z, f.row_off, f.label, f.tf_length_us, f.n_events)
+
+
+def config4_batch(n_tf: int = 64, workers: int | None = None) -> list:
+    """Frames 0..n_tf-1 of the uneven batch (config4_frame), generated in worker processes
+    started afresh (spawned interpreters that import only this module, so that the caller
+    may already drive a GPU).  The frames are those of config4_frame, without the
+    per-cluster truth other than the labels."""
+    import multiprocessing
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    workers = workers or min(16, os.cpu_count() or 1, n_tf)
+    if workers <= 1:
+        return [_config4_light(i) for i in range(n_tf)]
+    # Pb-Pb frames (odd indices) first: the long tasks start early
+    order = sorted(range(n_tf), key=lambda i: (i % 2 == 0, i))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn")) as ex:
+        got = dict(zip(order, ex.map(_config4_light, order)))
+    return [got[i] for i in range(n_tf)]
+
+
 def concat_frames(frames):
     """Concatenate frames into one batch: y, z, label concatenated, row offsets chained."""
     offs = [np.int64(0)]

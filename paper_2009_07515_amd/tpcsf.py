@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtpcsf.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "tpcsf.h")
 
 OK, E_INVALID, E_NOMEM, E_CAPACITY, E_HIP, E_BUSY, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_SCRATCH_BYTES = 256 << 20   # TPCSF_NOALLOC_SCRATCH_BYTES of the header
 _NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_CAPACITY", -4: "E_HIP", -5: "E_BUSY",
           -6: "E_TIMEOUT"}
 
@@ -117,7 +118,7 @@ def load():
     lib.tpcsf_set_tuning.restype = C.c_int
     lib.tpcsf_arena_bytes.argtypes = [vp, C.c_int64, C.c_int32]
     lib.tpcsf_arena_bytes.restype = C.c_size_t
-    for fn in ("tpcsf_track_plain", "tpcsf_track_batch"):
+    for fn in ("tpcsf_track_plain", "tpcsf_track_batch", "tpcsf_track_batch_noalloc"):
         getattr(lib, fn).argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), vp]
         getattr(lib, fn).restype = C.c_int
     lib.tpcsf_merge.argtypes = [vp, C.POINTER(FrameDesc), C.POINTER(TracksDesc), C.POINTER(MergedDesc), vp]
@@ -388,7 +389,8 @@ class Tracker:
     def launch(self, frame: DeviceFrame, out: TrackBuffers, mode="batch", stream=None):
         """Enqueue one tracking call (no sync)."""
         fd, od = frame.desc(), out.desc()
-        fn = self.lib.tpcsf_track_batch if mode == "batch" else self.lib.tpcsf_track_plain
+        fn = {"batch": self.lib.tpcsf_track_batch, "plain": self.lib.tpcsf_track_plain,
+              "noalloc": self.lib.tpcsf_track_batch_noalloc}[mode]
         self._check(fn(self.h, C.byref(fd), C.byref(od), self._stream(stream)))
 
     def sync(self, stream=None):

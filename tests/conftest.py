@@ -48,3 +48,35 @@ def small_pbpb_frame():
 def row_x():
     from paper_2009_07515_amd import synth
     return synth.row_x()
+
+
+# the benchmark's tuning of the 2 ms frame (grid bins 2 x 4 cm, at most 4n + 64 bins per row)
+CFG3_TUNING = dict(bin_y=2.0, bin_z=4.0, cap_mul=4, block=512, tl_block=256, chunk=2)
+CFG3_GRID = dict(bin_y=2.0, bin_z=4.0, cap_mul=4, cap_add=64)
+
+
+@pytest.fixture(scope="session")
+def cfg3_frame():
+    """The 2 ms continuous-readout Pb-Pb time frame (27.1M clusters), generated once."""
+    from paper_2009_07515_amd import synth
+    return _frame("cfg3", synth.config3_time_frame)
+
+
+@pytest.fixture(scope="session")
+def cfg3_oracle(cfg3_frame, row_x):
+    """The FP64 oracle on the whole 2 ms frame with the benchmark's grid, sectors in
+    parallel."""
+    import oracle_sectors
+
+    def run():
+        f = cfg3_frame
+        return oracle_sectors.track_frame_parallel(row_x, f.y, f.z, f.row_off, grid=CFG3_GRID)
+    return _frame("cfg3_oracle", run)
+
+
+@pytest.fixture(scope="session")
+def cfg4_frames():
+    """The 64 frames of the uneven batch (pp-like and Pb-Pb-like alternating), generated
+    once in worker processes."""
+    from paper_2009_07515_amd import synth
+    return _frame("cfg4", lambda: synth.config4_batch(64))

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import CFG3_TUNING
 from paper_2009_07515_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -60,11 +61,10 @@ def test_compress_parity_with_oracle(which, rec, cfg1_frame, small_pbpb_frame, c
     _check(f, tracks, codes, rows, yz, oc, ores, opred, which)
 
 
-def test_compress_of_the_full_time_frame_equals_oracle(row_x):
+def test_compress_of_the_full_time_frame_equals_oracle(cfg3_frame, row_x):
     """The 2 ms Pb-Pb frame: the oracle compresses the GPU's own tracks."""
-    f = synth.config3_time_frame()
-    _, tracks, codes, rows, yz = _gpu(f, tuning=dict(bin_y=2.0, bin_z=4.0, cap_mul=4, block=512, tl_block=256,
-                                                     chunk=2), hit_rec=True)
+    f = cfg3_frame
+    _, tracks, codes, rows, yz = _gpu(f, tuning=CFG3_TUNING, hit_rec=True)
     oc, ores, opred = oracle.Oracle(row_x).compress_frame(f.y, f.z, f.row_off, tracks)
     _check(f, tracks, codes, rows, yz, oc, ores, opred, "cfg3")
 

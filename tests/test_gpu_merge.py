@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import CFG3_TUNING
 from paper_2009_07515_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -146,14 +147,13 @@ def test_merge_parity_with_oracle(which, rec, small_pbpb_frame, cfg2_frame, row_
     assert n_multi > 0
 
 
-def test_merge_of_the_full_time_frame_equals_oracle_merge_of_the_same_tracks(row_x):
+def test_merge_of_the_full_time_frame_equals_oracle_merge_of_the_same_tracks(cfg3_frame, row_x):
     """The 2 ms Pb-Pb frame (27M clusters) in the benchmark's configuration: the oracle
     merges the GPU's own sector tracks (its tracking of this frame takes minutes), and the
     GPU merge must equal that merge."""
     from paper_2009_07515_amd import tpcsf
-    f = synth.config3_time_frame()
-    trk = tpcsf.Tracker(synth.row_x(), tuning=dict(bin_y=2.0, bin_z=4.0, cap_mul=4, block=512, tl_block=256,
-                                                    chunk=2))
+    f = cfg3_frame
+    trk = tpcsf.Tracker(synth.row_x(), tuning=CFG3_TUNING)
     _, tracks, merged = _gpu_tracks_and_merge(f, trk=trk, hit_rec=True)
     o = oracle.Oracle(row_x)
     m = o.merge_frame(f.y, f.z, f.row_off, tracks)

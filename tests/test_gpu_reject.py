@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import CFG3_TUNING
 from paper_2009_07515_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -34,11 +35,11 @@ def test_reject_parity_with_oracle(which, cfg1_frame, small_pbpb_frame, cfg2_fra
     print(f"{which}: kept {k} of {f.n_clusters} ({k / max(f.n_clusters, 1):.3f})")
 
 
-def test_reject_of_the_full_time_frame_equals_oracle(row_x):
+def test_reject_of_the_full_time_frame_equals_oracle(cfg3_frame, row_x):
     """The 2 ms Pb-Pb frame in the benchmark's tuning: the oracle removes hits around the
     GPU's own sector tracks (its tracking of this frame takes minutes)."""
-    f = synth.config3_time_frame()
-    _, tracks, keep, k = _gpu(f, tuning=dict(bin_y=2.0, bin_z=4.0, cap_mul=4, block=512, tl_block=256, chunk=2))
+    f = cfg3_frame
+    _, tracks, keep, k = _gpu(f, tuning=CFG3_TUNING)
     ko, kk = oracle.Oracle(row_x).reject_frame(f.y, f.z, f.row_off, tracks)
     assert k == kk and np.array_equal(keep, ko)
     print(f"cfg3: kept {k} of {f.n_clusters} ({k / f.n_clusters:.3f})")

@@ -44,3 +44,16 @@ def test_create_rejects_bad_geometry_without_touching_the_gpu():
     rx2 = (ctypes.c_float * 3)(1.0, 2.0, 3.0)
     geo = tpcsf.Geometry(36, 3, ctypes.cast(rx2, ctypes.c_void_p), 0.5)
     assert lib.tpcsf_create(ctypes.byref(geo), None, ctypes.byref(bad_t), 0, ctypes.byref(h)) == tpcsf.E_INVALID
+
+
+def test_create_rejects_more_than_255_rows():
+    """A tracklet's cluster count fills the 8 high bits of its 32-bit selection weight, so a
+    geometry of 256 rows (a 256-cluster tracklet would wrap to 0) is refused before any HIP
+    call; 255 rows pass the geometry check."""
+    from paper_2009_07515_amd import tpcsf
+    lib = tpcsf.load()
+    h = ctypes.c_void_p()
+    rx = (ctypes.c_float * 256)(*[85.0 + i for i in range(256)])
+    geo = tpcsf.Geometry(36, 256, ctypes.cast(rx, ctypes.c_void_p), 0.5)
+    assert lib.tpcsf_create(ctypes.byref(geo), None, None, 0, ctypes.byref(h)) == tpcsf.E_INVALID
+    assert not h.value
