@@ -1,15 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of TPC sector track finding on one MI355X.
 
-Workload: one 2 ms continuous-readout Pb-Pb time frame (Poisson 50 kHz collisions,
-Exp(1500) primaries each, 10% secondaries, 5% noise, z shifted by the drift velocity
-times the collision time), all 36 sectors x 152 rows, generated with a fixed seed.  The
-paper's Run 3 time frames are not available; this synthetic frame has their shape.
+Workload (the headline `value`): one 2 ms continuous-readout Pb-Pb time frame (Poisson
+50 kHz collisions, Exp(1500) primaries each, 10% secondaries, 5% noise, z shifted by the
+drift velocity times the collision time), all 36 sectors x 152 rows, generated with a
+fixed seed.  The paper's Run 3 time frames are not available; this synthetic frame has
+their shape.
 
 A step is one batched tracking call over the whole time frame (every stage, every
 sector, one HIP graph replay) with the clusters already resident in HBM.  The plain form
-(every stage launched per sector) is timed beside it on the same input.  The reference
-oracle is timed on a bounded sample of the same frame on the host cores.
+(every stage launched per sector) is timed beside it on the same input.  Besides the
+step: the uneven batch of 64 time frames (pp-like and Pb-Pb-like) in one batched call,
+autotuned on itself; the serving run (frames of that mix arriving by a Poisson process at
+80% of the measured capacity for 60 s, admitted under a 64 GiB budget); the next stages
+(merge, hit removal, compression); and the reference oracle on the host cores.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -73,6 +77,21 @@ def stage_bytes(c):
     }
 
 
+def survey_bytes(c):
+    """The same stages under the byte model of the method's stage-boundary arrays written
+    once and read once in their minimal form (8-byte (y, z), 4-byte links, indices and
+    weights): K1 grid 8N read + 8N sorted + 4N perm + 4B; K2 links 8N + 4B read, 8N links;
+    K3 cleaning 16N; K4 starts 8N + 4S; K5 tracklets 12 per chain cluster + 8 per
+    follow-window cluster + 4 per tracklet cluster + 80 per tracklet; K6 selection 4 per
+    tracklet cluster + 8N weights + N flags; K7 final fit and emit 16 per accepted
+    cluster + 100 per track + 4N cluster map."""
+    N, B, S, K, Ht, Ha, T, C = (c[k] for k in ("N", "B", "S", "K", "Ht", "Ha", "T", "C"))
+    W = c["work"]["tl_window_clusters"]
+    return {"grid": 20 * N + 4 * B, "links": 16 * N + 4 * B, "clean": 16 * N, "starts": 8 * N + 4 * S,
+            "tracklets": 12 * C + 8 * W + 4 * Ht + 80 * K, "selection": 4 * Ht + 9 * N,
+            "fit_emit": 16 * Ha + 100 * T + 4 * N}
+
+
 def counts_from(trk, frame, res, nr):
     d = trk.debug(frame)
     nb = d["row_nb"].astype(np.int64)
@@ -91,6 +110,9 @@ def counts_from(trk, frame, res, nr):
 # covariance transport J C J^T; Kalman update with the 2x2 gain; chi2 of a cluster
 # inside a follow window; chi2 of a cluster in the final fit
 FLOPS_PROPAGATE, FLOPS_UPDATE, FLOPS_WINDOW, FLOPS_CHI2 = 182, 121, 12, 17
+# the coarser per-step model of the method's description (propagation ~120, update ~130,
+# window cluster ~20), reported beside it
+SURVEY_PROPAGATE, SURVEY_UPDATE, SURVEY_WINDOW = 120, 130, 20
 
 
 def stage_flops(c):
@@ -129,6 +151,43 @@ def profiled_traffic(kernel):
             rec[f[1]] = dict(zip(f[2::2], map(float, f[3::2])))
     r = rec.get("k_" + kernel)
     return None if r is None else r["fetch_bytes"] + r["write_bytes"]
+
+
+def cpu_model():
+    """CPU model name and the cores this process may run on (the machine's CPU share)."""
+    name = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                name = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return name, avail, os.cpu_count() or 1
+
+
+def cpu_threads(f, threads):
+    """The FP64 oracle on all 36 sectors of the frame, one sector per task on `threads`
+    host threads (the oracle's C calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    from paper_2009_07515_amd import synth
+    rx = synth.row_x()
+
+    def one(s):
+        a, b = int(f.row_off[s * 152]), int(f.row_off[(s + 1) * 152])
+        ro = f.row_off[s * 152:(s + 1) * 152 + 1] - a
+        return oracle.Oracle(rx, n_sectors=1).track_frame(f.y[a:b], f.z[a:b], ro)["n_tracks"]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        n_tracks = sum(ex.map(one, range(36)))
+    wall = time.perf_counter() - t0
+    return dict(value=f.n_clusters / wall, seconds=wall, tracks=int(n_tracks), threads=threads)
 
 
 def cpu_baseline(f, budget_s, max_sectors):
@@ -196,100 +255,224 @@ def cpu_next_stages(f):
     return out
 
 
-def serve(f_main, tuning, batched_rate, seconds, n_slots):
-    """Serving run over a pool of frames (this time frame and three frames of the uneven
-    pp / Pb-Pb mix).  The server's capacity is measured first with every slot kept busy;
-    then frames arrive by a Poisson process at 80% of that capacity and are admitted into
-    the library's server (n_slots slots, 64 GiB HBM budget).  Latency = arrival to tracks
-    downloaded to the host; an admission stall is an arrival that found no free slot."""
+def config4_sweep():
+    """Tuning points of the uneven batch: grid bins (at most 4n + 64 bins per row, so that
+    the layout reserved for the batch holds every point) crossed with launch shapes and
+    work-queue chunks."""
+    bins = [dict(bin_y=2.0, bin_z=2.0, cap_mul=2), dict(bin_y=2.0, bin_z=4.0, cap_mul=4),
+            dict(bin_y=4.0, bin_z=4.0, cap_mul=2), dict(bin_y=1000.0, bin_z=1.0, cap_mul=2)]
+    shapes = [dict(block=256, tl_block=256, chunk=1), dict(block=512, tl_block=256, chunk=2),
+              dict(block=512, tl_block=256, chunk=8), dict(block=256, tl_block=128, chunk=4)]
+    return [dict(b, **sh) for b in bins for sh in shapes]
+
+
+def bench_config4(frames, steps, plain_steps, autotune=True):
+    """The uneven batch of 64 time frames in one batched call (one launch per stage over
+    all 64 x 36 sectors, the tracklet stage from the persistent work queue, one graph),
+    autotuned on itself; beside it the plain per-sector form and the frames tracked one
+    call each (batched form per frame)."""
     import torch
     from paper_2009_07515_amd import synth, tpcsf
-    pool = [f_main]
-    for i in (0, 1, 2):
+    y, z, ro = synth.concat_frames(frames)
+    n, n_tf = int(y.shape[0]), len(frames)
+    sizes = np.array([f.n_clusters for f in frames])
+    sec = np.diff(ro[::152])
+    stream = torch.cuda.current_stream()
+    trk = tpcsf.Tracker(synth.row_x(), tuning=dict(bin_y=2.0, bin_z=4.0, cap_mul=4, block=512, tl_block=256,
+                                                   chunk=2))
+    trk.reserve(n, n_tf)
+    fr = tpcsf.DeviceFrame.from_numpy(y, z, ro, n_tf=n_tf, device="cuda:0")
+    out = tpcsf.TrackBuffers(n)
+    tune = None
+    if autotune:
         t0 = time.perf_counter()
-        pool.append(synth.config4_frame(i))
-        log(f"serving pool: frame {i} of the uneven mix, {pool[-1].n_clusters} clusters "
-            f"({time.perf_counter() - t0:.1f} s)")
+        best, tms, pts = trk.autotune(fr, points=config4_sweep(), reps=2, out=out)
+        tune = {"points": len(pts), "best": pts[best], "best_ms": tms[best], "worst_ms": max(tms),
+                "seconds": time.perf_counter() - t0}
+        log(f"config4 autotune: {len(pts)} points in {tune['seconds']:.1f} s, best {pts[best]} {tms[best]:.2f} ms "
+            f"(slowest {max(tms):.2f} ms)")
+    res = trk.track(fr, out=out, mode="batch")
+    T, H = res["n_tracks"], res["n_hits"]
+    for _ in range(2):
+        trk.launch(fr, out, "batch")
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        trk.launch(fr, out, "batch")
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    trk.sync()
+    assert int(out.n_tracks.item()) == T
+    per = np.array([a.elapsed_time(b) for a, b in ev])
+    log(f"config4 batched: {n} clusters in {n_tf} frames, {wall * 1e3:.2f} ms/step, {n / wall / 1e9:.3f} G clusters/s")
+    plain = None
+    if plain_steps > 0:
+        trk.track(fr, out=out, mode="plain")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(plain_steps):
+            trk.launch(fr, out, "plain")
+        torch.cuda.synchronize()
+        wp = (time.perf_counter() - t0) / plain_steps
+        trk.sync()
+        assert int(out.n_tracks.item()) == T
+        plain = {"ms_per_step": wp * 1e3, "clusters_per_s": n / wp, "steps": plain_steps}
+        log(f"config4 plain: {wp * 1e3:.1f} ms/step, {n / wp / 1e9:.3f} G clusters/s")
+    # the frames one call each (batched form per frame, inputs already on the device)
+    one = tpcsf.Tracker(synth.row_x(), tuning=trk.tuning.as_dict())
+    one.reserve(int(sizes.max()), 1)
+    t_one = 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    base = 0
+    for f in frames:
+        rof = torch.from_numpy(f.row_off).to("cuda:0")
+        fi = tpcsf.DeviceFrame(fr.y[base:base + f.n_clusters], fr.z[base:base + f.n_clusters], rof,
+                               np.ascontiguousarray(f.row_off), 1)
+        oi = tpcsf.TrackBuffers(f.n_clusters)
+        one.launch(fi, oi, "batch")          # captures this frame's graph
+        e0.record(stream)
+        one.launch(fi, oi, "batch")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_one += e0.elapsed_time(e1) * 1e-3
+        base += f.n_clusters
+    one.sync()
+    one.close()
+    log(f"config4 frames one call each: {t_one * 1e3:.1f} ms in total, {n / t_one / 1e9:.3f} G clusters/s")
+    tuning = trk.tuning.as_dict()
+    del out, fr
+    trk.close()
+    torch.cuda.empty_cache()
+    return {"workload": "64 time frames, even pp-like (0.5 ms at 500 kHz, Exp(30) tracks), odd Pb-Pb-like "
+                        "(0.5-2 ms at 50 kHz, Exp(1500) tracks), in one batched call",
+            "clusters": n, "time_frames": n_tf, "tracks": T, "assigned_clusters": H,
+            "frame_clusters": {"min": int(sizes.min()), "max": int(sizes.max()), "mean": float(sizes.mean())},
+            "sector_clusters": {"min": int(sec.min()), "max": int(sec.max())},
+            "value": n / wall, "unit": "clusters/s", "ms_per_step": wall * 1e3, "steps": steps,
+            "step_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+            "plain": plain, "frames_one_call_each": {"ms": t_one * 1e3, "clusters_per_s": n / t_one},
+            "autotune": tune, "tuning": tuning}
+
+
+def serve(frames, tuning, seconds, n_slots, cap_seconds, budget_gib=64):
+    """Serving run over the frames of the uneven mix.  The server (n_slots slots, a
+    64 GiB HBM budget) first runs closed-loop with every slot kept busy, which gives its
+    capacity; then frames arrive by a Poisson process at 80% of that capacity for
+    `seconds` and are admitted first come, first served.  One host thread submits, a
+    second one polls the admitted frames (polling drives the download of each finished
+    frame's tracks) and releases them.  Per frame: arrival, admission and completion
+    (tracks on the host) times.  An admission stall is an arrival that found no slot
+    free or no budget left and had to wait."""
+    import threading
+    import torch
+    from paper_2009_07515_amd import synth, tpcsf
 
     def pinned(a):
-        t = torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
-        return t.numpy()
+        return torch.from_numpy(np.ascontiguousarray(a)).pin_memory().numpy()
 
-    pool_h = [(pinned(p.y), pinned(p.z), pinned(p.row_off)) for p in pool]
-    sizes = np.array([p.n_clusters for p in pool], dtype=np.float64)
-    srv = tpcsf.Server(synth.row_x(), tuning=tuning, n_slots=n_slots, hbm_budget=64 << 30)
-    # warm every slot with the largest pool frame so that slot growth is not timed
-    for _ in range(n_slots):
-        tks = [srv.submit(*pool_h[int(np.argmax(sizes))]) for _ in range(n_slots)]
-        for t in tks:
-            if t is not None:
-                srv.wait(t)
-                srv.release(t)
+    t0 = time.perf_counter()
+    pool = [(pinned(f.y), pinned(f.z), pinned(f.row_off)) for f in frames]
+    sizes = np.array([f.n_clusters for f in frames], dtype=np.float64)
+    log(f"serving pool: {len(pool)} frames pinned in {time.perf_counter() - t0:.1f} s")
+    srv = tpcsf.Server(synth.row_x(), tuning=tuning, n_slots=n_slots, hbm_budget=budget_gib << 30)
+    # grow the slots before timing: the largest frames, as many at once as the budget admits
+    big = list(np.argsort(-sizes)[:n_slots])
+    tks = [t for t in (srv.submit(*pool[i]) for i in big) if t is not None]
+    for t in tks:
+        srv.wait(t)
+        srv.release(t)
+    log(f"serving: {len(tks)} slots grown, {srv.bytes_used() / 2**30:.1f} GiB of device memory")
+
+    lock = threading.Lock()
+    inflight = {}           # ticket -> record
+    done = []
+    stop = threading.Event()
+
+    def completer():
+        while not stop.is_set() or inflight:
+            with lock:
+                items = list(inflight.items())
+            for t, rec in items:
+                if srv.poll(t):
+                    rec["done"] = time.perf_counter()
+                    srv.release(t)
+                    with lock:
+                        del inflight[t]
+                        done.append(rec)
+            time.sleep(5e-5)
+
     rng = np.random.Generator(np.random.PCG64(1005))
 
     # capacity: closed loop, every slot kept busy with frames drawn from the pool
-    cap_s, done_cl, inflight = 3.0, 0, {}
+    th = threading.Thread(target=completer)
+    th.start()
     t_start = time.perf_counter()
-    while time.perf_counter() - t_start < cap_s or inflight:
-        if time.perf_counter() - t_start < cap_s:
-            while True:
-                w = int(rng.integers(0, len(pool)))
-                t = srv.submit(*pool_h[w])
-                if t is None:
-                    break
-                inflight[t] = w
-        for t in list(inflight):
-            if srv.poll(t):
-                done_cl += pool[inflight.pop(t)].n_clusters
-                srv.release(t)
-        time.sleep(0.0002)
-    capacity = done_cl / (time.perf_counter() - t_start)
-    log(f"serving capacity (closed loop, {n_slots} slots): {capacity / 1e9:.3f} G clusters/s")
+    while time.perf_counter() - t_start < cap_seconds:
+        w = int(rng.integers(0, len(pool)))
+        while True:
+            t = srv.submit(*pool[w])
+            if t is not None:
+                break
+            time.sleep(5e-5)
+        with lock:
+            inflight[t] = {"w": w, "admit": time.perf_counter()}
+    stop.set()
+    th.join()
+    cap_wall = time.perf_counter() - t_start
+    capacity = sum(sizes[r["w"]] for r in done) / cap_wall
+    log(f"serving capacity (closed loop, {n_slots} slots, {cap_wall:.1f} s, {len(done)} frames): "
+        f"{capacity / 1e9:.3f} G clusters/s")
 
-    # open loop: Poisson arrivals at 80% of that capacity
+    # open loop: Poisson arrivals at 80% of that capacity, first come first served
     lam = 0.8 * capacity / sizes.mean()
     arrivals = np.cumsum(rng.exponential(1.0 / lam, int(seconds * lam * 1.5) + 16))
     arrivals = arrivals[arrivals < seconds]
     which = rng.integers(0, len(pool), arrivals.shape[0])
-    lat, done_clusters, stalled, stall_time = [], 0, 0, 0.0
-    queue, inflight = [], {}
-    i_next = 0
+    done.clear()
+    stop.clear()
+    th = threading.Thread(target=completer)
+    th.start()
     t_start = time.perf_counter()
-    while i_next < arrivals.shape[0] or queue or inflight:
-        now = time.perf_counter() - t_start
-        while i_next < arrivals.shape[0] and arrivals[i_next] <= now:
-            queue.append((arrivals[i_next], int(which[i_next])))
-            i_next += 1
-        while queue:
-            ta, w = queue[0]
-            t = srv.submit(*pool_h[w])
-            if t is None:
+    for a, w in zip(arrivals, which):
+        ta = t_start + a
+        while time.perf_counter() < ta:
+            time.sleep(min(2e-4, max(0.0, ta - time.perf_counter())))
+        while True:
+            t = srv.submit(*pool[int(w)])
+            if t is not None:
                 break
-            waited = (time.perf_counter() - t_start) - ta
-            if waited > 1e-3:           # had to wait for a slot: an admission stall
-                stalled += 1
-                stall_time += waited
-            inflight[t] = (ta, w)
-            queue.pop(0)
-        for t in list(inflight):
-            if srv.poll(t):
-                ta, w = inflight.pop(t)
-                lat.append((time.perf_counter() - t_start) - ta)
-                done_clusters += pool[w].n_clusters
-                srv.release(t)
-        time.sleep(0.0002)
+            time.sleep(5e-5)
+        with lock:
+            inflight[t] = {"w": int(w), "arrive": ta, "admit": time.perf_counter()}
+    stop.set()
+    th.join()
     wall = time.perf_counter() - t_start
-    lat = np.array(lat) * 1e3
-    res = {"seconds": wall, "frames": int(lat.shape[0]), "arrival_rate_hz": lam, "slots": n_slots,
-           "hbm_budget_gib": 64, "capacity_clusters_per_s": capacity,
-           "clusters_per_s_incl_pcie": done_clusters / wall,
-           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                          "max": float(lat.max())},
-           "admission_stalls": stalled, "admission_wait_s": stall_time,
-           "pool_clusters": [int(v) for v in sizes], "device_bytes": srv.bytes_used()}
-    log(f"serving: {res['frames']} frames in {wall:.1f} s, p50 {res['latency_ms']['p50']:.1f} ms, "
-        f"p99 {res['latency_ms']['p99']:.1f} ms, {stalled} stalled admissions")
+    srv_bytes = srv.bytes_used()
     srv.close()
+    arr = np.array([r["arrive"] for r in done])
+    adm = np.array([r["admit"] for r in done])
+    fin = np.array([r["done"] for r in done])
+    cl = np.array([sizes[r["w"]] for r in done])
+    lat, wait, svc = (fin - arr) * 1e3, (adm - arr) * 1e3, (fin - adm) * 1e3
+    stalled = int((wait > 0.1).sum())
+
+    def pct(v):
+        return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99)), "max": float(v.max())}
+
+    res = {"seconds": wall, "frames": int(len(done)), "arrival_rate_hz": lam, "load": 0.8, "slots": n_slots,
+           "hbm_budget_gib": budget_gib, "device_bytes": srv_bytes,
+           "capacity_clusters_per_s": capacity, "capacity_window_s": cap_wall,
+           "clusters_per_s_incl_pcie": float(cl.sum()) / wall,
+           "latency_ms": pct(lat), "admission_wait_ms": pct(wait), "service_ms": pct(svc),
+           "admission_stalls": stalled, "admission_wait_s": float(wait.sum() * 1e-3),
+           "pool": {"frames": len(pool), "clusters_min": int(sizes.min()), "clusters_max": int(sizes.max()),
+                    "clusters_mean": float(sizes.mean())}}
+    log(f"serving: {res['frames']} frames in {wall:.1f} s, latency p50 {res['latency_ms']['p50']:.1f} ms, p99 "
+        f"{res['latency_ms']['p99']:.1f} ms, {stalled} admissions waited (p99 "
+        f"{res['admission_wait_ms']['p99']:.1f} ms), service p50 {res['service_ms']['p50']:.1f} ms")
     return res
 
 
@@ -305,9 +488,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", type=str, default="", help="JSON dict of tuning overrides")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving run (Poisson arrivals at 80%% of capacity); 0 skips it")
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=6)
+    ap.add_argument("--serve-cap-seconds", type=float, default=10.0,
+                    help="length of the closed-loop capacity measurement before the serving run")
+    ap.add_argument("--config4-steps", type=int, default=5,
+                    help="timed batched calls of the 64-frame uneven batch (0 skips it)")
+    ap.add_argument("--config4-frames", type=int, default=64)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the multi-core oracle run (0: the cores available, at most 16)")
     ap.add_argument("--compress-steps", type=int, default=20,
                     help="timed calls of the track-model compression (0: skip)")
     ap.add_argument("--reject-steps", type=int, default=20,
@@ -336,6 +526,13 @@ def main():
     f = synth.config3_time_frame(length_us=args.tf_us)
     N = f.n_clusters
     log(f"{N} clusters, {f.n_events} collisions, generated in {time.perf_counter() - t0:.1f} s")
+    frames4 = None
+    if args.config4_steps > 0 or args.serve_seconds > 0:
+        # before the GPU is touched: worker processes generate the uneven batch
+        t0 = time.perf_counter()
+        frames4 = synth.config4_batch(args.config4_frames)
+        log(f"uneven batch: {len(frames4)} frames, {sum(x.n_clusters for x in frames4)} clusters, generated in "
+            f"{time.perf_counter() - t0:.1f} s")
 
     torch.cuda.set_device(0)
     frame = tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off, device="cuda:0")
@@ -444,6 +641,12 @@ def main():
             main_pt.update({"plain_ms": plain["ms_per_step"], "plain_clusters_per_s": plain["value"]})
         size_curve.append(main_pt)
 
+    # the uneven batch of 64 time frames in one call, autotuned on itself
+    config4 = None
+    if args.config4_steps > 0:
+        config4 = bench_config4(frames4, args.config4_steps, min(1, args.plain_steps),
+                                autotune=not args.no_autotune)
+
     # calibration copy for hardware byte counters: one device copy of a known size
     if args.calib_copy_mib > 0:
         n_el = args.calib_copy_mib * (1 << 20) // 4
@@ -486,6 +689,11 @@ def main():
                     "algorithmic_bytes_per_launch": sb[dom], "launch_ms": stages[dom]}
     kalman = {k: {"TFLOPs": sf[k] / (stages[k] * 1e-3) / 1e12, "frac_fp64_peak": sf[k] / (stages[k] * 1e-3) / 1e12
                   / FP64_PEAK_TFS} for k in sf}
+    w = cnt["work"]
+    sv = (SURVEY_PROPAGATE * w["tl_propagations"] + SURVEY_UPDATE * w["tl_updates"]
+          + SURVEY_WINDOW * w["tl_window_clusters"])
+    kalman["tracklets"]["coarse_model"] = {"flops_per_launch": sv,
+                                           "frac_fp64_peak": sv / (stages["tracklets"] * 1e-3) / 1e12 / FP64_PEAK_TFS}
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
     trk.set_stage_timing(False)
 
@@ -623,8 +831,9 @@ def main():
                    "clusters": N, "collisions": f.n_events, "tracks": T0, "batch_time_frames": 1,
                    "tuning": trk.tuning.as_dict()},
         "plain": plain,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "max": float(lat.max())},
+        # per-step event times of the back-to-back graph replays (device-resident frame)
+        "graph_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                     "max": float(lat.max())},
         "stages_ms": stages,
         "counts": cnt,
         "roofline": roofline,
@@ -635,14 +844,35 @@ def main():
         "size_curve": size_curve,
         "path_hbm": {"bytes_per_cluster": path_bytes / N,
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
-                     "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "coarse_model": {"bytes_per_cluster": sum(survey_bytes(cnt).values()) / N,
+                                      "achieved_GBs": sum(survey_bytes(cnt).values()) / (ms * 1e-3) / 1e9,
+                                      "frac": sum(survey_bytes(cnt).values()) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "io_floor_bytes_per_cluster": 16},
+        "config4": config4,
     }
     line["autotune"] = tune
+    # time-frame latency: arrival to tracks on the host, from the serving run
+    line["latency_ms"] = None
     if args.serve_seconds > 0:
-        line["serving"] = serve(f, trk.tuning.as_dict(), value, args.serve_seconds, args.serve_slots)
+        del out, frame
+        trk.close()
+        torch.cuda.empty_cache()
+        line["serving"] = serve(frames4, line["config"]["tuning"], args.serve_seconds, args.serve_slots,
+                                args.serve_cap_seconds)
+        line["latency_ms"] = line["serving"]["latency_ms"]
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(f, args.cpu_budget, args.cpu_sectors)
-        line["cpu_baseline"]["next_stages"] = cpu_next_stages(f)
+        name, avail, total = cpu_model()
+        threads = args.cpu_threads or min(16, avail)
+        single = cpu_baseline(f, args.cpu_budget, args.cpu_sectors)
+        multi = cpu_threads(f, threads)
+        log(f"oracle on {threads} threads: all 36 sectors in {multi['seconds']:.1f} s, "
+            f"{multi['value'] / 1e6:.2f} M clusters/s")
+        line["cpu_baseline"] = {"value": multi["value"], "unit": "clusters/s", "cores": threads, "kind": "oracle",
+                                "sample": f"FP64 oracle on the whole time frame ({N} clusters, 36 sectors, one "
+                                          f"sector per task on {threads} threads, {multi['seconds']:.1f} s)",
+                                "cpu": name, "cores_available": avail, "cores_host": total,
+                                "single_thread": single, "next_stages": cpu_next_stages(f)}
     print(json.dumps(line), flush=True)
 
 

@@ -368,8 +368,11 @@ const char* tpcsf_last_error(const tpcsf_ctx* ctx);
  * own device and pinned host buffers, sized on first use and grown on demand; the device
  * bytes of all slots stay within hbm_budget_bytes (0 = no bound).  tpcsf_server_submit()
  * admits a frame into a free slot at once, or returns TPCSF_E_BUSY (an admission stall)
- * when no free slot can hold it within the budget.  Upload, tracking and download run
- * asynchronously on the slot's stream, so admitted frames overlap on the device.  Each
+ * when no free slot can hold it within the budget.  Upload, tracking and the download of
+ * the frame's track and hit counts run asynchronously on the slot's stream, so admitted
+ * frames overlap on the device; the first tpcsf_server_poll()/tpcsf_server_wait() of the
+ * frame after its counts arrived enqueues the download of exactly that many tracks and
+ * hits (so a frame's completion needs its ticket to be polled or waited on).  Each
  * frame's result is the same as tpcsf_track_batch() on that frame alone.  All server
  * calls are thread-safe.
  * ------------------------------------------------------------------------------------- */

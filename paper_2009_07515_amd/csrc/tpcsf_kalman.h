@@ -15,6 +15,10 @@ struct Trk {
     double c[15];
 };
 
+// asin out of line: the rare long steps need it, and inlined, its registers would count
+// against every kernel that propagates
+__device__ __attribute__((noinline)) double asin_outline(double h) { return asin(h); }
+
 // asin(h)/h and its derivative; Taylor series near 0
 __device__ __forceinline__ void arc_factor(double h, double& A, double& Ap)
 {
@@ -23,7 +27,7 @@ __device__ __forceinline__ void arc_factor(double h, double& A, double& Ap)
         A = 1.0 + h2 * (1.0 / 6.0 + h2 * (3.0 / 40.0 + h2 * (5.0 / 112.0)));
         Ap = h * (1.0 / 3.0 + h2 * (3.0 / 10.0 + h2 * (15.0 / 56.0 + h2 * (35.0 / 144.0))));
     } else {
-        const double as = asin(h);
+        const double as = asin_outline(h);
         const double ih = 1.0 / h;
         A = as * ih;
         Ap = (h / sqrt((1.0 - h) * (1.0 + h)) - as) * ih * ih;
@@ -68,38 +72,43 @@ static __device__ bool trk_propagate(Trk& t, double x1, const DevParams& P)
     t.p[2] = s1;
     t.x = x1;
 
-    // C <- J C J^T with J = identity + {j02, j04, j12, j13, j14, j24}
+    // C <- J C J^T with J = identity + {j02, j04, j12, j13, j14, j24}, one column of the
+    // result at a time: column j of C' (rows >= j) is J applied to v_j = C J_j^T, and v_j
+    // needs only entries of C that the earlier columns did not overwrite.
     double* c = t.c;
-    const double c00 = c[0], c10 = c[1], c11 = c[2], c20 = c[3], c21 = c[4], c22 = c[5];
-    const double c30 = c[6], c31 = c[7], c32 = c[8], c33 = c[9];
-    const double c40 = c[10], c41 = c[11], c42 = c[12], c43 = c[13], c44 = c[14];
-    // rows of A = J C (A_ij for all i, j)
-    const double a00 = c00 + j02 * c20 + j04 * c40, a01 = c10 + j02 * c21 + j04 * c41;
-    const double a02 = c20 + j02 * c22 + j04 * c42, a03 = c30 + j02 * c32 + j04 * c43;
-    const double a04 = c40 + j02 * c42 + j04 * c44;
-    const double a10 = c10 + j12 * c20 + j13 * c30 + j14 * c40;
-    const double a11 = c11 + j12 * c21 + j13 * c31 + j14 * c41;
-    const double a12 = c21 + j12 * c22 + j13 * c32 + j14 * c42;
-    const double a13 = c31 + j12 * c32 + j13 * c33 + j14 * c43;
-    const double a14 = c41 + j12 * c42 + j13 * c43 + j14 * c44;
-    const double a20 = c20 + j24 * c40, a21 = c21 + j24 * c41, a22 = c22 + j24 * c42;
-    const double a23 = c32 + j24 * c43, a24 = c42 + j24 * c44;
-    // C' = A J^T (lower triangle); rows 3 and 4 of A equal those of C
-    c[0] = a00 + j02 * a02 + j04 * a04;
-    c[1] = a10 + j02 * a12 + j04 * a14;
-    c[2] = a11 + j12 * a12 + j13 * a13 + j14 * a14;
-    c[3] = a20 + j02 * a22 + j04 * a24;
-    c[4] = a21 + j12 * a22 + j13 * a23 + j14 * a24;
-    c[5] = a22 + j24 * a24;
-    c[6] = c30 + j02 * c32 + j04 * c43;
-    c[7] = c31 + j12 * c32 + j13 * c33 + j14 * c43;
-    c[8] = c32 + j24 * c43;
-    c[9] = c33;
-    c[10] = c40 + j02 * c42 + j04 * c44;
-    c[11] = c41 + j12 * c42 + j13 * c43 + j14 * c44;
-    c[12] = c42 + j24 * c44;
-    c[13] = c43;
-    c[14] = c44;
+    // column 0: v0 = C (e0 + j02 e2 + j04 e4)
+    {
+        const double v0 = c[0] + j02 * c[3] + j04 * c[10];
+        const double v1 = c[1] + j02 * c[4] + j04 * c[11];
+        const double v2 = c[3] + j02 * c[5] + j04 * c[12];
+        const double v3 = c[6] + j02 * c[8] + j04 * c[13];
+        const double v4 = c[10] + j02 * c[12] + j04 * c[14];
+        c[0] = v0 + j02 * v2 + j04 * v4;
+        c[1] = v1 + j12 * v2 + j13 * v3 + j14 * v4;
+        c[3] = v2 + j24 * v4;
+        c[6] = v3;
+        c[10] = v4;
+    }
+    // column 1 (rows 1..4): v1 = C (e1 + j12 e2 + j13 e3 + j14 e4)
+    {
+        const double v1 = c[2] + j12 * c[4] + j13 * c[7] + j14 * c[11];
+        const double v2 = c[4] + j12 * c[5] + j13 * c[8] + j14 * c[12];
+        const double v3 = c[7] + j12 * c[8] + j13 * c[9] + j14 * c[13];
+        const double v4 = c[11] + j12 * c[12] + j13 * c[13] + j14 * c[14];
+        c[2] = v1 + j12 * v2 + j13 * v3 + j14 * v4;
+        c[4] = v2 + j24 * v4;
+        c[7] = v3;
+        c[11] = v4;
+    }
+    // column 2 (rows 2..4): v2 = C (e2 + j24 e4); columns 3 and 4 are unchanged
+    {
+        const double v2 = c[5] + j24 * c[12];
+        const double v3 = c[8] + j24 * c[13];
+        const double v4 = c[12] + j24 * c[14];
+        c[5] = v2 + j24 * v4;
+        c[8] = v3;
+        c[12] = v4;
+    }
     return true;
 }
 
@@ -137,7 +146,10 @@ __device__ __forceinline__ double trk_chi2(const Trk& t, double my, double mz, c
     return (r0 * r0 * s11 - 2.0 * r0 * r1 * s01 + r1 * r1 * s00) / (s00 * s11 - s01 * s01);
 }
 
-// Kalman update with the cluster (my, mz), R = diag(sy2, sz2).
+// Kalman update with the cluster (my, mz), R = diag(sy2, sz2).  The gain rows
+// K_i = (C_i0, C_i1) S^-1 and the covariance rows C_ij -= K_i (C_j0, C_j1)^T are taken
+// from the last row to the first: row i reads columns 0 and 1 of rows j <= i only, which
+// the rows after it have not changed yet.
 static __device__ void trk_update(Trk& t, double my, double mz, const DevParams& P)
 {
     const double r0 = my - t.p[0], r1 = mz - t.p[1];
@@ -145,20 +157,22 @@ static __device__ void trk_update(Trk& t, double my, double mz, const DevParams&
     const double s00 = c[0] + P.sy2, s01 = c[1], s11 = c[2] + P.sz2;
     const double idet = 1.0 / (s00 * s11 - s01 * s01);
     const double i00 = s11 * idet, i01 = -s01 * idet, i11 = s00 * idet;
-    const double h0[5] = {c[0], c[1], c[3], c[6], c[10]};
-    const double h1[5] = {c[1], c[2], c[4], c[7], c[11]};
-    double k0[5], k1[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        k0[i] = h0[i] * i00 + h1[i] * i01;
-        k1[i] = h0[i] * i01 + h1[i] * i11;
-        t.p[i] += k0[i] * r0 + k1[i] * r1;
+    for (int i = 4; i >= 0; --i) {
+        const int ri = i * (i + 1) / 2;
+        // C_i0, C_i1; row 1 has already replaced the shared entry C_10 = C_01 when row 0
+        // comes, so row 0 takes it from s01
+        const double a0 = c[ri], a1 = i == 0 ? s01 : c[ri + 1];
+        const double k0 = a0 * i00 + a1 * i01;
+        const double k1 = a0 * i01 + a1 * i11;
+        t.p[i] += k0 * r0 + k1 * r1;
+#pragma unroll
+        for (int j = i; j >= 0; --j) {
+            const double b0 = j == i ? a0 : c[j * (j + 1) / 2];
+            const double b1 = j == i ? a1 : c[j == 0 ? 1 : j * (j + 1) / 2 + 1];
+            c[ri + j] -= k0 * b0 + k1 * b1;
+        }
     }
-    int k = 0;
-#pragma unroll
-    for (int i = 0; i < 5; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j, ++k) c[k] -= k0[i] * h0[j] + k1[i] * h1[j];
 }
 
 __device__ __forceinline__ void trk_reset_cov(Trk& t, const DevParams& P)

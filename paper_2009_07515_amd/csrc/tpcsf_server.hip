@@ -6,9 +6,11 @@
 // stream, device input/output buffers and pinned host output buffers, all sized on first
 // use and grown on demand, and a scratch layout reserved to that size so that one HIP
 // graph serves every frame the slot takes.  A frame is admitted into any free slot whose
-// growth stays inside the HBM budget; its upload, tracking and download are enqueued on
-// the slot's stream, so frames in different slots overlap on the device.  Admission never
-// waits: without a slot or budget it returns TPCSF_E_BUSY (an admission stall).
+// growth stays inside the HBM budget; its upload, tracking and the download of its track
+// and hit counts are enqueued on the slot's stream, so frames in different slots overlap
+// on the device.  Once those counts are on the host, the next poll (or wait) of the frame
+// enqueues the download of exactly that many tracks and hits.  Admission never waits:
+// without a slot or budget it returns TPCSF_E_BUSY (an admission stall).
 #include "tpcsf.h"
 
 #include <hip/hip_runtime.h>
@@ -27,7 +29,8 @@ enum SlotState { kFree = 0, kBusy = 1 };
 struct Slot {
     tpcsf_ctx* ctx = nullptr;
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    hipEvent_t tracked = nullptr;      // tracking done, counts on the host
+    hipEvent_t done = nullptr;         // outputs on the host
     int64_t cap = 0;                   // clusters the buffers hold
     size_t bytes = 0;                  // device bytes held (buffers + scratch)
     // device inputs
@@ -49,6 +52,7 @@ struct Slot {
     uint64_t ticket = 0;
     int64_t n = 0;
     tpcsf_status status = TPCSF_OK;
+    bool downloading = false;          // the output downloads are enqueued
     bool finished = false;
 };
 
@@ -189,6 +193,7 @@ tpcsf_status tpcsf_server_create(const tpcsf_geometry* geo, const tpcsf_params* 
     s->slots.resize(n_slots);
     for (Slot& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.tracked, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
             (void)tpcsf_server_destroy(s);
             return TPCSF_E_HIP;
@@ -206,6 +211,7 @@ tpcsf_status tpcsf_server_destroy(tpcsf_server* s)
         free_slot_buffers(sl);
         if (sl.ctx) (void)tpcsf_destroy(sl.ctx);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.tracked) (void)hipEventDestroy(sl.tracked);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     delete s;
@@ -262,24 +268,12 @@ tpcsf_status tpcsf_server_submit(tpcsf_server* s, const float* y, const float* z
     if (e != hipSuccess) return srv_fail(s, TPCSF_E_HIP, std::string("upload: ") + hipGetErrorString(e));
     tpcsf_status ts = tpcsf_track_batch(sl.ctx, &f, &o, st_);
     if (ts != TPCSF_OK) return srv_fail(s, ts, tpcsf_last_error(sl.ctx));
-    // download everything that may be valid; counts decide what the caller reads
+    // the counts now; the outputs once the counts are known (advance)
     chk(hipMemcpyAsync(sl.h_n, sl.d_n, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_par, sl.d_par, sizeof(double) * 5 * T, hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_cov, sl.d_cov, sizeof(double) * 15 * T, hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_x, sl.d_x, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_chi2, sl.d_chi2, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_zb, sl.d_zb, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_ndf, sl.d_ndf, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_nh, sl.d_nh, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_sec, sl.d_sec, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
-    chk(hipMemcpyAsync(sl.h_hoff, sl.d_hoff, sizeof(int64_t) * (T + 1), hipMemcpyDeviceToHost, st_));
-    if (n_clusters > 0) {
-        chk(hipMemcpyAsync(sl.h_hid, sl.d_hid, sizeof(int32_t) * n_clusters, hipMemcpyDeviceToHost, st_));
-        chk(hipMemcpyAsync(sl.h_ct, sl.d_ct, sizeof(int32_t) * n_clusters, hipMemcpyDeviceToHost, st_));
-    }
-    chk(hipEventRecord(sl.done, st_));
+    chk(hipEventRecord(sl.tracked, st_));
     if (e != hipSuccess) return srv_fail(s, TPCSF_E_HIP, std::string("download: ") + hipGetErrorString(e));
     sl.state = kBusy;
+    sl.downloading = false;
     sl.finished = false;
     sl.status = TPCSF_OK;
     sl.n = n_clusters;
@@ -295,20 +289,59 @@ static Slot* find_ticket(tpcsf_server* s, uint64_t ticket)
     return nullptr;
 }
 
+// Moves a busy slot on (caller holds the lock): once the tracking and the counts are done,
+// the download of exactly the frame's tracks and hits is enqueued; once that is done, the
+// frame is finished.
+static tpcsf_status advance(tpcsf_server* s, Slot& sl)
+{
+    if (sl.finished) return TPCSF_OK;
+    if (!sl.downloading) {
+        const hipError_t e = hipEventQuery(sl.tracked);
+        if (e == hipErrorNotReady) return TPCSF_OK;
+        if (e != hipSuccess) return srv_fail(s, TPCSF_E_HIP, hipGetErrorString(e));
+        sl.status = tpcsf_sync(sl.ctx, sl.stream);
+        const int64_t capT = cap_tracks_for(sl.cap, s->params.min_track_hits);
+        const int64_t T = sl.h_n[0] < capT ? sl.h_n[0] : capT;
+        const int64_t H = sl.h_n[1] < sl.cap ? sl.h_n[1] : sl.cap;
+        hipStream_t st_ = sl.stream;
+        hipError_t x = hipSuccess;
+        auto chk = [&](hipError_t y) { if (x == hipSuccess) x = y; };
+        if (sl.status == TPCSF_OK && T > 0) {
+            chk(hipMemcpyAsync(sl.h_par, sl.d_par, sizeof(double) * 5 * T, hipMemcpyDeviceToHost, st_));
+            chk(hipMemcpyAsync(sl.h_cov, sl.d_cov, sizeof(double) * 15 * T, hipMemcpyDeviceToHost, st_));
+            chk(hipMemcpyAsync(sl.h_x, sl.d_x, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
+            chk(hipMemcpyAsync(sl.h_chi2, sl.d_chi2, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
+            chk(hipMemcpyAsync(sl.h_zb, sl.d_zb, sizeof(double) * T, hipMemcpyDeviceToHost, st_));
+            chk(hipMemcpyAsync(sl.h_ndf, sl.d_ndf, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
+            chk(hipMemcpyAsync(sl.h_nh, sl.d_nh, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
+            chk(hipMemcpyAsync(sl.h_sec, sl.d_sec, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st_));
+        }
+        if (sl.status == TPCSF_OK)
+            chk(hipMemcpyAsync(sl.h_hoff, sl.d_hoff, sizeof(int64_t) * (T + 1), hipMemcpyDeviceToHost, st_));
+        if (sl.status == TPCSF_OK && H > 0)
+            chk(hipMemcpyAsync(sl.h_hid, sl.d_hid, sizeof(int32_t) * H, hipMemcpyDeviceToHost, st_));
+        if (sl.status == TPCSF_OK && sl.n > 0)
+            chk(hipMemcpyAsync(sl.h_ct, sl.d_ct, sizeof(int32_t) * sl.n, hipMemcpyDeviceToHost, st_));
+        chk(hipEventRecord(sl.done, st_));
+        if (x != hipSuccess) return srv_fail(s, TPCSF_E_HIP, std::string("download: ") + hipGetErrorString(x));
+        sl.downloading = true;
+    }
+    const hipError_t e = hipEventQuery(sl.done);
+    if (e == hipErrorNotReady) return TPCSF_OK;
+    if (e != hipSuccess) return srv_fail(s, TPCSF_E_HIP, hipGetErrorString(e));
+    sl.finished = true;
+    return TPCSF_OK;
+}
+
 tpcsf_status tpcsf_server_poll(tpcsf_server* s, uint64_t ticket, int32_t* done)
 {
     if (!s || !done) return TPCSF_E_INVALID;
     std::lock_guard<std::mutex> lock(s->mu);
     Slot* sl = find_ticket(s, ticket);
     if (!sl) return srv_fail(s, TPCSF_E_INVALID, "unknown ticket");
-    const hipError_t e = hipEventQuery(sl->done);
-    if (e == hipErrorNotReady) { *done = 0; return TPCSF_OK; }
-    if (e != hipSuccess) return srv_fail(s, TPCSF_E_HIP, hipGetErrorString(e));
-    if (!sl->finished) {
-        sl->status = tpcsf_sync(sl->ctx, sl->stream);
-        sl->finished = true;
-    }
-    *done = 1;
+    const tpcsf_status st = advance(s, *sl);
+    if (st != TPCSF_OK) return st;
+    *done = sl->finished ? 1 : 0;
     return TPCSF_OK;
 }
 

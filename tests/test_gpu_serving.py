@@ -94,3 +94,63 @@ def test_server_budget_too_small_stalls():
     srv = tpcsf.Server(synth.row_x(), n_slots=2, hbm_budget=1 << 16)
     assert srv.submit(f.y, f.z, f.row_off) is None
     assert srv.bytes_used() == 0
+
+
+def test_served_frames_match_the_oracle(small_pbpb_frame, cfg1_frame, row_x):
+    """Frames served in a mix (two slots, three frames in flight) against the FP64 oracle:
+    the same tracks and hit lists, parameters within 1e-4 relative (floors 10 cm, 10 cm,
+    0.1, 0.1, 0.1 c/GeV)."""
+    import oracle
+    from paper_2009_07515_amd import tpcsf
+    fs = [small_pbpb_frame, cfg1_frame, small_pbpb_frame]
+    srv = tpcsf.Server(row_x, n_slots=2)
+    got, pending, inflight = {}, list(range(len(fs))), {}
+    t_end = time.time() + 60
+    while (pending or inflight) and time.time() < t_end:
+        while pending:
+            f = fs[pending[0]]
+            t = srv.submit(f.y, f.z, f.row_off)
+            if t is None:
+                break
+            inflight[t] = pending.pop(0)
+        for t in list(inflight):
+            if srv.wait(t, timeout_s=0.001):
+                got[inflight.pop(t)] = srv.result(t)
+    assert len(got) == len(fs)
+    floors = np.array([10.0, 10.0, 0.1, 0.1, 0.1])
+    for i, f in enumerate(fs):
+        ref = oracle.Oracle(row_x).track_frame(f.y, f.z, f.row_off)
+        g = got[i]
+        assert g["n_tracks"] == ref["n_tracks"]
+        assert np.array_equal(g["hit_off"], ref["hit_off"])
+        assert np.array_equal(g["hit_ids"].astype(np.int64), ref["hit_ids"])
+        assert np.array_equal(g["cluster_track"], ref["cluster_track"])
+        err = np.abs(g["params"] - ref["params"]) / np.maximum(np.abs(ref["params"]), floors)
+        assert np.all(err <= 1e-4), err.max(axis=0)
+        assert np.all(np.abs(g["z_beam"] - ref["z_beam"]) <= 1e-4 * np.maximum(np.abs(ref["z_beam"]), 10.0))
+
+
+def test_server_wait_times_out_and_the_server_keeps_serving(cfg2_frame, cfg1_frame):
+    """A wait whose time limit ends before the frame is done returns TPCSF_E_TIMEOUT (the
+    limit is forced from the host: zero, right after admitting 1.3M clusters, whose
+    upload and tracking take milliseconds); the frame still completes, its result is the
+    one of the frame alone, and the server admits and serves the next frame."""
+    from paper_2009_07515_amd import tpcsf
+    trk = tpcsf.Tracker(synth.row_x())
+    alone = [_np(trk.track(tpcsf.DeviceFrame.from_numpy(f.y, f.z, f.row_off))) for f in (cfg2_frame, cfg1_frame)]
+    srv = tpcsf.Server(synth.row_x(), n_slots=1)
+    f = cfg2_frame
+    t = srv.submit(f.y, f.z, f.row_off)
+    assert t is not None
+    st = srv.lib.tpcsf_server_wait(srv.h, t, 0)
+    assert st == tpcsf.E_TIMEOUT
+    assert srv.submit(cfg1_frame.y, cfg1_frame.z, cfg1_frame.row_off) is None   # the one slot is busy
+    assert srv.wait(t, timeout_s=-1)
+    got = srv.result(t)
+    for k in KEYS:
+        assert np.array_equal(np.asarray(alone[0][k]), np.asarray(got[k])), k
+    t2 = srv.submit(cfg1_frame.y, cfg1_frame.z, cfg1_frame.row_off)
+    assert t2 is not None and srv.wait(t2, timeout_s=30)
+    got2 = srv.result(t2)
+    for k in KEYS:
+        assert np.array_equal(np.asarray(alone[1][k]), np.asarray(got2[k])), k
