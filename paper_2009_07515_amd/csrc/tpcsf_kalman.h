@@ -15,6 +15,36 @@ struct Trk {
     double c[15];
 };
 
+// 1/x, 1/sqrt(x) and sqrt(x) of positive, normal binary64 values: the hardware estimate
+// (relative error below 2^-22) refined by two Newton steps, within about an ulp.  The
+// correctly rounded library forms take about twice the instructions; the filter needs
+// neither their last ulp nor their handling of zero, infinity and denormals.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double y = rsqrt_nr(x);
+    const double s = x * y;
+    return fma(fma(-s, s, x), 0.5 * y, s);
+}
+
 // asin out of line: the rare long steps need it, and inlined, its registers would count
 // against every kernel that propagates
 __device__ __attribute__((noinline)) double asin_outline(double h) { return asin(h); }
@@ -47,12 +77,12 @@ static __device__ bool trk_propagate(Trk& t, double x1, const DevParams& P)
     if (!(fabs(s0) < P.sinphi_max) || !(fabs(s1) < P.sinphi_max)) return false;
     // cos(phi) at both ends and their reciprocals from one reciprocal square root each
     const double u0 = (1.0 - s0) * (1.0 + s0), u1 = (1.0 - s1) * (1.0 + s1);
-    const double ic0 = rsqrt(u0), ic1 = rsqrt(u1);
+    const double ic0 = rsqrt_nr(u0), ic1 = rsqrt_nr(u1);
     const double c0 = u0 * ic0, c1 = u1 * ic1;
-    const double ics = 1.0 / (c0 + c1);
+    const double ics = rcp_nr(c0 + c1);
     const double tb = (s0 + s1) * ics;
     const double sec2 = 1.0 + tb * tb;
-    const double sec = sqrt(sec2);
+    const double sec = sqrt_nr(sec2);
     const double chord = dx * sec;
     const double h = 0.5 * kap * chord;
     if (!(fabs(h) < 1.0)) return false;
@@ -123,12 +153,12 @@ __device__ __forceinline__ bool trk_predict(const double* p, double x0, double x
     const double s1 = s0 + kap * dx;
     if (!(fabs(s0) < P.sinphi_max) || !(fabs(s1) < P.sinphi_max)) return false;
     const double u0 = (1.0 - s0) * (1.0 + s0), u1 = (1.0 - s1) * (1.0 + s1);
-    const double ic0 = rsqrt(u0), ic1 = rsqrt(u1);
+    const double ic0 = rsqrt_nr(u0), ic1 = rsqrt_nr(u1);
     const double c0 = u0 * ic0, c1 = u1 * ic1;
-    const double ics = 1.0 / (c0 + c1);
+    const double ics = rcp_nr(c0 + c1);
     const double tb = (s0 + s1) * ics;
     const double sec2 = 1.0 + tb * tb;
-    const double sec = sqrt(sec2);
+    const double sec = sqrt_nr(sec2);
     const double chord = dx * sec;
     const double h = 0.5 * kap * chord;
     if (!(fabs(h) < 1.0)) return false;
@@ -139,24 +169,18 @@ __device__ __forceinline__ bool trk_predict(const double* p, double x0, double x
     return true;
 }
 
-__device__ __forceinline__ double trk_chi2(const Trk& t, double my, double mz, const DevParams& P)
-{
-    const double r0 = my - t.p[0], r1 = mz - t.p[1];
-    const double s00 = t.c[0] + P.sy2, s01 = t.c[1], s11 = t.c[2] + P.sz2;
-    return (r0 * r0 * s11 - 2.0 * r0 * r1 * s01 + r1 * r1 * s00) / (s00 * s11 - s01 * s01);
-}
-
-// Kalman update with the cluster (my, mz), R = diag(sy2, sz2).  The gain rows
-// K_i = (C_i0, C_i1) S^-1 and the covariance rows C_ij -= K_i (C_j0, C_j1)^T are taken
-// from the last row to the first: row i reads columns 0 and 1 of rows j <= i only, which
-// the rows after it have not changed yet.
-static __device__ void trk_update(Trk& t, double my, double mz, const DevParams& P)
+// Kalman update with the cluster (my, mz), R = diag(sy2, sz2); returns the cluster's chi2
+// r^T S^-1 r before the update.  The gain rows K_i = (C_i0, C_i1) S^-1 and the covariance
+// rows C_ij -= K_i (C_j0, C_j1)^T are taken from the last row to the first: row i reads
+// columns 0 and 1 of rows j <= i only, which the rows after it have not changed yet.
+static __device__ double trk_update(Trk& t, double my, double mz, const DevParams& P)
 {
     const double r0 = my - t.p[0], r1 = mz - t.p[1];
     double* c = t.c;
     const double s00 = c[0] + P.sy2, s01 = c[1], s11 = c[2] + P.sz2;
-    const double idet = 1.0 / (s00 * s11 - s01 * s01);
+    const double idet = rcp_nr(s00 * s11 - s01 * s01);
     const double i00 = s11 * idet, i01 = -s01 * idet, i11 = s00 * idet;
+    const double chi2 = r0 * (r0 * i00 + r1 * i01) + r1 * (r0 * i01 + r1 * i11);
 #pragma unroll
     for (int i = 4; i >= 0; --i) {
         const int ri = i * (i + 1) / 2;
@@ -173,6 +197,7 @@ static __device__ void trk_update(Trk& t, double my, double mz, const DevParams&
             c[ri + j] -= k0 * b0 + k1 * b1;
         }
     }
+    return chi2;
 }
 
 __device__ __forceinline__ void trk_reset_cov(Trk& t, const DevParams& P)

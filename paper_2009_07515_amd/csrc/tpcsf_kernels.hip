@@ -893,7 +893,7 @@ __device__ int search_row(const Batch& B, const DevParams& P, const float4 rf, c
     best_chi2 = 0.0;
     if (v.n == 0) return -1;
     const double s00 = t.c[0] + P.sy2, s01 = t.c[1], s11 = t.c[2] + P.sz2;
-    double wy = P.nsig * sqrt(s00), wz = P.nsig * sqrt(s11);
+    double wy = P.nsig * sqrt_nr(s00), wz = P.nsig * sqrt_nr(s11);
     if (wy > (double)P.win_y) wy = (double)P.win_y;
     if (wz > (double)P.win_z) wz = (double)P.win_z;
     const double yp = t.p[0], zp = t.p[1];
@@ -901,7 +901,7 @@ __device__ int search_row(const Batch& B, const DevParams& P, const float4 rf, c
     int iy0, iy1, iz0, iz1;
     bin_span((float)yp, (float)wy, v.ylo, v.iby, v.ny, iy0, iy1);
     bin_span((float)zp, (float)wz, v.zlo, v.ibz, v.nz, iz0, iz1);
-    const double idet = 1.0 / (s00 * s11 - s01 * s01);
+    const double idet = rcp_nr(s00 * s11 - s01 * s01);
     const float2* yz = B.yz + v.first;
     int best = -1;
     int iz;
@@ -1536,9 +1536,7 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
                     continue;
                 }
             }
-            const double my = (double)e.x, mz = (double)e.y;
-            chi2 += trk_chi2(tr, my, mz, P);
-            trk_update(tr, my, mz, P);
+            chi2 += trk_update(tr, (double)e.x, (double)e.y, P);
             ++nupd;
             ++nchi;
         }

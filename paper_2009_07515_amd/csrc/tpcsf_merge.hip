@@ -680,9 +680,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_m_fit(MergeBatch M, DevParams
                         ++n_prop;
                         if (!trk_propagate(tr, (double)e.z, P)) { ok = false; break; }
                     }
-                    const double my = e.x, mz = e.y;
-                    chi2 += trk_chi2(tr, my, mz, P);
-                    trk_update(tr, my, mz, P);
+                    chi2 += trk_update(tr, (double)e.x, (double)e.y, P);
                     ++n_upd;
                 }
             }
