@@ -48,8 +48,8 @@ def stage_bytes(c):
                                                              "T", "nr"))
     return {
         "reset": 0,
-        # read y, z; write sorted (y, z), perm, inverse perm, bin table; clear W
-        "grid": 8 * N + 16 * N + 4 * B + 4 * N,
+        # read y, z; write sorted (y, z), perm, inverse perm, bin table
+        "grid": 8 * N + 16 * N + 4 * B,
         # read sorted (y, z), perm, bin tables; write up, dn
         "links": 12 * N + 4 * B + 8 * N,
         # read up, dn; write cleaned links; per-row start counts
@@ -60,9 +60,11 @@ def stage_bytes(c):
         # read starts and the chain links; write chain rows of the hit table, lengths
         "walk": 8 * S + 4 * C + 2 * C + 8 * S,
         # read start, chain coordinates (twice: fit and refit); write the hit table rows
-        # outside the chain and the tracklet record; claim: read-modify-write one 4-byte
-        # weight per cluster of the tracklets in the selection
-        "tracklets": 16 * K + 16 * Ht + 2 * nr * K + 8 * Hc,
+        # outside the chain and the tracklet record with its selection weight
+        "tracklets": 20 * K + 16 * Ht + 2 * nr * K,
+        # read every tracklet's weight and row range, the hit-table entries of the
+        # tracklets in the selection; write the weight of every cluster
+        "claim": 8 * K + 2 * Hc + 4 * N,
         # read records, tables and weights; write kept masks and the candidate list
         "keep": 12 * K + 2 * nr * K + 4 * Hc + 40 * F,
         # read candidates, masks, kept coordinates (twice); write the fit results
@@ -440,13 +442,17 @@ def serve(frames, tuning, seconds, n_slots, cap_seconds, budget_gib=64):
         ta = t_start + a
         while time.perf_counter() < ta:
             time.sleep(min(2e-4, max(0.0, ta - time.perf_counter())))
+        busy = False
         while True:
+            ts = time.perf_counter()
             t = srv.submit(*pool[int(w)])
+            te = time.perf_counter()
             if t is not None:
                 break
+            busy = True
             time.sleep(5e-5)
         with lock:
-            inflight[t] = {"w": int(w), "arrive": ta, "admit": time.perf_counter()}
+            inflight[t] = {"w": int(w), "arrive": ta, "admit": te, "busy": busy, "submit": te - ts}
     stop.set()
     th.join()
     wall = time.perf_counter() - t_start
@@ -457,7 +463,10 @@ def serve(frames, tuning, seconds, n_slots, cap_seconds, budget_gib=64):
     fin = np.array([r["done"] for r in done])
     cl = np.array([sizes[r["w"]] for r in done])
     lat, wait, svc = (fin - arr) * 1e3, (adm - arr) * 1e3, (fin - adm) * 1e3
-    stalled = int((wait > 0.1).sum())
+    sub = np.array([r["submit"] for r in done]) * 1e3
+    # a stall: the first admission attempt found no free slot or no budget (E_BUSY)
+    busy = np.array([r["busy"] for r in done])
+    stalled = int(busy.sum())
 
     def pct(v):
         return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99)), "max": float(v.max())}
@@ -468,11 +477,15 @@ def serve(frames, tuning, seconds, n_slots, cap_seconds, budget_gib=64):
            "clusters_per_s_incl_pcie": float(cl.sum()) / wall,
            "latency_ms": pct(lat), "admission_wait_ms": pct(wait), "service_ms": pct(svc),
            "admission_stalls": stalled, "admission_wait_s": float(wait.sum() * 1e-3),
+           "stalled_wait_ms": pct(wait[busy]) if stalled else None,
+           # host time of the admitting call itself (checks, upload enqueue, graph launch)
+           "submit_call_ms": pct(sub),
            "pool": {"frames": len(pool), "clusters_min": int(sizes.min()), "clusters_max": int(sizes.max()),
                     "clusters_mean": float(sizes.mean())}}
     log(f"serving: {res['frames']} frames in {wall:.1f} s, latency p50 {res['latency_ms']['p50']:.1f} ms, p99 "
-        f"{res['latency_ms']['p99']:.1f} ms, {stalled} admissions waited (p99 "
-        f"{res['admission_wait_ms']['p99']:.1f} ms), service p50 {res['service_ms']['p50']:.1f} ms")
+        f"{res['latency_ms']['p99']:.1f} ms, {stalled} arrivals stalled (admission wait p99 "
+        f"{res['admission_wait_ms']['p99']:.1f} ms, submit call p50 {res['submit_call_ms']['p50']:.2f} ms), "
+        f"service p50 {res['service_ms']['p50']:.1f} ms")
     return res
 
 

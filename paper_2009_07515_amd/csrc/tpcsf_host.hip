@@ -53,16 +53,16 @@ struct Layout {
     int64_t n = 0, R = 0, cap_starts = 0, cap_fit = 0, n_bins = 0;
     size_t row_lo, row_bin, row_nb, row_f, row_i, row_nstart, row_sbase;
     size_t bin_start, yz, perm, iperm, upk, dnk, cupk, cdnk, rank_at, W;
-    size_t st_row, st_k, st_rank, tl_len, order, tl_n, tl_rlo, tl_rhi, tl_hits;
+    size_t st_row, st_k, st_rank, tl_len, order, tl_n, tl_rlo, tl_rhi, tl_w, tl_hits;
     size_t keep_n, fit_pos, cand_off, kept_list, keep_mask, fit_list;
     size_t trk_flag, hit_cnt, trk_idx, hit_pos, trk_out;
     size_t f_par, f_cov, f_chi2, f_xref, f_pout, f_cout, scan_part;
     size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n;
 };
 
-constexpr int kStages = 13;
-const char* const kStageNames[kStages] = {"reset",     "grid", "links", "clean", "row_scan",   "starts", "walk",
-                                          "tracklets", "keep", "fit",   "track_scan", "emit", "assign"};
+constexpr int kStages = 14;
+const char* const kStageNames[kStages] = {"reset", "grid", "links", "clean",      "row_scan", "starts", "walk",
+                                          "tracklets", "claim", "keep", "fit", "track_scan", "emit", "assign"};
 
 struct GraphKey {
     const void* y = nullptr; const void* z = nullptr; const void* off = nullptr;
@@ -169,6 +169,7 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf, bool reserved = 
     L.tl_n = take(S * 4);
     L.tl_rlo = take(S * 2);
     L.tl_rhi = take(S * 2);
+    L.tl_w = take(S * 4);
     L.tl_hits = take(S * (size_t)c->n_rows * 2);
     L.keep_n = take(S * 4);
     L.fit_pos = take(S * 8);
@@ -337,6 +338,7 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.tl_n = (int32_t*)(a + L.tl_n);
     B.tl_rlo = (int16_t*)(a + L.tl_rlo);
     B.tl_rhi = (int16_t*)(a + L.tl_rhi);
+    B.tl_w = (uint32_t*)(a + L.tl_w);
     B.tl_hits = (uint16_t*)(a + L.tl_hits);
     B.keep_n = (int32_t*)(a + L.keep_n);
     B.fit_pos = (int64_t*)(a + L.fit_pos);
@@ -398,6 +400,7 @@ void enqueue_batch(const tpcsf_ctx* c, const Batch& B, hipStream_t s, hipEvent_t
     mark(); launch_walk(B, P, LC, s);
     launch_order(B, P, LC, s);
     mark(); launch_tracklets(B, P, LC, s);
+    mark(); launch_claim(B, P, 0, R, LC, s);
     mark(); launch_keep(B, P, LC, s);
     launch_fit_scan(B, P, LC, s);
     mark(); launch_fit(B, P, LC, s);
@@ -868,6 +871,7 @@ tpcsf_status tpcsf_track_plain(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks*
             launch_walk(B, P, LC, s);
             launch_order(B, P, LC, s);
             launch_tracklets(B, P, LC, s);
+            launch_claim(B, P, g0, g1, LC, s);
             launch_keep(B, P, LC, s);
             launch_fit_scan(B, P, LC, s);
             launch_fit(B, P, LC, s);

@@ -90,6 +90,7 @@ struct Batch {
     int32_t* tl_n;                  // clusters, 0 = none
     int16_t* tl_rlo;                // first row holding a cluster
     int16_t* tl_rhi;                // last row holding a cluster
+    uint32_t* tl_w;                 // selection weight, 0 = takes no part
     uint16_t* tl_hits;              // sorted position per row, kNoHit if none
     // keep and final fit: candidates listed densely
     int32_t* keep_n;                // [cap_starts] (p indexed) kept clusters, 0 = not a candidate
@@ -296,6 +297,7 @@ void launch_starts(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, c
 void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_order(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
+void launch_claim(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s);
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_fit_scan(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s);

@@ -176,8 +176,7 @@ __global__ void k_reset(Batch B)
 // sorted (y, z), perm (sorted -> in-row index), the bin table, and the inverse
 // permutation inside the row.  A row whose tables do not fit in LDS takes the same steps
 // on the global bin table, ordered chunk by chunk by one wave (a ballot match on the bin
-// key ranks equal keys inside a chunk).  The same pass clears the selection weights of
-// the row.
+// key ranks equal keys inside a chunk).
 // ------------------------------------------------------------------------------------
 constexpr int kGridThreads = 1024;
 constexpr int kGridStaticLds = 1024;    // bytes reserved for the kernel's static LDS
@@ -254,7 +253,6 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(Batch B, DevParams P, int
             bad |= !(fabsf(y) <= 1.0e5f) || !(fabsf(z) <= 1.0e5f);
             ylo = fminf(ylo, y); yhi = fmaxf(yhi, y);
             zlo = fminf(zlo, z); zhi = fmaxf(zhi, z);
-            B.W[base + i] = 0u;
         }
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
@@ -969,6 +967,7 @@ __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
         }
         B.tl_len[p] = L;
         B.tl_n[p] = 0;
+        B.tl_w[p] = 0u;
     }
 }
 
@@ -985,8 +984,8 @@ __global__ void __launch_bounds__(256) k_order(Batch B, DevParams P)
 // ------------------------------------------------------------------------------------
 // Stage 6, selection.  A tracklet's weight orders tracklets by (clusters, then smaller
 // rank); every cluster ends with the largest weight of the tracklets that contain it
-// (atomic max, order independent).  The claim is made by the lane that built the
-// tracklet, right after building it.  Weights are only ever compared within a sector, so
+// (a maximum, order independent; reduced row by row in k_claim from the weight each
+// tracklet records when it is built).  Weights are only ever compared within a sector, so
 // the rank counts from the sector's first start: w = (n << 24) | (2^24 - 1 - rank_s)
 // (n <= n_rows <= 255, checked at context creation; rank_s < 2^24 since a sector of at
 // most 255 rows of < 65535 clusters holds < 2^23 starts).  Tracklets shorter than
@@ -1006,12 +1005,12 @@ __device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P
 // more than max_miss consecutive misses or when the propagation fails.  Clusters are
 // recorded per row (sorted positions); rows [rlo, rhi] are all written.  A failed seed,
 // fit or refit leaves a tracklet of size 0.  A tracklet of >= min_track_hits clusters
-// then claims them (stage 6).
+// records the weight with which it claims them (stage 6).
 //
 // Execution is row-synchronous: a wave takes 64 consecutive tracklets of the list, which
 // is in processing order (one start row, neighbouring bins: the tracks lie close
 // together), and sweeps the rows with all of them: upward for the chain fit and the outward follow, downward
-// for the refit and the inward follow, then once more for the claim.  At every pass all
+// for the refit and the inward follow.  At every pass all
 // lanes work on the same row, so row records, hit table entries (row-major) and search
 // windows are shared between the lanes of the wave.
 // ------------------------------------------------------------------------------------
@@ -1073,7 +1072,7 @@ __device__ __forceinline__ void wave_count(int64_t* ctr, int v)
     if (lane_id() == 0 && t != 0) atomicAdd((unsigned long long*)ctr, (unsigned long long)t);
 }
 
-constexpr int kRowBatch = 8;   // rows per pass of the claim, keep and emit sweeps
+constexpr int kRowBatch = 8;   // rows per pass of the keep sweep
 
 enum : int { kWait = 0, kFit = 1, kOut = 2, kUpDone = 3, kRefit = 4, kIn = 5, kDone = 6 };
 
@@ -1226,28 +1225,69 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int gra
             B.tl_n[p] = n;
             B.tl_rlo[p] = (int16_t)rlo;
             B.tl_rhi[p] = (int16_t)rhi;
+            // the weight with which the tracklet claims its clusters (stage 6), 0 if it
+            // takes no part
+            B.tl_w[p] = n >= P.min_track_hits ? weight_of(B, P, n, B.st_rank[p], gs) : 0u;
         }
         wave_count(&B.ctr->work[0], nprop);
         wave_count(&B.ctr->work[1], nupd);
         wave_count(&B.ctr->work[2], nwin);
-        // claim, kRowBatch rows per pass: the loads of all of them are issued before
-        // their atomics
-        const bool claim = live && n >= P.min_track_hits;
-        const uint32_t w = claim ? weight_of(B, P, n, B.st_rank[p], gs) : 0u;
-        const int c1 = wave_max_i(claim ? rhi : -1);
-        for (int r = wave_min_i(claim ? rlo : nr); r <= c1; r += kRowBatch) {
-            uint16_t kk[kRowBatch];
-            int64_t ff[kRowBatch];
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Stage 6, selection, one block per row: every cluster of the row takes the largest
+// weight of the tracklets that hold it, 0 if none does.  The tracklets of a sector are
+// the starts [first start of its first row, end of the starts of its last row); the hit
+// table is row-major, so the block reads the row's entries of all of them contiguously,
+// and reduces the weights by LDS atomics on the row's clusters (sorted positions); the
+// row's weights are then written out contiguously.  A row of more than kClaimLds
+// clusters takes the same steps with global atomics.
+// ------------------------------------------------------------------------------------
+constexpr int kClaimLds = 12288;   // clusters of a row reduced in LDS (48 KB)
+constexpr int kClaimBatch = 4;     // starts per thread and pass
+
+__global__ void __launch_bounds__(512) k_claim(Batch B, DevParams P, int64_t g0, int64_t g1)
+{
+    __shared__ uint32_t wl[kClaimLds];
+    const int nr = P.n_rows;
+    for (int64_t g = g0 + xcd_block(); g < g1; g += gridDim.x) {
+        const int r = (int)(g % nr);
+        const int64_t gs = g - r;
+        const int64_t base = B.off[g];
+        const int n = (int)(B.off[g + 1] - base);
+        const int64_t p0 = B.row_sbase[gs];
+        const int64_t p1 = B.row_sbase[gs + nr - 1] + B.row_nstart[gs + nr - 1];
+        const bool in_lds = n <= kClaimLds;
+        uint32_t* wr = in_lds ? wl : B.W + base;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) wr[k] = 0u;
+        __threadfence_block();
+        __syncthreads();
+        // kClaimBatch starts per thread and pass, all their loads issued before any test
+        // (hit-table entries outside a tracklet's rows are stale and are not used)
+        const uint16_t* hr = B.tl_hits + (int64_t)r * B.cap_starts;
+        for (int64_t pb = p0 + threadIdx.x; pb < p1; pb += kClaimBatch * (int64_t)blockDim.x) {
+            uint32_t w[kClaimBatch];
+            int lo[kClaimBatch], hi[kClaimBatch];
+            uint16_t kk[kClaimBatch];
 #pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) {
-                const int rr = r + u;
-                const bool on = claim && rr >= rlo && rr <= rhi;
-                kk[u] = on ? *hit_slot(B, rr, p) : kNoHit;
-                ff[u] = on ? B.off[gs + rr] : 0;
+            for (int u = 0; u < kClaimBatch; ++u) {
+                const int64_t p = pb + (int64_t)u * blockDim.x;
+                const bool on = p < p1;
+                w[u] = on ? B.tl_w[p] : 0u;
+                lo[u] = on ? B.tl_rlo[p] : 0;
+                hi[u] = on ? B.tl_rhi[p] : -1;
+                kk[u] = on ? hr[p] : kNoHit;
             }
 #pragma unroll
-            for (int u = 0; u < kRowBatch; ++u)
-                if (kk[u] != kNoHit) atomicMax(&B.W[ff[u] + kk[u]], w);
+            for (int u = 0; u < kClaimBatch; ++u)
+                if (w[u] != 0u && r >= lo[u] && r <= hi[u] && kk[u] != kNoHit) atomicMax(&wr[kk[u]], w[u]);
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (in_lds) {
+            for (int k = threadIdx.x; k < n; k += blockDim.x) B.W[base + k] = wl[k];
+            __syncthreads();
         }
     }
 }
@@ -1392,54 +1432,67 @@ __device__ __forceinline__ bool row_set(uint64_t m0, uint64_t m1, uint64_t m2, u
     return (mask_word(m0, m1, m2, m3, r >> 6) >> (r & 63)) & 1ull;
 }
 
-// The kept clusters of every candidate, gathered into one list in slot order (inner to
-// outer), at offsets from the scan of the kept counts.  A wave takes 64 consecutive
-// candidates and sweeps their kept rows together (row-major hit table).
-__global__ void __launch_bounds__(256) k_gather(Batch B, DevParams P)
+// The kept clusters of every candidate as one list per candidate in slot order (inner to
+// outer), at offsets from the scan of the kept counts.  Work items are (256 consecutive
+// candidates, kKeptRows consecutive rows); a thread takes one candidate's kept clusters in
+// those rows, which are consecutive in its list (their place is the number of kept rows
+// below, from its mask), with all their loads issued together.  Consecutive work items
+// take neighbouring candidates in the same rows, whose clusters then stay in L2.
+constexpr int kKeptRows = 8;   // divides 64: an item's rows lie in one word of a kept mask
+
+__global__ void __launch_bounds__(256) k_kept(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
-    const int lane = lane_id();
-    int64_t first, end, stride;
-    xcd_span(0, B.ctr->n_fit, first, end, stride);
-    for (int64_t i0 = first - lane; i0 < end; i0 += stride) {
-        const int64_t i = i0 + lane;
-        const bool on = i < end;
-        int64_t p = 0, gs = 0, j = 0;
-        uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-        int rlo = nr, rhi = -1;
-        if (on) {
-            p = B.fit_list[i];
-            const int64_t g = B.st_row[p];
-            gs = g - g % nr;
-            j = B.cand_off[p];
-            m0 = B.keep_mask[p * 4 + 0]; m1 = B.keep_mask[p * 4 + 1];
-            m2 = B.keep_mask[p * 4 + 2]; m3 = B.keep_mask[p * 4 + 3];
-            rlo = B.tl_rlo[p];
-            rhi = B.tl_rhi[p];
+    const int groups = (nr + kKeptRows - 1) / kKeptRows;
+    const int64_t nfit = B.ctr->n_fit;
+    const int64_t n_chunks = (nfit + 255) / 256;
+    const int64_t n_items = n_chunks * groups;
+    for (int64_t it = xcd_block(); it < n_items; it += gridDim.x) {
+        const int r0 = (int)(it / n_chunks) * kKeptRows;
+        const int64_t i = (it % n_chunks) * 256 + threadIdx.x;
+        if (i >= nfit) continue;
+        const int r1 = min(r0 + kKeptRows, nr) - 1;
+        const int64_t p = B.fit_list[i];
+        const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
+        const int64_t g = B.st_row[p];
+        const int64_t jb = B.cand_off[p];
+        uint64_t mw[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) mw[w] = B.keep_mask[p * 4 + w];
+        if (rhi < r0 || rlo > r1) continue;
+        const int64_t gs = g - g % nr;
+        // kept rows below r0, then this item's rows
+        const int w0 = r0 >> 6;
+        int below = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) below += w < w0 ? __popcll(mw[w]) : 0;
+        const uint64_t word = w0 == 0 ? mw[0] : (w0 == 1 ? mw[1] : (w0 == 2 ? mw[2] : mw[3]));
+        below += __popcll(word & ((1ull << (r0 & 63)) - 1ull));
+        const uint32_t bits = (uint32_t)(word >> (r0 & 63)) & ((1u << kKeptRows) - 1u);
+        if (bits == 0u) continue;
+        const int64_t j = jb + below;
+        int64_t ff[kKeptRows];
+        uint32_t kk[kKeptRows];
+#pragma unroll
+        for (int u = 0; u < kKeptRows; ++u) {
+            const bool on = (bits >> u) & 1u;
+            ff[u] = on ? B.off[gs + r0 + u] : 0;
+            kk[u] = on ? *hit_slot(B, r0 + u, p) : 0u;
         }
-        const int rb = wave_max_i(rhi);
-        for (int r = wave_min_i(rlo); r <= rb; r += kRowBatch) {
-            uint32_t kk[kRowBatch];
-            int64_t ff[kRowBatch];
+        float2 cc[kKeptRows];
+        uint32_t oo[kKeptRows];
 #pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) {
-                const int rr = r + u;
-                const bool set = on && rr <= rhi && row_set(m0, m1, m2, m3, rr);
-                kk[u] = set ? *hit_slot(B, rr, p) : 0xFFFFFFFFu;
-                ff[u] = set ? B.off[gs + rr] : 0;
-            }
-            float2 cc[kRowBatch];
-            uint32_t oo[kRowBatch];
+        for (int u = 0; u < kKeptRows; ++u) {
+            const bool on = (bits >> u) & 1u;
+            cc[u] = on ? B.yz[ff[u] + kk[u]] : make_float2(0.0f, 0.0f);
+            oo[u] = on ? B.perm[ff[u] + kk[u]] : 0u;
+        }
+        int q = 0;
 #pragma unroll
-            for (int u = 0; u < kRowBatch; ++u) {
-                cc[u] = kk[u] != 0xFFFFFFFFu ? B.yz[ff[u] + kk[u]] : make_float2(0.0f, 0.0f);
-                oo[u] = kk[u] != 0xFFFFFFFFu ? B.perm[ff[u] + kk[u]] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < kRowBatch; ++u)
-                if (kk[u] != 0xFFFFFFFFu)
-                    B.kept_list[j++] = make_float4(cc[u].x, cc[u].y, P.rx[r + u],
-                                                   __int_as_float((int)(ff[u] + oo[u])));
+        for (int u = 0; u < kKeptRows; ++u) {
+            if (!((bits >> u) & 1u)) continue;
+            B.kept_list[j + q] = make_float4(cc[u].x, cc[u].y, P.rx[r0 + u], __int_as_float((int)(ff[u] + oo[u])));
+            ++q;
         }
     }
 }
@@ -1859,6 +1912,11 @@ void launch_tracklets(const Batch& b, const DevParams& p, const LaunchCfg& c, hi
     hipLaunchKernelGGL(k_tracklets, dim3(blocks), dim3(c.tl_block), 0, s, b, p, 64 * c.chunk);
 }
 
+void launch_claim(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, const LaunchCfg& c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_claim, dim3(grid_for(g1 - g0, 1, 1 << 16)), dim3(512), 0, s, b, p, g0, g1);
+}
+
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_keep, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
@@ -1882,7 +1940,7 @@ void launch_fit_scan(const Batch& b, const DevParams& p, const LaunchCfg& c, hip
 
 void launch_fit(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+    hipLaunchKernelGGL(k_kept, dim3(c.n_cu * 8), dim3(256), 0, s, b, p);
     hipLaunchKernelGGL(k_fit, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
