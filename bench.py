@@ -264,7 +264,7 @@ def config4_sweep():
     bins = [dict(bin_y=2.0, bin_z=2.0, cap_mul=2), dict(bin_y=2.0, bin_z=4.0, cap_mul=4),
             dict(bin_y=4.0, bin_z=4.0, cap_mul=2), dict(bin_y=1000.0, bin_z=1.0, cap_mul=2)]
     shapes = [dict(block=256, tl_block=256, chunk=1), dict(block=512, tl_block=256, chunk=2),
-              dict(block=512, tl_block=256, chunk=8), dict(block=256, tl_block=128, chunk=4)]
+              dict(block=1024, tl_block=256, chunk=1), dict(block=256, tl_block=128, chunk=4)]
     return [dict(b, **sh) for b in bins for sh in shapes]
 
 

@@ -170,7 +170,7 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf, bool reserved = 
     L.tl_rlo = take(S * 2);
     L.tl_rhi = take(S * 2);
     L.tl_w = take(S * 4);
-    L.tl_hits = take(S * (size_t)c->n_rows * 2);
+    L.tl_hits = take((S + 63) / 64 * 64 * (size_t)c->n_rows * 2);   // tiles of 64 starts
     L.keep_n = take(S * 4);
     L.fit_pos = take(S * 8);
     L.cand_off = take(S * 8);

@@ -84,14 +84,15 @@ struct Batch {
     int32_t* st_k;                  // [cap_starts] sorted position
     int32_t* st_rank;               // [cap_starts] rank
     int64_t cap_starts;
-    // tracklets (p indexed); hit table H[p * n_rows + r]
+    // tracklets (p indexed)
     int32_t* tl_len;                // chain length
     int32_t* order;                 // [cap_starts] p of every tracklet to build, in p order
     int32_t* tl_n;                  // clusters, 0 = none
     int16_t* tl_rlo;                // first row holding a cluster
     int16_t* tl_rhi;                // last row holding a cluster
     uint32_t* tl_w;                 // selection weight, 0 = takes no part
-    uint16_t* tl_hits;              // sorted position per row, kNoHit if none
+    uint16_t* tl_hits;              // sorted position per row, kNoHit if none; tiles of
+                                    //     64 starts x n_rows rows
     // keep and final fit: candidates listed densely
     int32_t* keep_n;                // [cap_starts] (p indexed) kept clusters, 0 = not a candidate
     int64_t* fit_pos;               // [cap_starts] (p indexed) candidate slot (scan of keep_n)

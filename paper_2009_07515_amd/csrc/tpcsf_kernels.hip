@@ -941,11 +941,12 @@ __device__ int search_row(const Batch& B, const DevParams& P, const float4 rf, c
 // the chain in the tracklet's hit table and its length; chains of >= min_chain clusters
 // become tracklets.
 // ------------------------------------------------------------------------------------
-// Hit table, row-major: entry (r, p) at r * cap_starts + p, so that neighbouring
-// tracklets' entries for one row are adjacent.
+// Hit table in tiles of 64 starts: tile p/64 holds rows 0..n_rows-1 of its 64 starts,
+// row by row, so that neighbouring tracklets' entries for one row are adjacent (one
+// 128-byte line for a wave of 64) and one tracklet's rows lie within one 19 KB tile.
 __device__ __forceinline__ uint16_t* hit_slot(const Batch& B, int r, int64_t p)
 {
-    return B.tl_hits + (int64_t)r * B.cap_starts + p;
+    return B.tl_hits + (((p >> 6) * B.n_rows + r) << 6) + (p & 63);
 }
 
 __global__ void __launch_bounds__(256) k_walk(Batch B, DevParams P)
@@ -1011,7 +1012,7 @@ __device__ __forceinline__ uint32_t weight_of(const Batch& B, const DevParams& P
 // is in processing order (one start row, neighbouring bins: the tracks lie close
 // together), and sweeps the rows with all of them: upward for the chain fit and the outward follow, downward
 // for the refit and the inward follow.  At every pass all
-// lanes work on the same row, so row records, hit table entries (row-major) and search
+// lanes work on the same row, so row records, hit table entries (adjacent per row) and search
 // windows are shared between the lanes of the wave.
 // ------------------------------------------------------------------------------------
 // Hands work items of [lo, hi) to the idle lanes of a wave, in lane order.  The range is
@@ -1074,6 +1075,33 @@ __device__ __forceinline__ void wave_count(int64_t* ctr, int v)
 
 constexpr int kRowBatch = 8;   // rows per pass of the keep sweep
 
+// What a tracklet sweep needs of a row before the state reaches it: the row's search
+// records, its first cluster and the tracklet's hit-table entry (stale outside the rows
+// the tracklet has written; used only inside them).
+struct RowAhead {
+    float4 f;
+    int4 i;
+    int64_t off;
+    int k;
+};
+
+__device__ __forceinline__ RowAhead row_ahead(const Batch& B, int64_t p, int64_t gs, int r, bool on)
+{
+    RowAhead a;
+    if (on) {
+        a.f = B.row_f[gs + r];
+        a.i = B.row_i[gs + r];
+        a.off = B.off[gs + r];
+        a.k = *hit_slot(B, r, p);
+    } else {
+        a.f = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        a.i = make_int4(0, 0, 0, 0);
+        a.off = 0;
+        a.k = kNoHit;
+    }
+    return a;
+}
+
 enum : int { kWait = 0, kFit = 1, kOut = 2, kUpDone = 3, kRefit = 4, kIn = 5, kDone = 6 };
 
 __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int grab)
@@ -1113,8 +1141,13 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int gra
             }
         }
 
-        // upward: chain fit from r0, then follow outward
-        for (int r = wave_min_i(phase == kWait ? r0 : nr); r < nr && __ballot(phase <= kOut) != 0ull; ++r) {
+        // upward: chain fit from r0, then follow outward; each row's loads that do not
+        // depend on the state are issued one row ahead
+        int ru = wave_min_i(phase == kWait ? r0 : nr);
+        RowAhead nx = row_ahead(B, p, gs, ru, live && ru < nr);
+        for (int r = ru; r < nr && __ballot(phase <= kOut) != 0ull; ++r) {
+            const RowAhead cur = nx;
+            nx = row_ahead(B, p, gs, r + 1, live && r + 1 < nr);
             if (phase == kWait && r == r0) phase = kFit;
             const bool act = phase == kFit || phase == kOut;
             bool moved = true;
@@ -1126,11 +1159,11 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int gra
             float2 c = make_float2(0.0f, 0.0f);
             if (act && moved) {
                 if (phase == kFit) {
-                    k = *hit_slot(B, r, p);
-                    c = B.yz[B.off[gs + r] + k];
+                    k = cur.k;
+                    c = B.yz[cur.off + k];
                 } else {
                     double chi2;
-                    k = search_row(B, P, B.row_f[gs + r], B.row_i[gs + r], gs + r, tr, chi2, c, nwin);
+                    k = search_row(B, P, cur.f, cur.i, gs + r, tr, chi2, c, nwin);
                     if (k >= 0 && !(chi2 <= P.chi2_max)) k = -1;
                 }
             }
@@ -1166,12 +1199,15 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int gra
         }
 
         // downward: refit over the rows with a cluster from rhi to r0, then follow inward
-        for (int r = wave_max_i(phase == kRefit ? rhi : -1); r >= 0 && __ballot(phase == kRefit || phase == kIn) != 0ull;
-             --r) {
+        int rd = wave_max_i(phase == kRefit ? rhi : -1);
+        nx = row_ahead(B, p, gs, rd, live && rd >= 0);
+        for (int r = rd; r >= 0 && __ballot(phase == kRefit || phase == kIn) != 0ull; --r) {
+            const RowAhead cur = nx;
+            nx = row_ahead(B, p, gs, r - 1, live && r >= 1);
             bool act = false;
             int k = -1;
             if (phase == kRefit && r <= rhi) {
-                k = *hit_slot(B, r, p);
+                k = cur.k;
                 act = k != kNoHit;
             } else if (phase == kIn) {
                 act = true;
@@ -1184,10 +1220,10 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int gra
             float2 c = make_float2(0.0f, 0.0f);
             if (act && moved) {
                 if (phase == kRefit) {
-                    c = B.yz[B.off[gs + r] + k];
+                    c = B.yz[cur.off + k];
                 } else {
                     double chi2;
-                    k = search_row(B, P, B.row_f[gs + r], B.row_i[gs + r], gs + r, tr, chi2, c, nwin);
+                    k = search_row(B, P, cur.f, cur.i, gs + r, tr, chi2, c, nwin);
                     if (k >= 0 && !(chi2 <= P.chi2_max)) k = -1;
                 }
                 if (k >= 0) {
@@ -1239,9 +1275,9 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int gra
 // Stage 6, selection, one block per row: every cluster of the row takes the largest
 // weight of the tracklets that hold it, 0 if none does.  The tracklets of a sector are
 // the starts [first start of its first row, end of the starts of its last row); the hit
-// table is row-major, so the block reads the row's entries of all of them contiguously,
-// and reduces the weights by LDS atomics on the row's clusters (sorted positions); the
-// row's weights are then written out contiguously.  A row of more than kClaimLds
+// table keeps a row's entries of neighbouring tracklets adjacent, so the block reads
+// them in coalesced runs, and reduces the weights by LDS atomics on the row's clusters
+// (sorted positions); the row's weights are then written out contiguously.  A row of more than kClaimLds
 // clusters takes the same steps with global atomics.
 // ------------------------------------------------------------------------------------
 constexpr int kClaimLds = 12288;   // clusters of a row reduced in LDS (48 KB)
@@ -1265,7 +1301,6 @@ __global__ void __launch_bounds__(512) k_claim(Batch B, DevParams P, int64_t g0,
         __syncthreads();
         // kClaimBatch starts per thread and pass, all their loads issued before any test
         // (hit-table entries outside a tracklet's rows are stale and are not used)
-        const uint16_t* hr = B.tl_hits + (int64_t)r * B.cap_starts;
         for (int64_t pb = p0 + threadIdx.x; pb < p1; pb += kClaimBatch * (int64_t)blockDim.x) {
             uint32_t w[kClaimBatch];
             int lo[kClaimBatch], hi[kClaimBatch];
@@ -1277,7 +1312,7 @@ __global__ void __launch_bounds__(512) k_claim(Batch B, DevParams P, int64_t g0,
                 w[u] = on ? B.tl_w[p] : 0u;
                 lo[u] = on ? B.tl_rlo[p] : 0;
                 hi[u] = on ? B.tl_rhi[p] : -1;
-                kk[u] = on ? hr[p] : kNoHit;
+                kk[u] = on ? *hit_slot(B, r, p) : kNoHit;
             }
 #pragma unroll
             for (int u = 0; u < kClaimBatch; ++u)

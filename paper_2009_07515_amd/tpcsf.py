@@ -548,7 +548,8 @@ def default_sweep():
             dict(bin_y=1000.0, bin_z=0.5, cap_mul=2), dict(bin_y=1000.0, bin_z=1.0, cap_mul=2),
             dict(bin_y=1000.0, bin_z=2.0, cap_mul=2)]
     shapes = [dict(block=256, tl_block=256, chunk=1), dict(block=128, tl_block=128, chunk=1),
-              dict(block=256, tl_block=64, chunk=1), dict(block=512, tl_block=256, chunk=2)]
+              dict(block=256, tl_block=64, chunk=1), dict(block=512, tl_block=256, chunk=2),
+              dict(block=1024, tl_block=256, chunk=1)]
     return [dict(b, **sh) for b in bins for sh in shapes]
 
 
