@@ -127,13 +127,18 @@ __device__ __forceinline__ void segment(int64_t lo, int64_t hi, int x, int parts
 }
 
 // Per-thread loop bounds over [lo, hi): this block's XCD takes its segment, and the
-// XCD's blocks stride over it.  Iterate i = first; i < end; i += stride.
+// XCD's blocks stride over it.  Iterate i = first; i < end; i += stride.  Segment
+// boundaries inside the range fall on multiples of 64, so that (with blocks of whole
+// waves) every wave but a segment's first takes 64 indices of one 64-aligned group, the
+// unit of the hit table's tiles.
 __device__ __forceinline__ void xcd_span(int64_t lo, int64_t hi, int64_t& first, int64_t& end, int64_t& stride)
 {
     const int parts = xcd_parts(), x = (int)blockIdx.x % parts, j = (int)blockIdx.x / parts;
     const int nbx = ((int)gridDim.x - x + parts - 1) / parts;
     int64_t s0, s1;
     segment(lo, hi, x, parts, s0, s1);
+    if (x > 0) s0 = max(lo, s0 & ~(int64_t)63);
+    if (x < parts - 1) s1 = max(lo, s1 & ~(int64_t)63);
     first = s0 + (int64_t)j * blockDim.x + threadIdx.x;
     end = s1;
     stride = (int64_t)nbx * blockDim.x;
@@ -1277,8 +1282,8 @@ __global__ void __launch_bounds__(256) k_tracklets(Batch B, DevParams P, int gra
 // the starts [first start of its first row, end of the starts of its last row); the hit
 // table keeps a row's entries of neighbouring tracklets adjacent, so the block reads
 // them in coalesced runs, and reduces the weights by LDS atomics on the row's clusters
-// (sorted positions); the row's weights are then written out contiguously.  A row of more than kClaimLds
-// clusters takes the same steps with global atomics.
+// (sorted positions); the row's weights are then written out contiguously.  A row of
+// more than kClaimLds clusters takes the same steps with global atomics.
 // ------------------------------------------------------------------------------------
 constexpr int kClaimLds = 12288;   // clusters of a row reduced in LDS (48 KB)
 constexpr int kClaimBatch = 4;     // starts per thread and pass
@@ -1300,15 +1305,16 @@ __global__ void __launch_bounds__(512) k_claim(Batch B, DevParams P, int64_t g0,
         __threadfence_block();
         __syncthreads();
         // kClaimBatch starts per thread and pass, all their loads issued before any test
-        // (hit-table entries outside a tracklet's rows are stale and are not used)
-        for (int64_t pb = p0 + threadIdx.x; pb < p1; pb += kClaimBatch * (int64_t)blockDim.x) {
+        // (hit-table entries outside a tracklet's rows are stale and are not used); the
+        // waves start at a tile boundary
+        for (int64_t pb = (p0 & ~(int64_t)63) + threadIdx.x; pb < p1; pb += kClaimBatch * (int64_t)blockDim.x) {
             uint32_t w[kClaimBatch];
             int lo[kClaimBatch], hi[kClaimBatch];
             uint16_t kk[kClaimBatch];
 #pragma unroll
             for (int u = 0; u < kClaimBatch; ++u) {
                 const int64_t p = pb + (int64_t)u * blockDim.x;
-                const bool on = p < p1;
+                const bool on = p >= p0 && p < p1;
                 w[u] = on ? B.tl_w[p] : 0u;
                 lo[u] = on ? B.tl_rlo[p] : 0;
                 hi[u] = on ? B.tl_rhi[p] : -1;
@@ -1356,7 +1362,7 @@ __global__ void __launch_bounds__(256) k_keep(Batch B, DevParams P)
             if (n >= P.min_track_hits) {
                 const int64_t g = B.st_row[p];
                 gs = g - g % nr;
-                w = weight_of(B, P, n, rank, gs);
+                w = B.tl_w[p];
                 rlo = B.tl_rlo[p];
                 rhi = B.tl_rhi[p];
             }
@@ -1468,67 +1474,49 @@ __device__ __forceinline__ bool row_set(uint64_t m0, uint64_t m1, uint64_t m2, u
 }
 
 // The kept clusters of every candidate as one list per candidate in slot order (inner to
-// outer), at offsets from the scan of the kept counts.  Work items are (256 consecutive
-// candidates, kKeptRows consecutive rows); a thread takes one candidate's kept clusters in
-// those rows, which are consecutive in its list (their place is the number of kept rows
-// below, from its mask), with all their loads issued together.  Consecutive work items
-// take neighbouring candidates in the same rows, whose clusters then stay in L2.
+// outer), at offsets from the scan of the kept counts.  Work items are (32 consecutive
+// candidates, kKeptRows consecutive rows): kKeptRows neighbouring lanes take one candidate,
+// a row each, and place its kept cluster of that row (if any) at its position in the list
+// (the kept rows below, from its mask).  A candidate's entries for these rows are
+// consecutive, so the lanes of one candidate write one contiguous run and a store
+// instruction covers whole runs of 64 / kKeptRows candidates.  Consecutive work items take
+// neighbouring candidates in the same rows, whose clusters then stay in L2.
 constexpr int kKeptRows = 8;   // divides 64: an item's rows lie in one word of a kept mask
+constexpr int kKeptCands = 256 / kKeptRows;
 
 __global__ void __launch_bounds__(256) k_kept(Batch B, DevParams P)
 {
     const int nr = P.n_rows;
     const int groups = (nr + kKeptRows - 1) / kKeptRows;
     const int64_t nfit = B.ctr->n_fit;
-    const int64_t n_chunks = (nfit + 255) / 256;
+    const int64_t n_chunks = (nfit + kKeptCands - 1) / kKeptCands;
     const int64_t n_items = n_chunks * groups;
+    const int u = (int)threadIdx.x % kKeptRows;
     for (int64_t it = xcd_block(); it < n_items; it += gridDim.x) {
         const int r0 = (int)(it / n_chunks) * kKeptRows;
-        const int64_t i = (it % n_chunks) * 256 + threadIdx.x;
-        if (i >= nfit) continue;
-        const int r1 = min(r0 + kKeptRows, nr) - 1;
+        const int r = r0 + u;
+        const int64_t i = (it % n_chunks) * kKeptCands + (int)threadIdx.x / kKeptRows;
+        if (i >= nfit || r >= nr) continue;
         const int64_t p = B.fit_list[i];
         const int rlo = B.tl_rlo[p], rhi = B.tl_rhi[p];
-        const int64_t g = B.st_row[p];
-        const int64_t jb = B.cand_off[p];
+        if (r < rlo || r > rhi) continue;
+        const int w0 = r0 >> 6;
         uint64_t mw[4];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) mw[w] = B.keep_mask[p * 4 + w];
-        if (rhi < r0 || rlo > r1) continue;
-        const int64_t gs = g - g % nr;
-        // kept rows below r0, then this item's rows
-        const int w0 = r0 >> 6;
-        int below = 0;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) below += w < w0 ? __popcll(mw[w]) : 0;
+        for (int w = 0; w < 4; ++w) mw[w] = w <= w0 ? B.keep_mask[p * 4 + w] : 0ull;
         const uint64_t word = w0 == 0 ? mw[0] : (w0 == 1 ? mw[1] : (w0 == 2 ? mw[2] : mw[3]));
-        below += __popcll(word & ((1ull << (r0 & 63)) - 1ull));
-        const uint32_t bits = (uint32_t)(word >> (r0 & 63)) & ((1u << kKeptRows) - 1u);
-        if (bits == 0u) continue;
-        const int64_t j = jb + below;
-        int64_t ff[kKeptRows];
-        uint32_t kk[kKeptRows];
+        if (!((word >> (r & 63)) & 1ull)) continue;
+        // kept rows below r
+        int below = __popcll(word & ((1ull << (r & 63)) - 1ull));
 #pragma unroll
-        for (int u = 0; u < kKeptRows; ++u) {
-            const bool on = (bits >> u) & 1u;
-            ff[u] = on ? B.off[gs + r0 + u] : 0;
-            kk[u] = on ? *hit_slot(B, r0 + u, p) : 0u;
-        }
-        float2 cc[kKeptRows];
-        uint32_t oo[kKeptRows];
-#pragma unroll
-        for (int u = 0; u < kKeptRows; ++u) {
-            const bool on = (bits >> u) & 1u;
-            cc[u] = on ? B.yz[ff[u] + kk[u]] : make_float2(0.0f, 0.0f);
-            oo[u] = on ? B.perm[ff[u] + kk[u]] : 0u;
-        }
-        int q = 0;
-#pragma unroll
-        for (int u = 0; u < kKeptRows; ++u) {
-            if (!((bits >> u) & 1u)) continue;
-            B.kept_list[j + q] = make_float4(cc[u].x, cc[u].y, P.rx[r0 + u], __int_as_float((int)(ff[u] + oo[u])));
-            ++q;
-        }
+        for (int w = 0; w < 3; ++w) below += w < w0 ? __popcll(mw[w]) : 0;
+        const int64_t g = B.st_row[p];
+        const int64_t f = B.off[g - g % nr + r];
+        const uint32_t k = *hit_slot(B, r, p);
+        const int64_t j = B.cand_off[p] + below;
+        const float2 c = B.yz[f + k];
+        const uint32_t o = B.perm[f + k];
+        B.kept_list[j] = make_float4(c.x, c.y, P.rx[r], __int_as_float((int)(f + o)));
     }
 }
 
