@@ -172,24 +172,31 @@ def cpu_model():
     return name, avail, os.cpu_count() or 1
 
 
-def cpu_threads(f, threads):
-    """The FP64 oracle on all 36 sectors of the frame, one sector per task on `threads`
-    host threads (the oracle's C calls release the interpreter lock)."""
+# sectors of the oracle samples, alternating between the two sides of the TPC
+SECTOR_SAMPLE = [0, 18, 9, 27, 4, 22, 13, 31, 2, 20, 11, 29, 6, 24, 15, 33, 1, 19, 10, 28]
+
+
+def cpu_threads(f, threads, n_sectors):
+    """The FP64 oracle on a sample of whole sectors of the frame (about 2 s of CPU work
+    each), one sector per task on `threads` host threads (the oracle's C calls release
+    the interpreter lock)."""
     from concurrent.futures import ThreadPoolExecutor
     import oracle
     from paper_2009_07515_amd import synth
     rx = synth.row_x()
+    secs = SECTOR_SAMPLE[:n_sectors]
 
     def one(s):
         a, b = int(f.row_off[s * 152]), int(f.row_off[(s + 1) * 152])
         ro = f.row_off[s * 152:(s + 1) * 152 + 1] - a
         return oracle.Oracle(rx, n_sectors=1).track_frame(f.y[a:b], f.z[a:b], ro)["n_tracks"]
 
+    n_cl = int(sum(f.row_off[(s + 1) * 152] - f.row_off[s * 152] for s in secs))
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        n_tracks = sum(ex.map(one, range(36)))
+        n_tracks = sum(ex.map(one, secs))
     wall = time.perf_counter() - t0
-    return dict(value=f.n_clusters / wall, seconds=wall, tracks=int(n_tracks), threads=threads)
+    return dict(value=n_cl / wall, seconds=wall, tracks=int(n_tracks), threads=threads, sectors=secs, clusters=n_cl)
 
 
 def cpu_baseline(f, budget_s, max_sectors):
@@ -200,8 +207,7 @@ def cpu_baseline(f, budget_s, max_sectors):
     R = 36 * 152
     counts = np.diff(f.row_off)
     done_cl, done_t, sectors = 0, 0.0, []
-    order = [0, 18, 9, 27, 4, 22, 13, 31, 2, 20, 11, 29]
-    for s in order[:max_sectors]:
+    for s in SECTOR_SAMPLE[:max_sectors]:
         sub = np.zeros(R, np.int64)
         sub[s * 152:(s + 1) * 152] = counts[s * 152:(s + 1) * 152]
         a, b = f.row_off[s * 152], f.row_off[(s + 1) * 152]
@@ -496,8 +502,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--tf-us", type=float, default=2000.0, help="time-frame length (us)")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
-    ap.add_argument("--cpu-sectors", type=int, default=6)
+    ap.add_argument("--cpu-budget", type=float, default=6.0, help="seconds of single-thread oracle time")
+    ap.add_argument("--cpu-sectors", type=int, default=3, help="at most this many sectors in the single-thread run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", type=str, default="", help="JSON dict of tuning overrides")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
@@ -878,12 +884,13 @@ def main():
         name, avail, total = cpu_model()
         threads = args.cpu_threads or min(16, avail)
         single = cpu_baseline(f, args.cpu_budget, args.cpu_sectors)
-        multi = cpu_threads(f, threads)
-        log(f"oracle on {threads} threads: all 36 sectors in {multi['seconds']:.1f} s, "
+        multi = cpu_threads(f, threads, threads)
+        log(f"oracle on {threads} threads: {len(multi['sectors'])} sectors in {multi['seconds']:.1f} s, "
             f"{multi['value'] / 1e6:.2f} M clusters/s")
         line["cpu_baseline"] = {"value": multi["value"], "unit": "clusters/s", "cores": threads, "kind": "oracle",
-                                "sample": f"FP64 oracle on the whole time frame ({N} clusters, 36 sectors, one "
-                                          f"sector per task on {threads} threads, {multi['seconds']:.1f} s)",
+                                "sample": f"FP64 oracle on {len(multi['sectors'])} whole sectors {multi['sectors']} of "
+                                          f"the same time frame ({multi['clusters']} clusters, one sector per task "
+                                          f"on {threads} threads, {multi['seconds']:.1f} s wall)",
                                 "cpu": name, "cores_available": avail, "cores_host": total,
                                 "single_thread": single, "next_stages": cpu_next_stages(f)}
     print(json.dumps(line), flush=True)
