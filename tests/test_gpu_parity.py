@@ -236,6 +236,33 @@ def test_edge_cases(row_x):
             assert np.array_equal(dbg[k], ref["debug"][k])
 
 
+def test_selection_in_a_row_beyond_the_on_chip_weights(small_pbpb_frame, row_x):
+    """A row of 13,000 clusters (more than the selection kernel reduces in LDS, so its
+    weights take the global-atomics path) that the tracks of the event cross: the same
+    tracks, hit lists and parameters as the oracle."""
+    from paper_2009_07515_amd import tpcsf
+    f = small_pbpb_frame
+    g = 60                                   # sector 0, row 60
+    a, b = int(f.row_off[g]), int(f.row_off[g + 1])
+    rng = np.random.Generator(np.random.PCG64(17))
+    n_add = 13000 - (b - a)
+    x = float(row_x[60])
+    ya = rng.uniform(-x * np.tan(np.pi / 18), x * np.tan(np.pi / 18), n_add).astype(np.float32)
+    za = rng.uniform(0.0, 250.0, n_add).astype(np.float32)
+    y = np.concatenate([f.y[:b], ya, f.y[b:]]).astype(np.float32)
+    z = np.concatenate([f.z[:b], za, f.z[b:]]).astype(np.float32)
+    ro = f.row_off.copy()
+    ro[g + 1:] += n_add
+    assert ro[g + 1] - ro[g] == 13000
+    trk = _tracker()
+    res = _np(trk.track(tpcsf.DeviceFrame.from_numpy(y, z, ro)))
+    ref = oracle.Oracle(row_x).track_frame(y, z, ro)
+    in_row = int(((res["hit_ids"] >= ro[g]) & (res["hit_ids"] < ro[g + 1])).sum())
+    assert res["n_tracks"] > 100 and in_row > 10
+    print(f"{res['n_tracks']} tracks, {in_row} of their clusters in the 13,000-cluster row", flush=True)
+    _check_tracks(None, res, ref, None)
+
+
 def test_capacity_and_invalid_inputs(small_pbpb_frame):
     from paper_2009_07515_amd import tpcsf
     f = small_pbpb_frame
