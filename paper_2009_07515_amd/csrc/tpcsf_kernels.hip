@@ -1909,7 +1909,7 @@ void launch_starts(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, c
 
 void launch_walk(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_walk, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+    hipLaunchKernelGGL(k_walk, dim3(c.n_cu * 16), dim3(256), 0, s, b, p);
 }
 
 void launch_order(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
@@ -1942,7 +1942,7 @@ void launch_claim(const Batch& b, const DevParams& p, int64_t g0, int64_t g1, co
 
 void launch_keep(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_keep, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
+    hipLaunchKernelGGL(k_keep, dim3(c.n_cu * 5), dim3(256), 0, s, b, p);
 }
 
 void launch_fit_scan(const Batch& b, const DevParams& p, const LaunchCfg& c, hipStream_t s)
