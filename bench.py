@@ -79,7 +79,7 @@ def stage_bytes(c):
     }
 
 
-def survey_bytes(c):
+def coarse_bytes(c):
     """The same stages under the byte model of the method's stage-boundary arrays written
     once and read once in their minimal form (8-byte (y, z), 4-byte links, indices and
     weights): K1 grid 8N read + 8N sorted + 4N perm + 4B; K2 links 8N + 4B read, 8N links;
@@ -114,7 +114,7 @@ def counts_from(trk, frame, res, nr):
 FLOPS_PROPAGATE, FLOPS_UPDATE, FLOPS_WINDOW, FLOPS_CHI2 = 182, 121, 12, 17
 # the coarser per-step model of the method's description (propagation ~120, update ~130,
 # window cluster ~20), reported beside it
-SURVEY_PROPAGATE, SURVEY_UPDATE, SURVEY_WINDOW = 120, 130, 20
+COARSE_PROPAGATE, COARSE_UPDATE, COARSE_WINDOW = 120, 130, 20
 
 
 def stage_flops(c):
@@ -709,8 +709,8 @@ def main():
     kalman = {k: {"TFLOPs": sf[k] / (stages[k] * 1e-3) / 1e12, "frac_fp64_peak": sf[k] / (stages[k] * 1e-3) / 1e12
                   / FP64_PEAK_TFS} for k in sf}
     w = cnt["work"]
-    sv = (SURVEY_PROPAGATE * w["tl_propagations"] + SURVEY_UPDATE * w["tl_updates"]
-          + SURVEY_WINDOW * w["tl_window_clusters"])
+    sv = (COARSE_PROPAGATE * w["tl_propagations"] + COARSE_UPDATE * w["tl_updates"]
+          + COARSE_WINDOW * w["tl_window_clusters"])
     kalman["tracklets"]["coarse_model"] = {"flops_per_launch": sv,
                                            "frac_fp64_peak": sv / (stages["tracklets"] * 1e-3) / 1e12 / FP64_PEAK_TFS}
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
@@ -864,9 +864,9 @@ def main():
         "path_hbm": {"bytes_per_cluster": path_bytes / N,
                      "achieved_GBs": path_bytes / (ms * 1e-3) / 1e9,
                      "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "coarse_model": {"bytes_per_cluster": sum(survey_bytes(cnt).values()) / N,
-                                      "achieved_GBs": sum(survey_bytes(cnt).values()) / (ms * 1e-3) / 1e9,
-                                      "frac": sum(survey_bytes(cnt).values()) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "coarse_model": {"bytes_per_cluster": sum(coarse_bytes(cnt).values()) / N,
+                                      "achieved_GBs": sum(coarse_bytes(cnt).values()) / (ms * 1e-3) / 1e9,
+                                      "frac": sum(coarse_bytes(cnt).values()) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
                      "io_floor_bytes_per_cluster": 16},
         "config4": config4,
     }
