@@ -80,6 +80,7 @@ struct tpcsf_ctx {
     int device = 0;
     int n_cu = 256;
     int grid_lds_max = 0;           // dynamic LDS bytes the grid kernel may use on the device
+    int grid_lds_used = 0;          // dynamic LDS bytes it takes: the largest need seen so far
     int64_t frame_max_row = 0;      // largest row of the frame being tracked
     int32_t n_sectors = 36, n_rows = 152;
     std::vector<float> row_x;
@@ -224,13 +225,7 @@ LaunchCfg launch_cfg(const tpcsf_ctx* c)
     L.tl_block = c->tuning.tl_block;
     L.chunk = c->tuning.chunk;
     L.n_cu = c->n_cu;
-    // the grid kernel's LDS: bin counters (16-bit pairs) and the placement of the largest
-    // row.  Frames whose rows fit in 64 KB (two row blocks per compute unit) all use 64 KB,
-    // so that frames of different sizes keep one launch configuration (and one graph).
-    const int64_t m = c->frame_max_row;
-    const int64_t need = 4 * ((c->tuning.cap_mul * m + c->tuning.cap_add + 2) / 2 + 1) + 2 * m + 256;
-    const int64_t small = 65536 - 1024;   // the kernel's static LDS stays within the 64 KB
-    L.grid_lds = (int)(need <= small && small <= c->grid_lds_max ? small : c->grid_lds_max);
+    L.grid_lds = c->grid_lds_used;
     return L;
 }
 
@@ -276,6 +271,16 @@ tpcsf_status check_frame(tpcsf_ctx* c, const tpcsf_frame* f, const tpcsf_tracks*
         if (d > max_row) max_row = d;
     }
     c->frame_max_row = max_row;
+    // the grid kernel's LDS: bin counters (16-bit pairs) at the bin cap and the placement
+    // of the largest row, rounded up to 4 KB; the less a block takes, the more row blocks
+    // share a compute unit.  It only grows within a context (any size that holds the
+    // largest row gives the same result), so that frames of different sizes keep one
+    // launch configuration and one graph.  Rows beyond the device's limit take the
+    // global-memory path.
+    const int64_t need = 4 * ((c->tuning.cap_mul * max_row + c->tuning.cap_add + 2) / 2 + 1) + 2 * max_row + 256;
+    int64_t fit = (need + 4095) / 4096 * 4096;
+    if (fit > c->grid_lds_max) fit = c->grid_lds_max;
+    if (fit > c->grid_lds_used) c->grid_lds_used = (int)fit;
     if (o->cap_tracks < 0 || o->cap_hits < 0 || !o->n_tracks || !o->n_hits || !o->hit_off)
         return fail(c, TPCSF_E_INVALID, "output descriptor incomplete");
     if (o->cap_tracks > 0 && (!o->params || !o->cov || !o->x_ref || !o->chi2 || !o->ndf || !o->nhits ||
@@ -837,6 +842,7 @@ tpcsf_status tpcsf_set_tuning(tpcsf_ctx* c, const tpcsf_tuning* t)
     if (!c) return TPCSF_E_INVALID;
     if (!tuning_ok(t)) return fail(c, TPCSF_E_INVALID, "tuning out of range");
     c->tuning = *t;
+    c->grid_lds_used = 0;   // the grid's LDS need depends on the bin cap
     return TPCSF_OK;
 }
 
@@ -1042,6 +1048,7 @@ tpcsf_status tpcsf_autotune(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks* o,
     tpcsf_status st = TPCSF_OK;
     for (int i = 0; i < n_points && st == TPCSF_OK; ++i) {
         c->tuning = points[i];
+        c->grid_lds_used = 0;   // the grid's LDS need depends on the bin cap
         if ((st = tpcsf_track_batch(c, f, o, stream)) != TPCSF_OK) break;
         launch_hash(c->last, f->n_clusters, launch_cfg(c), s);
         if ((st = tpcsf_sync(c, stream)) != TPCSF_OK) break;
@@ -1072,9 +1079,11 @@ tpcsf_status tpcsf_autotune(tpcsf_ctx* c, const tpcsf_frame* f, tpcsf_tracks* o,
     c->timing = timing;
     if (st != TPCSF_OK || best_i < 0) {
         c->tuning = saved;
+        c->grid_lds_used = 0;   // the grid's LDS need depends on the bin cap
         return st != TPCSF_OK ? st : TPCSF_E_INVALID;
     }
     c->tuning = points[best_i];
+    c->grid_lds_used = 0;   // the grid's LDS need depends on the bin cap
     if (best) *best = best_i;
     return TPCSF_OK;
 }

@@ -183,7 +183,7 @@ __global__ void k_reset(Batch B)
 // on the global bin table, ordered chunk by chunk by one wave (a ballot match on the bin
 // key ranks equal keys inside a chunk).
 // ------------------------------------------------------------------------------------
-constexpr int kGridThreads = 1024;
+constexpr int kGridThreads = 512;
 constexpr int kGridStaticLds = 1024;    // bytes reserved for the kernel's static LDS
 constexpr int kGridMaxLdsBin = 64;      // largest bin ordered by the in-LDS insertion sort
 
