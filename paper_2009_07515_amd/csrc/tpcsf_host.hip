@@ -54,7 +54,7 @@ struct Layout {
     size_t row_lo, row_bin, row_nb, row_f, row_i, row_nstart, row_sbase;
     size_t bin_start, yz, perm, iperm, upk, dnk, cupk, cdnk, rank_at, W;
     size_t st_row, st_k, st_rank, tl_len, order, tl_n, tl_rlo, tl_rhi, tl_w, tl_hits;
-    size_t keep_n, fit_pos, cand_off, kept_list, keep_mask, fit_list;
+    size_t keep_n, fit_pos, fit_pos_long, cand_off, kept_list, keep_mask, fit_list;
     size_t trk_flag, hit_cnt, trk_idx, hit_pos, trk_out;
     size_t f_par, f_cov, f_chi2, f_xref, f_pout, f_cout, scan_part;
     size_t d_up, d_dn, d_cup, d_cdn, d_start_row, d_start_idx, d_tl_n;
@@ -174,6 +174,7 @@ Layout make_layout(const tpcsf_ctx* c, int64_t n, int32_t n_tf, bool reserved = 
     L.tl_hits = take((S + 63) / 64 * 64 * (size_t)c->n_rows * 2);   // tiles of 64 starts
     L.keep_n = take(S * 4);
     L.fit_pos = take(S * 8);
+    L.fit_pos_long = take(S * 8);
     L.cand_off = take(S * 8);
     L.kept_list = take(N * 16);
     L.keep_mask = take(S * 4 * 8);
@@ -347,6 +348,7 @@ Batch make_batch(tpcsf_ctx* c, const Layout& L, const tpcsf_frame* f, const tpcs
     B.tl_hits = (uint16_t*)(a + L.tl_hits);
     B.keep_n = (int32_t*)(a + L.keep_n);
     B.fit_pos = (int64_t*)(a + L.fit_pos);
+    B.fit_pos_long = (int64_t*)(a + L.fit_pos_long);
     B.cand_off = (int64_t*)(a + L.cand_off);
     B.kept_list = (float4*)(a + L.kept_list);
     B.keep_mask = (uint64_t*)(a + L.keep_mask);

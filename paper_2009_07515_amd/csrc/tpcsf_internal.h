@@ -39,6 +39,7 @@ struct Counters {
     int64_t hit_base;               // hits emitted so far
     int64_t n_order;                // tracklets to build (chains of >= min_chain)
     int64_t n_fit;                  // track candidates (>= min_track_hits kept)
+    int64_t n_fit_long;             // candidates of >= kFitLong kept clusters
     int32_t queue[8];               // tracklet work queue: head of each XCD's segment
     int32_t fit_queue[8];           // fit work queue: head of each XCD's segment
     int32_t err;                    // error bits
@@ -96,6 +97,7 @@ struct Batch {
     // keep and final fit: candidates listed densely
     int32_t* keep_n;                // [cap_starts] (p indexed) kept clusters, 0 = not a candidate
     int64_t* fit_pos;               // [cap_starts] (p indexed) candidate slot (scan of keep_n)
+    int64_t* fit_pos_long;          // [cap_starts] (p indexed) scan of the long candidates
     int64_t* cand_off;              // [cap_starts] (p indexed) first entry of the kept list
     float4* kept_list;              // [N] kept clusters of the candidates, slot order, inner to
                                     //     outer: y, z, row plane x, input index (as bits)

@@ -157,6 +157,7 @@ __global__ void k_reset(Batch B)
         c->track_base = 0;
         c->hit_base = 0;
         c->n_fit = 0;
+        c->n_fit_long = 0;
         c->n_order = 0;
         for (int w = 0; w < 6; ++w) c->work[w] = 0;
         for (int x = 0; x < kXcds; ++x) {
@@ -1459,13 +1460,24 @@ __device__ __forceinline__ int nth_set_bit(uint64_t x, int k)
     return pos;
 }
 
-// Candidates listed by slot (processing order), from the scan of the kept counts.
+// Candidates listed by slot: those of at least kFitLong kept clusters first, then the
+// others, each part in processing order (from two scans of the kept counts).  The fit's
+// lanes outnumber the candidates less than twice, so the lanes that take a second
+// candidate then take a short one.  A slot only says which lane fits the candidate; the
+// tracks are emitted in rank order whatever the slot.
+constexpr int kFitLong = 64;
+
 __global__ void __launch_bounds__(256) k_fit_list(Batch B, DevParams P)
 {
     int64_t first, end, stride;
     xcd_span(B.ctr->rank_lo, B.ctr->rank_hi, first, end, stride);
-    for (int64_t p = first; p < end; p += stride)
-        if (B.keep_n[p] > 0) B.fit_list[B.fit_pos[p]] = (int32_t)p;
+    const int64_t n_long = B.ctr->n_fit_long;
+    for (int64_t p = first; p < end; p += stride) {
+        const int kept = B.keep_n[p];
+        if (kept <= 0) continue;
+        const int64_t slot = kept >= kFitLong ? B.fit_pos_long[p] : n_long + B.fit_pos[p] - B.fit_pos_long[p];
+        B.fit_list[slot] = (int32_t)p;
+    }
 }
 
 __device__ __forceinline__ bool row_set(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3, int r)
@@ -1540,8 +1552,8 @@ __device__ void bitonic_desc_256(uint32_t* key)
     }
 }
 
-// Each block takes 256 consecutive candidates and orders them by kept count, so that the
-// lanes of a wave run passes of similar length over their own contiguous kept lists.
+// Each block takes 256 consecutive candidate slots and orders them by kept count, so that
+// the lanes of a wave run passes of similar length over their own contiguous kept lists.
 __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
 {
     __shared__ uint32_t key[256];
@@ -1549,9 +1561,10 @@ __global__ void __launch_bounds__(256) k_fit(Batch B, DevParams P)
     const int64_t nfit = B.ctr->n_fit;
     const int parts = xcd_parts(), x = (int)blockIdx.x % parts, bj = (int)blockIdx.x / parts;
     const int nbx = ((int)gridDim.x - x + parts - 1) / parts;
-    int64_t s0, s1;
-    segment(0, (nfit + 255) / 256, x, parts, s0, s1);   // chunks of 256 candidates
-    for (int64_t ch = s0 + bj; ch < s1; ch += nbx) {
+    // chunks of 256 candidates dealt round-robin to the XCDs, each XCD's blocks taking its
+    // chunks in slot order: the long candidates first everywhere
+    const int64_t n_ch = (nfit + 255) / 256;
+    for (int64_t ch = x + (int64_t)parts * bj; ch < n_ch; ch += (int64_t)parts * nbx) {
         const int64_t i_own = ch * 256 + t;
         const int kept_own = i_own < nfit ? B.keep_n[B.fit_list[i_own]] : 0;
         key[t] = ((uint32_t)kept_own << 8) | (uint32_t)t;
@@ -1958,6 +1971,15 @@ void launch_fit_scan(const Batch& b, const DevParams& p, const LaunchCfg& c, hip
     J.outB = b.cand_off;
     J.part = b.scan_part;
     run_scan(J, s);
+    ScanJob L = {};            // the long candidates
+    L.a32 = b.keep_n;
+    L.a_min = kFitLong;
+    L.outA = b.fit_pos_long;
+    L.lo_ptr = &b.ctr->rank_lo;
+    L.hi_ptr = &b.ctr->rank_hi;
+    L.totA = &b.ctr->n_fit_long;
+    L.part = b.scan_part;
+    run_scan(L, s);
     hipLaunchKernelGGL(k_fit_list, dim3(c.n_cu * 4), dim3(256), 0, s, b, p);
 }
 
